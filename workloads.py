@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs for vectorized uncertainty propagation (VUP) runs.
+
+This module only *describes* problems: a grid (domain and cell counts), a model
+by name, a bin count, and the parameters (means, standard deviations, mixture
+weights) of the K input distributions. It contains none of the method's
+arithmetic: no densities, windows, bins or moments are computed here. Both the
+HIP path and the CPU oracle receive exactly these arrays.
+
+Workloads (all analytic and synthetic; the paper's Sec. 4.1 and Sec. 5.3 runs
+also use analytic models on uniform grids, so no dataset is involved):
+
+* ``grid64``   2-D 64x64 on [-3,3]^2, f = sin x + 0.5 cos 2y + xy/4, B = 64,
+               K = 256 isotropic Gaussians, means on the 16x16 midpoint
+               subgrid, sigma = 0.25.
+* ``grid1024`` 2-D 1024x1024 on [-3,3]^2, same f, B = 256, K = 65536 means on
+               the 256x256 midpoint subgrid, sigma_k ~ U[0.05, 0.5]
+               (isotropic, seed 11246002).
+* ``grid128_3d`` 3-D 128^3 on [-2,2]^3, f = exp(-0.1 z) sin x cos y + 0.1 xyz,
+               B = 512, K = 32768 diagonal Gaussians, mu ~ U[-1.5,1.5]^3,
+               per-axis sigma ~ U[0.05, 0.3] (seed 11246003).
+* ``grid48_4d`` 4-D 48^4 on [-2,2]^4, f = sum_j sin(x_j) x_{j+1 mod 4}
+               + 0.05 (sum_j x_j)^2, B = 1024, K = 16384 two-component
+               mixtures, weights Dirichlet(1,1), mu ~ U[-1.5,1.5]^4,
+               isotropic sigma per component ~ U[0.05, 0.25] (seed 11246005).
+
+Means "on an M x M subgrid" are the subgrid cell midpoints
+lo + (m + 1/2)(hi - lo)/M on each axis, with k = m0 * M + m1.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+SEED_GRID1024 = 11246002
+SEED_GRID128_3D = 11246003
+SEED_FD_SUBSET = 11246004
+SEED_GRID48_4D = 11246005
+
+# model names understood by both the library binding and the oracle wrapper
+MODELS = ("linear", "sincos2", "damped3", "ring4", "timing2", "ipsa2")
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    ndim: int
+    n: tuple            # cells per axis, axis 0 slowest in memory
+    lo: tuple           # domain lower edge per axis
+    hi: tuple           # domain upper edge per axis
+    model: str          # one of MODELS
+    theta: tuple        # model parameters (only "linear" uses them)
+    B: int              # number of output bins
+    mu: np.ndarray      # [K][C][d] float64
+    sigma: np.ndarray   # [K][C][d] float64
+    weight: Optional[np.ndarray]  # [K][C] float64, None when C == 1
+    n_sigma: float = 4.0
+
+    @property
+    def K(self) -> int:
+        return int(self.mu.shape[0])
+
+    @property
+    def C(self) -> int:
+        return int(self.mu.shape[1])
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    def subset(self, ks) -> "Workload":
+        """Same grid/model/bins, only the distributions with indices ``ks``."""
+        ks = np.asarray(ks, dtype=np.int64)
+        return dataclasses.replace(
+            self, name=f"{self.name}[subset {len(ks)}]",
+            mu=np.ascontiguousarray(self.mu[ks]),
+            sigma=np.ascontiguousarray(self.sigma[ks]),
+            weight=None if self.weight is None else np.ascontiguousarray(self.weight[ks]))
+
+
+def subgrid_midpoints(lo: float, hi: float, M: int) -> np.ndarray:
+    """Midpoints of an M-cell subdivision of [lo, hi]."""
+    return lo + (np.arange(M, dtype=np.float64) + 0.5) * ((hi - lo) / M)
+
+
+def _subgrid_means_2d(lo, hi, M):
+    m = subgrid_midpoints(lo, hi, M)
+    mu = np.empty((M * M, 1, 2), dtype=np.float64)
+    mu[:, 0, 0] = np.repeat(m, M)
+    mu[:, 0, 1] = np.tile(m, M)
+    return mu
+
+
+def grid64() -> Workload:
+    mu = _subgrid_means_2d(-3.0, 3.0, 16)
+    sigma = np.full_like(mu, 0.25)
+    return Workload("grid64", 2, (64, 64), (-3.0, -3.0), (3.0, 3.0), "sincos2", (),
+                    64, mu, sigma, None)
+
+
+def grid1024(seed: int = SEED_GRID1024) -> Workload:
+    mu = _subgrid_means_2d(-3.0, 3.0, 256)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = rng.uniform(0.05, 0.5, size=mu.shape[0])
+    sigma = np.repeat(s[:, None, None], 2, axis=2)
+    return Workload("grid1024", 2, (1024, 1024), (-3.0, -3.0), (3.0, 3.0), "sincos2", (),
+                    256, mu, np.ascontiguousarray(sigma), None)
+
+
+def grid128_3d(seed: int = SEED_GRID128_3D) -> Workload:
+    K = 32768
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = rng.uniform(-1.5, 1.5, size=(K, 1, 3))
+    sigma = rng.uniform(0.05, 0.3, size=(K, 1, 3))
+    return Workload("grid128_3d", 3, (128, 128, 128), (-2.0,) * 3, (2.0,) * 3, "damped3", (),
+                    512, mu, sigma, None)
+
+
+def grid48_4d(seed: int = SEED_GRID48_4D) -> Workload:
+    K = 16384
+    rng = np.random.Generator(np.random.PCG64(seed))
+    weight = rng.dirichlet([1.0, 1.0], size=K)
+    mu = rng.uniform(-1.5, 1.5, size=(K, 2, 4))
+    s = rng.uniform(0.05, 0.25, size=(K, 2))
+    sigma = np.repeat(s[:, :, None], 4, axis=2)
+    return Workload("grid48_4d", 4, (48,) * 4, (-2.0,) * 4, (2.0,) * 4, "ring4", (),
+                    1024, mu, np.ascontiguousarray(sigma), np.ascontiguousarray(weight))
+
+
+def fd_subset(K: int, count: int = 64, seed: int = SEED_FD_SUBSET) -> np.ndarray:
+    """Seeded subset of distribution indices used for finite-difference checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(K, size=min(count, K), replace=False))
+
+
+def sample_indices(K: int, count: int, seed: int) -> np.ndarray:
+    """Seeded sorted sample of distribution indices (parity sampling, CPU baseline)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(K, size=min(count, K), replace=False))
+
+
+def random_workload(name: str, n, lo, hi, model: str, B: int, K: int, C: int,
+                    sigma_range, seed: int, theta=(), mu_margin: float = 0.0,
+                    isotropic: bool = False) -> Workload:
+    """Generic seeded workload: means uniform in the domain shrunk by ``mu_margin``
+    per side, sigma uniform in ``sigma_range``; mixture weights Dirichlet(1,..,1)."""
+    d = len(n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo_a = np.asarray(lo, dtype=np.float64)
+    hi_a = np.asarray(hi, dtype=np.float64)
+    mu = rng.uniform(lo_a + mu_margin, hi_a - mu_margin, size=(K, C, d))
+    if isotropic:
+        s = rng.uniform(sigma_range[0], sigma_range[1], size=(K, C))
+        sigma = np.repeat(s[:, :, None], d, axis=2)
+    else:
+        sigma = rng.uniform(sigma_range[0], sigma_range[1], size=(K, C, d))
+    weight = rng.dirichlet(np.ones(C), size=K) if C > 1 else None
+    return Workload(name, d, tuple(int(x) for x in n), tuple(float(x) for x in lo),
+                    tuple(float(x) for x in hi), model, tuple(theta), B,
+                    np.ascontiguousarray(mu), np.ascontiguousarray(sigma),
+                    None if weight is None else np.ascontiguousarray(weight))
+
+
+CONFIGS = {
+    "grid64": grid64,
+    "grid1024": grid1024,
+    "grid128_3d": grid128_3d,
+    "grid48_4d": grid48_4d,
+}
