@@ -1,0 +1,267 @@
+/*
+ * vup.h - C ABI of the MI355X (gfx950) library for Vectorized Uncertainty
+ * Propagation (VUP) and Input Probability Sensitivity Analysis (IPSA),
+ * arXiv:1908.11246.
+ *
+ * The problem (Sec. 3, eq. (4), eq. (5), eq. VUP): a model y = M(x) is
+ * evaluated ONCE on a uniform cell-centred grid; every cell gets the index of
+ * the output bin its value falls in (the sparse one-hot "model matrix"); then
+ * K input probability distributions are propagated together,
+ *     P[k][b] = sum_i [bin(i) = b] p_k(x_i),
+ * where p_k is a Gaussian (Sec. 5.2, eq. gaussh) or a mixture of Gaussians,
+ * evaluated at cell centres, truncated per axis at n_sigma standard deviations
+ * and renormalised over the kept cells. From P the library derives the
+ * coarse-grained IPSA quantities (Sec. 5.2): per-location output variance and
+ * entropy, and their gradients with respect to the pdf parameters.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: ndim in [1,4] axes, n[d] cells on [lo[d], hi[d]]; cell centre
+ *    x_{d,j} = lo_d + (j + 1/2) (hi_d - lo_d)/n_d (composite midpoint rule,
+ *    Sec. 3); flat cell index row major, axis 0 slowest.
+ *  - Memory: the caller owns all memory. Pointers marked "dev" are device
+ *    (HBM) pointers of the current HIP device; "host" pointers are ordinary
+ *    host memory. No call allocates device memory; the only buffer the
+ *    library needs is the workspace the caller passes to vup_bin.
+ *  - Streams: every kernel is enqueued on `stream` (a hipStream_t; NULL = the
+ *    default stream). No call synchronises except vup_counters.
+ *  - Errors: every call returns VUP_OK (0) or a negative status. Arguments
+ *    that can be checked on the host are checked before anything is enqueued;
+ *    on failure nothing is enqueued and vup_last_error() (thread-local)
+ *    explains why. Problems only visible on the device never fail a call:
+ *    they give defined outputs (NaN or zero columns, bin -1) and raise the
+ *    counters read by vup_counters.
+ *  - Determinism: no cross-workgroup floating-point atomics; repeated calls
+ *    with the same inputs give bit-identical outputs.
+ */
+#ifndef VUP_H
+#define VUP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VUP_OK 0
+#define VUP_EINVAL (-1)       /* invalid argument (see vup_last_error)          */
+#define VUP_ENODEV (-2)       /* no usable HIP device                            */
+#define VUP_EDEVICE (-3)      /* a HIP runtime call failed                       */
+#define VUP_EUNSUPPORTED (-4) /* valid but unsupported combination / size       */
+#define VUP_EWORKSPACE (-5)   /* workspace too small or not built by vup_bin    */
+
+/* density precision of vup_propagate (Sec. 3 leaves it open; all variants
+ * accumulate in FP32 and normalise with an FP64 sum of the same values) */
+#define VUP_FP32 0      /* density in FP32                                          */
+#define VUP_BF16 1      /* density rounded to bfloat16 (nearest even)               */
+#define VUP_BF16X2 2    /* hi + lo bfloat16 pair: hi = bf16(w), lo = bf16(w - hi)    */
+#define VUP_FP8E4M3 3   /* OCP FP8 E4M3 of 448*w (nearest even); the scale cancels  */
+
+/* built-in models for vup_eval_grid (Sec. 2, eq. modelfunction: any model can
+ * instead be evaluated by the caller into f[N] and passed to vup_bin) */
+#define VUP_MODEL_LINEAR 0   /* theta[0] + sum_d theta[d+1] x_d              any ndim */
+#define VUP_MODEL_SINCOS2 1  /* sin x0 + 0.5 cos(2 x1) + x0 x1 / 4            ndim 2  */
+#define VUP_MODEL_DAMPED3 2  /* exp(-0.1 x2) sin x0 cos x1 + 0.1 x0 x1 x2      ndim 3  */
+#define VUP_MODEL_RING4 3    /* sum_j sin(x_j) x_{j+1 mod 4} + 0.05 (sum x)^2  ndim 4  */
+#define VUP_MODEL_TIMING2 4  /* 1.1 sin x + 7 sin^2 alpha (Sec. 4.1)           ndim 2  */
+#define VUP_MODEL_IPSA2 5    /* x^2 + 5 sin 3x + alpha (Sec. 5.3)              ndim 2  */
+
+/* limits */
+#define VUP_MAX_DIM 4
+#define VUP_MAX_BINS 4096     /* B; the per-workgroup histograms live in LDS     */
+#define VUP_MAX_COMP 2        /* mixture components per distribution            */
+#define VUP_MAX_AXIS 65536    /* n[d]                                            */
+
+typedef struct vup_grid {
+  int32_t ndim;      /* 1..4                                                   */
+  int32_t n[4];      /* cells per axis, n[d] >= 1; entries >= ndim ignored     */
+  double lo[4];      /* domain lower edge per axis (finite)                    */
+  double hi[4];      /* domain upper edge per axis (finite, > lo)              */
+} vup_grid;
+
+typedef struct vup_model {
+  int32_t kind;      /* VUP_MODEL_*                                            */
+  int32_t reserved;
+  double theta[8];   /* model parameters (VUP_MODEL_LINEAR only)               */
+} vup_model;
+
+/* K input distributions, each a mixture of ncomp diagonal Gaussians
+ * (eq. gaussh per axis). Arrays are dev, FP64, row major:
+ *   mu[K][ncomp][ndim], sigma[K][ncomp][ndim], weight[K][ncomp].
+ * Each component is truncated to the box |x_d - mu_d| <= n_sigma sigma_d
+ * intersected with the grid and normalised separately; the column is
+ * sum_c weight_c * component_c (weights are used as given). */
+typedef struct vup_dists {
+  int64_t K;             /* number of distributions, >= 0                      */
+  int32_t ncomp;         /* 1 or 2                                              */
+  int32_t ndim;          /* must equal the grid's ndim                          */
+  double n_sigma;        /* truncation half-width in standard deviations, > 0   */
+  const double* mu;      /* dev [K][ncomp][ndim]                                */
+  const double* sigma;   /* dev [K][ncomp][ndim]; <= 0 or non-finite -> NaN column */
+  const double* weight;  /* dev [K][ncomp]; NULL iff ncomp == 1                 */
+} vup_dists;
+
+/* Host-side descriptor of a model matrix built by vup_bin. Plain data: copy
+ * it freely. The arrays it refers to live inside the caller's workspace. */
+typedef struct vup_mm {
+  vup_grid grid;
+  int32_t B;            /* number of bins                                       */
+  int32_t pitch;        /* padded length of the fastest axis in the bin map     */
+  int64_t N;            /* cells                                                */
+  int64_t rows;         /* N / n[ndim-1]                                        */
+  void* ws;             /* dev workspace base                                   */
+  size_t ws_bytes;
+  /* byte offsets inside ws */
+  size_t off_edges;     /* double[B+1]      bin edges                           */
+  size_t off_binmap;    /* uint16[rows*pitch] 4*bin (4*B for no bin), padded    */
+  size_t off_f32;       /* float[rows*pitch] model values in FP32, padded       */
+  size_t off_counts;    /* int64[B+1]       cells per bin; [B] = outside        */
+  size_t off_offsets;   /* int64[B+1]       CSR row starts of the model matrix  */
+  size_t off_perm;      /* int32[N]         cells sorted by bin (stable)        */
+  size_t off_scratch;   /* int32 scratch for the sort                           */
+  size_t off_counters;  /* int64[8]         device-side event counters          */
+  uint64_t magic;
+} vup_mm;
+
+/* --------------------------------------------------------------------------
+ * vup_eval_grid - Alg. VUP steps "generate a uniform grid" and "evaluate the
+ * model" (Sec. 2 eq. modelfunction; Appendix A, Alg. VUP). Writes f[i] =
+ * M(x_i) in FP64 for every cell, row major. f: dev [N].
+ * EINVAL: bad grid, unknown model, model/ndim mismatch.
+ * ------------------------------------------------------------------------ */
+int vup_eval_grid(const vup_grid* g, const vup_model* m, double* f, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_uniform_edges - B uniform bins over [min f, max f] (the output
+ * partition of eq. (4), whose bin widths "uniformly partition" the output).
+ * edges[b] = lo + b*((hi - lo)/B) for b < B, edges[B] = hi, with lo/hi the
+ * min/max of the non-NaN f. f: dev [N]; edges: dev [B+1].
+ * A constant f gives non-increasing edges, which vup_bin then flags.
+ * EINVAL: N < 1, B outside [1, VUP_MAX_BINS], NULL pointers.
+ * ------------------------------------------------------------------------ */
+int vup_uniform_edges(const double* f, int64_t N, int32_t B, double* edges, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_bin_workspace_bytes - bytes of device workspace vup_bin needs.
+ * Returns 0 for an invalid grid or B.
+ * ------------------------------------------------------------------------ */
+size_t vup_bin_workspace_bytes(const vup_grid* g, int32_t B);
+
+/* --------------------------------------------------------------------------
+ * vup_bin - builds the model matrix (eq. (5), eq. MUP; Alg. VUP
+ * "UniqueSorted ... set indexed model matrix elements to 1"): the indicator
+ * Theta of eq. (4) as bin(i) = largest b < B with edges[b] <= f[i], valid when
+ * edges[0] <= f[i] <= edges[B] (the last bin is closed); -1 for values
+ * outside or NaN. Also stores, inside ws: the edges, a padded FP32 copy of f,
+ * the bin map used by the propagation kernels, per-bin cell counts and the
+ * compressed-by-bin form (cells of each bin in increasing order).
+ *   f: dev [N] FP64;  edges: dev [B+1] FP64, finite and strictly increasing
+ *   (checked on the device: if violated every bin is -1 and the `bad_edges`
+ *   counter is raised);  bin: dev [N] int32 (may be NULL);  ws: dev,
+ *   ws_bytes >= vup_bin_workspace_bytes(g, B), 256-byte aligned.
+ * mm_out (host) receives the descriptor used by the calls below. The
+ * workspace must stay allocated and unmodified while mm_out is in use.
+ * EINVAL / EWORKSPACE before any launch.
+ * ------------------------------------------------------------------------ */
+int vup_bin(const vup_grid* g, const double* f, const double* edges, int32_t B, int32_t* bin,
+            void* ws, size_t ws_bytes, vup_mm* mm_out, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_windows - truncation windows of every (distribution, component), the
+ * kept cells of eq. gaussh after truncation (Sec. 5.3): per axis
+ *   t_lo = ((mu - ns*sigma) - lo)/h - 1/2, j_lo = max(0, ceil(t_lo)),
+ *   t_hi = ((mu + ns*sigma) - lo)/h - 1/2, j_hi = min(n-1, floor(t_hi)),
+ * h = (hi - lo)/n, all in FP64 without contraction; if j_lo > j_hi and mu is
+ * inside [lo, hi] the window is the cell holding mu, else empty (0, -1).
+ * Invalid parameters give (0, -1) as well.
+ *   win: dev int32 [K][ncomp][ndim][2] (inclusive bounds).
+ * ------------------------------------------------------------------------ */
+int vup_windows(const vup_grid* g, const vup_dists* d, int32_t* win, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_propagate - eq. VUP: P = M . P_in for all K input pdfs at once, with
+ * the input probability matrix never materialised: densities are generated in
+ * the kernel from (mu, sigma) as products of per-axis Gaussian factors over
+ * the truncation window and accumulated per bin in on-chip histograms.
+ *   P: dev FP32 [K][B] (row k = output pdf of distribution k; the paper's
+ *      N_y x L output matrix stored column-major);
+ *   Z: dev FP64 [K][ncomp] or NULL: sum of the (precision-rounded) weights of
+ *      each component over its window, including cells with no bin.
+ * precision: VUP_FP32 / VUP_BF16 / VUP_BF16X2 / VUP_FP8E4M3.
+ * Invalid parameters -> NaN row (counter bad_param); every window empty ->
+ * zero row (counter empty). Column sums are 1 up to FP32 rounding unless some
+ * cells of the window have bin -1.
+ * EINVAL: bad descriptors; EWORKSPACE: mm not from vup_bin.
+ * ------------------------------------------------------------------------ */
+int vup_propagate(const vup_mm* mm, const vup_dists* d, int32_t precision, float* P, double* Z,
+                  void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_moments - output moments of each propagated pdf from the exact model
+ * values (quadrature form of the marginalisation integral, eq. UP):
+ *   mean[k] = sum_i p_k(x_i) f_i,  var[k] = sum_i p_k(x_i) (f_i - mean_k)^2,
+ * with FP32 per-row partial sums of shifted values and FP64 accumulation.
+ * delta2 (optional, ncomp == 1 and a built-in model only): the local expected
+ * squared deviation of eq. IPSAvar, 1/2 sum_i p_k(x_i)(f_i - M(mu_k))^2,
+ * computed as (var + (mean - M(mu_k))^2)/2 with M evaluated at mu_k.
+ *   mean, var: dev FP64 [K]; delta2: dev FP64 [K] or NULL; model: host, used
+ *   only for delta2 (may be NULL when delta2 is NULL).
+ * Moments are of the f given to vup_bin (its FP32 copy, see DESIGN notes in
+ * the source). NaN for invalid parameters or all-empty windows.
+ * ------------------------------------------------------------------------ */
+int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, double* mean,
+                double* var, double* delta2, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_ipsa - coarse-grained IPSA quantities per column (Sec. 5.2): with bin
+ * centres c_b = (e_b + e_{b+1})/2,
+ *   mean_hist[k] = sum_b P[k][b] c_b,
+ *   var[k]       = sum_b P[k][b] (c_b - mean_hist[k])^2   (two passes),
+ *   entropy[k]   = -sum_{b: P>0} P[k][b] ln P[k][b]        (nats),
+ * all accumulated in FP64. Variance and entropy are invariant under the
+ * per-column translation y -> y - y(l) that turns the output matrix into the
+ * IPSA probability matrix.
+ *   P: dev FP32 [K][B]; mean_hist, var, entropy: dev FP64 [K] (any may be NULL).
+ * ------------------------------------------------------------------------ */
+int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, double* var,
+             double* entropy, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_ipsa_backward - sensitivity of Q_k = g_var[k] var[k] + g_ent[k] entropy[k]
+ * (the IPSA outputs of vup_ipsa) to the pdf parameters, by an adjoint sweep
+ * over the same truncation windows (windows are held fixed: cells entering or
+ * leaving a window are not differentiated). With v_b = dQ/dP_b =
+ * g_var((c_b - E)^2 - 2 c_b S) - g_ent(ln P_b + 1), S = sum_b P_b (c_b - E):
+ *   dQ/dmu_{c,d}    = pi_c Cov_{q_c}(v_bin, (x_d - mu_d)/sigma_d^2)
+ *   dQ/dsigma_{c,d} = pi_c Cov_{q_c}(v_bin, (x_d - mu_d)^2/sigma_d^3)
+ *   dQ/dpi_c        = E_{q_c}[v_bin]
+ * where q_c is component c's normalised truncated density.
+ *   P: dev FP32 [K][B] from vup_propagate (VUP_FP32); mean_hist: dev FP64 [K]
+ *   from vup_ipsa; g_var, g_ent: dev FP64 [K] or NULL (= 0);
+ *   g_mu, g_sigma: dev FP64 [K][ncomp][ndim]; g_weight: dev FP64 [K][ncomp] or NULL.
+ * Invalid parameters give NaN gradients.
+ * ------------------------------------------------------------------------ */
+int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
+                      const double* mean_hist, const double* g_var, const double* g_ent,
+                      double* g_mu, double* g_sigma, double* g_weight, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_counters - reads and clears the device-side event counters of a model
+ * matrix's workspace. Synchronises `stream`.
+ *   out (host int64[4]): [0] cells with no bin (set by vup_bin),
+ *   [1] bad_edges (vup_bin), [2] components with invalid parameters,
+ *   [3] distributions whose every window is empty (vup_propagate).
+ * ------------------------------------------------------------------------ */
+int vup_counters(const vup_mm* mm, void* stream, int64_t* out);
+
+/* last error message of the calling thread ("" if none). */
+const char* vup_last_error(void);
+
+/* library version string */
+const char* vup_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VUP_H */

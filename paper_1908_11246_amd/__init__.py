@@ -1,0 +1,338 @@
+"""Python binding of libvup.so: Vectorized Uncertainty Propagation (VUP) and
+Input Probability Sensitivity Analysis (IPSA), arXiv:1908.11246, on MI355X.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the current HIP stream. The
+binding fails loudly when the library or a GPU is missing; there is no CPU
+fallback.
+
+    mm = build_model_matrix(grid, f, edges)        # eq. (5): model matrix, once
+    P, Z = propagate(mm, mu, sigma)                # eq. VUP for all K pdfs at once
+    mean, var, _ = moments(mm, mu, sigma)          # exact-f output moments
+    mean_h, var_h, ent = ipsa(mm, P)               # IPSA coarse-grained quantities
+    var_h, ent = IPSA.apply(mu, sigma, None, mm)   # differentiable wrt mu, sigma
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libvup.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "vup.h")
+
+VUP_OK = 0
+STATUS = {-1: "VUP_EINVAL", -2: "VUP_ENODEV", -3: "VUP_EDEVICE", -4: "VUP_EUNSUPPORTED",
+          -5: "VUP_EWORKSPACE"}
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x2": 2, "fp8e4m3": 3}
+MODELS = {"linear": 0, "sincos2": 1, "damped3": 2, "ring4": 3, "timing2": 4, "ipsa2": 5}
+
+
+class VupError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class VupGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 4),
+                ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4)]
+
+
+class VupModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("theta", ctypes.c_double * 8)]
+
+
+class VupDists(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("ncomp", ctypes.c_int32), ("ndim", ctypes.c_int32),
+                ("n_sigma", ctypes.c_double), ("mu", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+
+
+class VupMM(ctypes.Structure):
+    _fields_ = [("grid", VupGrid), ("B", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("N", ctypes.c_int64), ("rows", ctypes.c_int64), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("off_edges", ctypes.c_size_t),
+                ("off_binmap", ctypes.c_size_t), ("off_f32", ctypes.c_size_t),
+                ("off_counts", ctypes.c_size_t), ("off_offsets", ctypes.c_size_t),
+                ("off_perm", ctypes.c_size_t), ("off_scratch", ctypes.c_size_t),
+                ("off_counters", ctypes.c_size_t), ("magic", ctypes.c_uint64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIBPATH)
+    lib.vup_last_error.restype = ctypes.c_char_p
+    lib.vup_version.restype = ctypes.c_char_p
+    lib.vup_eval_grid.argtypes = [_P(VupGrid), _P(VupModel), _vp, _vp]
+    lib.vup_uniform_edges.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]
+    lib.vup_bin_workspace_bytes.restype = ctypes.c_size_t
+    lib.vup_bin_workspace_bytes.argtypes = [_P(VupGrid), ctypes.c_int32]
+    lib.vup_bin.argtypes = [_P(VupGrid), _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t,
+                            _P(VupMM), _vp]
+    lib.vup_windows.argtypes = [_P(VupGrid), _P(VupDists), _vp, _vp]
+    lib.vup_propagate.argtypes = [_P(VupMM), _P(VupDists), ctypes.c_int32, _vp, _vp, _vp]
+    lib.vup_moments.argtypes = [_P(VupMM), _P(VupDists), _P(VupModel), _vp, _vp, _vp, _vp]
+    lib.vup_ipsa.argtypes = [_P(VupMM), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+    lib.vup_ipsa_backward.argtypes = [_P(VupMM), _P(VupDists), _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp]
+    lib.vup_counters.argtypes = [_P(VupMM), _vp, _P(ctypes.c_int64)]
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/vup.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(vup_\w+)\s*\(", txt, re.M)))
+
+
+def _check(code: int):
+    if code != VUP_OK:
+        raise VupError(code, _load().vup_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, device) -> torch.Tensor:
+    t = torch.as_tensor(t)
+    return t.to(device=device, dtype=torch.float64).contiguous()
+
+
+def make_grid(n: Sequence[int], lo: Sequence[float], hi: Sequence[float]) -> VupGrid:
+    g = VupGrid()
+    g.ndim = len(n)
+    for d in range(len(n)):
+        g.n[d] = int(n[d])
+        g.lo[d] = float(lo[d])
+        g.hi[d] = float(hi[d])
+    return g
+
+
+def make_model(name: str, theta: Sequence[float] = ()) -> VupModel:
+    m = VupModel()
+    m.kind = MODELS[name]
+    for i, v in enumerate(theta):
+        m.theta[i] = float(v)
+    return m
+
+
+def _dists(mu: torch.Tensor, sigma: torch.Tensor, weight: Optional[torch.Tensor],
+           n_sigma: float) -> VupDists:
+    d = VupDists()
+    d.K = mu.shape[0]
+    d.ncomp = mu.shape[1]
+    d.ndim = mu.shape[2]
+    d.n_sigma = float(n_sigma)
+    d.mu = mu.data_ptr() if mu.numel() else None
+    d.sigma = sigma.data_ptr() if sigma.numel() else None
+    d.weight = None if weight is None else weight.data_ptr()
+    return d
+
+
+def _norm_params(mu, sigma, weight, device):
+    mu = _dev_f64(mu, device)
+    sigma = _dev_f64(sigma, device)
+    if mu.dim() == 2:
+        mu = mu.unsqueeze(1)
+        sigma = sigma.unsqueeze(1)
+    if mu.shape != sigma.shape:
+        raise ValueError("mu and sigma must have the same shape [K][C][d]")
+    w = None if weight is None else _dev_f64(weight, device)
+    return mu, sigma, w
+
+
+def eval_grid(grid: VupGrid, model: str, theta: Sequence[float] = (), device="cuda") -> torch.Tensor:
+    """Alg. VUP: f_i = M(x_i) at every cell centre (FP64, row major)."""
+    N = 1
+    for d in range(grid.ndim):
+        N *= grid.n[d]
+    f = torch.empty(N, dtype=torch.float64, device=device)
+    m = make_model(model, theta)
+    _check(_load().vup_eval_grid(ctypes.byref(grid), ctypes.byref(m), _ptr(f), _vp(_stream())))
+    return f
+
+
+def uniform_edges(f: torch.Tensor, B: int) -> torch.Tensor:
+    e = torch.empty(B + 1, dtype=torch.float64, device=f.device)
+    _check(_load().vup_uniform_edges(_ptr(f), f.numel(), int(B), _ptr(e), _vp(_stream())))
+    return e
+
+
+class ModelMatrix:
+    """The sparse one-hot model matrix of eq. (5), built once by vup_bin and
+    reused for every propagated distribution. Owns its device workspace."""
+
+    def __init__(self, grid: VupGrid, f: torch.Tensor, edges: torch.Tensor,
+                 want_bin: bool = True):
+        lib_ = _load()
+        self.grid = grid
+        self.B = edges.numel() - 1
+        nbytes = lib_.vup_bin_workspace_bytes(ctypes.byref(grid), self.B)
+        if nbytes == 0:
+            raise VupError(-1, "invalid grid or bin count")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=f.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.mm = VupMM()
+        self.bin = torch.empty(f.numel(), dtype=torch.int32, device=f.device) if want_bin else None
+        _check(lib_.vup_bin(ctypes.byref(grid), _ptr(f), _ptr(edges), self.B, _ptr(self.bin),
+                            _vp(self._ws_ptr), nbytes, ctypes.byref(self.mm), _vp(_stream())))
+        self.device = f.device
+
+    def _view(self, off, dtype, count):
+        start = self._ws_ptr - self.ws.data_ptr() + off
+        esz = torch.empty((), dtype=dtype).element_size()
+        return self.ws[start:start + count * esz].view(dtype)
+
+    @property
+    def edges(self) -> torch.Tensor:
+        return self._view(self.mm.off_edges, torch.float64, self.B + 1)
+
+    @property
+    def counts(self) -> torch.Tensor:
+        """cells per bin; index B counts cells with no bin."""
+        return self._view(self.mm.off_counts, torch.int64, self.B + 1)
+
+    @property
+    def offsets(self) -> torch.Tensor:
+        """CSR row starts of the model matrix (by bin); offsets[B] = binned cells."""
+        return self._view(self.mm.off_offsets, torch.int64, self.B + 1)
+
+    @property
+    def perm(self) -> torch.Tensor:
+        """binned cell indices sorted by bin, increasing within a bin."""
+        return self._view(self.mm.off_perm, torch.int32, int(self.mm.N))
+
+    def counters(self) -> dict:
+        out = (ctypes.c_int64 * 4)()
+        _check(_load().vup_counters(ctypes.byref(self.mm), _vp(_stream()), out))
+        return dict(outside=out[0], bad_edges=out[1], bad_param=out[2], empty=out[3])
+
+
+def build_model_matrix(grid: VupGrid, f: torch.Tensor, edges: torch.Tensor,
+                       want_bin: bool = True) -> ModelMatrix:
+    return ModelMatrix(grid, f, edges, want_bin)
+
+
+def windows(grid: VupGrid, mu, sigma, n_sigma: float = 4.0, device="cuda") -> torch.Tensor:
+    mu, sigma, _ = _norm_params(mu, sigma, None, device)
+    K, C, D = mu.shape
+    win = torch.empty((K, C, D, 2), dtype=torch.int32, device=device)
+    d = _dists(mu, sigma, None, n_sigma)
+    _check(_load().vup_windows(ctypes.byref(grid), ctypes.byref(d), _ptr(win), _vp(_stream())))
+    return win
+
+
+def propagate(mm: ModelMatrix, mu, sigma, weight=None, precision: str = "fp32",
+              n_sigma: float = 4.0, out: Optional[torch.Tensor] = None, want_Z: bool = True):
+    """eq. VUP: P[K][B] (FP32) and Z[K][C] (FP64) for all distributions at once."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
+    K, C, _ = mu.shape
+    P = out if out is not None else torch.empty((K, mm.B), dtype=torch.float32, device=mm.device)
+    Z = torch.empty((K, C), dtype=torch.float64, device=mm.device) if want_Z else None
+    d = _dists(mu, sigma, w, n_sigma)
+    _check(_load().vup_propagate(ctypes.byref(mm.mm), ctypes.byref(d), PRECISIONS[precision],
+                                 _ptr(P), _ptr(Z), _vp(_stream())))
+    return P, Z
+
+
+def moments(mm: ModelMatrix, mu, sigma, weight=None, model: Optional[str] = None,
+            theta: Sequence[float] = (), n_sigma: float = 4.0):
+    """(mean[K], var[K], delta2[K] or None) from the exact model values."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
+    K = mu.shape[0]
+    mean = torch.empty(K, dtype=torch.float64, device=mm.device)
+    var = torch.empty(K, dtype=torch.float64, device=mm.device)
+    d2 = torch.empty(K, dtype=torch.float64, device=mm.device) if model else None
+    m = make_model(model, theta) if model else None
+    d = _dists(mu, sigma, w, n_sigma)
+    _check(_load().vup_moments(ctypes.byref(mm.mm), ctypes.byref(d),
+                               ctypes.byref(m) if m is not None else None, _ptr(mean), _ptr(var),
+                               _ptr(d2), _vp(_stream())))
+    return mean, var, d2
+
+
+def ipsa(mm: ModelMatrix, P: torch.Tensor):
+    """(mean_hist[K], var[K], entropy[K]) of each propagated column (FP64)."""
+    K = P.shape[0]
+    m = torch.empty(K, dtype=torch.float64, device=P.device)
+    v = torch.empty(K, dtype=torch.float64, device=P.device)
+    h = torch.empty(K, dtype=torch.float64, device=P.device)
+    _check(_load().vup_ipsa(ctypes.byref(mm.mm), K, _ptr(P), _ptr(m), _ptr(v), _ptr(h),
+                            _vp(_stream())))
+    return m, v, h
+
+
+def ipsa_backward(mm: ModelMatrix, mu, sigma, weight, P, mean_hist, g_var=None, g_ent=None,
+                  n_sigma: float = 4.0):
+    """Gradients of g_var*var + g_ent*entropy wrt mu, sigma [K][C][d], weight [K][C]."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
+    K, C, D = mu.shape
+    gm = torch.empty((K, C, D), dtype=torch.float64, device=mm.device)
+    gs = torch.empty((K, C, D), dtype=torch.float64, device=mm.device)
+    gw = torch.empty((K, C), dtype=torch.float64, device=mm.device)
+    gv = None if g_var is None else _dev_f64(g_var, mm.device)
+    ge = None if g_ent is None else _dev_f64(g_ent, mm.device)
+    d = _dists(mu, sigma, w, n_sigma)
+    _check(_load().vup_ipsa_backward(ctypes.byref(mm.mm), ctypes.byref(d), _ptr(P),
+                                     _ptr(mean_hist), _ptr(gv), _ptr(ge), _ptr(gm), _ptr(gs),
+                                     _ptr(gw), _vp(_stream())))
+    return gm, gs, gw
+
+
+class IPSA(torch.autograd.Function):
+    """IPSA map (per-location output variance and entropy) as a differentiable
+    function of the input pdf parameters; the backward is the library's
+    adjoint sweep (windows held fixed)."""
+
+    @staticmethod
+    def forward(ctx, mu, sigma, weight, mm: ModelMatrix, n_sigma: float = 4.0):
+        P, _ = propagate(mm, mu.detach(), sigma.detach(),
+                         None if weight is None else weight.detach(), "fp32", n_sigma)
+        mean_h, var, ent = ipsa(mm, P)
+        ctx.mm = mm
+        ctx.n_sigma = n_sigma
+        ctx.has_weight = weight is not None
+        ctx.save_for_backward(mu.detach(), sigma.detach(),
+                              weight.detach() if weight is not None else mu.new_empty(0), P,
+                              mean_h)
+        return var, ent
+
+    @staticmethod
+    def backward(ctx, g_var, g_ent):
+        mu, sigma, weight, P, mean_h = ctx.saved_tensors
+        w = weight if ctx.has_weight else None
+        gv = g_var if g_var is not None else torch.zeros_like(mean_h)
+        ge = g_ent if g_ent is not None else torch.zeros_like(mean_h)
+        gm, gs, gw = ipsa_backward(ctx.mm, mu, sigma, w, P, mean_h, gv.contiguous(),
+                                   ge.contiguous(), ctx.n_sigma)
+        gm = gm.reshape(mu.shape).to(mu.dtype)
+        gs = gs.reshape(sigma.shape).to(sigma.dtype)
+        gwo = gw.reshape(weight.shape).to(weight.dtype) if ctx.has_weight else None
+        return gm, gs, gwo, None, None

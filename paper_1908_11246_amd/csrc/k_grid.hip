@@ -1,0 +1,437 @@
+// Model-matrix construction (done once per grid and model, Appendix A: the
+// N model evaluations and the sort are amortised over all propagated pdfs):
+//   k_eval_grid     f_i = M(x_i) at cell centres, FP64
+//   k_minmax / k_edges   B uniform bins over [min f, max f]
+//   k_bin           indicator of eq. (4) as a bin index; padded bin map
+//                   (4*bin, LDS byte offsets for the sweep kernels), padded
+//                   FP32 copy of f, per-chunk bin counts
+//   k_scan_counts   exclusive scan of the counts in (bin, chunk) order
+//   k_scatter       stable scatter of cell indices into compressed-by-bin
+//                   order (the sparse one-hot model matrix of eq. (5))
+// plus the per-distribution window listing and the IPSA column statistics.
+#include <hip/hip_runtime.h>
+
+#include "vup_device.hpp"
+#include "vup_internal.hpp"
+
+namespace vup {
+
+// ---------------------------------------------------------------------------
+// model evaluation
+// ---------------------------------------------------------------------------
+struct EvalArgs {
+  int ndim;
+  int n[4];
+  double lo[4], hi[4];
+  vup_model m;
+  long long N;
+};
+
+__global__ __launch_bounds__(256) void k_eval_grid(EvalArgs a, double* __restrict__ f) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  double x[4];
+  long long t = i;
+  for (int d = a.ndim - 1; d >= 0; --d) {
+    const int j = (int)(t % a.n[d]);
+    t /= a.n[d];
+    x[d] = cell_centre(a.lo[d], a.hi[d], a.n[d], j);
+  }
+  f[i] = model_at(a.m.kind, a.ndim, a.m.theta, x);
+}
+
+hipError_t launch_eval_grid(const vup_grid& g, const vup_model& m, double* f, hipStream_t s) {
+  EvalArgs a{};
+  a.ndim = g.ndim;
+  a.N = 1;
+  for (int d = 0; d < g.ndim; ++d) {
+    a.n[d] = g.n[d];
+    a.lo[d] = g.lo[d];
+    a.hi[d] = g.hi[d];
+    a.N *= g.n[d];
+  }
+  a.m = m;
+  const long long blocks = (a.N + 255) / 256;
+  hipLaunchKernelGGL(k_eval_grid, dim3((unsigned)blocks), dim3(256), 0, s, a, f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// uniform edges: min/max via order-preserving integer images of the doubles
+// (exact, order independent), then e_b = lo + b*((hi - lo)/B), e_B = hi.
+// The two extreme slots of `edges` hold the running min/max images.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ord_of(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double of_ord(unsigned long long o) {
+  const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+  return __longlong_as_double((long long)u);
+}
+
+__global__ void k_minmax_init(unsigned long long* e, int B) {
+  if (threadIdx.x == 0) {
+    e[0] = ~0ull;  // running min image
+    e[B] = 0ull;   // running max image
+  }
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const double* __restrict__ f, long long N,
+                                                unsigned long long* e, int B) {
+  unsigned long long mn = ~0ull, mx = 0ull;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (long long)gridDim.x * 256) {
+    const double v = f[i];
+    if (v != v) continue;
+    const unsigned long long o = ord_of(v);
+    mn = o < mn ? o : mn;
+    mx = o > mx ? o : mx;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_xor(mn, off, 64), b = __shfl_xor(mx, off, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(e, mn);
+    atomicMax(e + B, mx);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_edges(double* e, int B) {
+#pragma clang fp contract(off)
+  __shared__ double lohi[2];
+  if (threadIdx.x == 0) {
+    const unsigned long long* u = reinterpret_cast<const unsigned long long*>(e);
+    lohi[0] = of_ord(u[0]);
+    lohi[1] = of_ord(u[B]);
+  }
+  __syncthreads();
+  const double lo = lohi[0], hi = lohi[1];
+  const double w = (hi - lo) / B;
+  for (int b = threadIdx.x; b <= B; b += blockDim.x) e[b] = (b == B) ? hi : lo + b * w;
+}
+
+hipError_t launch_uniform_edges(const double* f, int64_t N, int B, double* edges, hipStream_t s) {
+  unsigned long long* e = reinterpret_cast<unsigned long long*>(edges);
+  hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(64), 0, s, e, B);
+  long long blocks = (N + 4095) / 4096;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, s, f, (long long)N, e, B);
+  hipLaunchKernelGGL(k_edges, dim3(1), dim3(256), 0, s, edges, B);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+struct BinArgs {
+  const double* __restrict__ f;
+  const double* __restrict__ edges_in;
+  double* edges_ws;
+  int32_t* bin;       // may be null
+  uint16_t* binmap;   // [rows*pitch]
+  float* f32;         // [rows*pitch]
+  int* chunk_counts;  // [(B+1) * nblk], bin-major
+  unsigned long long* counters;
+  int B;
+  int nL;             // cells on the fastest axis
+  int pitch;
+  long long rows;
+  long long nblk;
+};
+
+// bin index of y: largest b < B with e[b] <= y, when e[0] <= y <= e[B]
+__device__ __forceinline__ int bin_search(const double* e, int B, double y) {
+  if (!(y >= e[0] && y <= e[B])) return -1;
+  int lo = 0, hi = B - 1;  // answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (e[mid] <= y) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bin(BinArgs a) {
+  extern __shared__ double sh[];  // edges[B+1], then int counts[B+1]
+  double* e = sh;
+  int* cnt = reinterpret_cast<int*>(sh + a.B + 1);
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b <= a.B; b += 256) {
+    const double v = a.edges_in[b];
+    e[b] = v;
+    if (!isfinite(v)) atomicOr(&bad, 1);
+    if (b > 0 && !(a.edges_in[b - 1] < v)) atomicOr(&bad, 1);
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int b = threadIdx.x; b <= a.B; b += 256) a.edges_ws[b] = e[b];
+    if (threadIdx.x == 0 && bad) atomicAdd(a.counters + kCntBadEdges, 1ull);
+  }
+  const long long base = (long long)blockIdx.x * kBinChunk;
+  const long long total = a.rows * a.pitch;
+  int outside = 0;
+  for (int q = threadIdx.x; q < kBinChunk; q += 256) {
+    const long long p = base + q;
+    if (p >= total) break;
+    const long long row = p / a.pitch;
+    const int col = (int)(p - row * a.pitch);
+    uint16_t code = (uint16_t)(4 * a.B);
+    float fv = 0.0f;
+    if (col < a.nL) {
+      const long long cell = row * a.nL + col;
+      const double y = a.f[cell];
+      const int b = bad ? -1 : bin_search(e, a.B, y);
+      if (a.bin) a.bin[cell] = b;
+      if (b >= 0) {
+        code = (uint16_t)(4 * b);
+        atomicAdd(&cnt[b], 1);
+      } else {
+        ++outside;
+        atomicAdd(&cnt[a.B], 1);
+      }
+      fv = (float)y;
+    }
+    a.binmap[p] = code;
+    a.f32[p] = fv;
+  }
+  for (int off = 32; off > 0; off >>= 1) outside += __shfl_xor(outside, off, 64);
+  if ((threadIdx.x & 63) == 0 && outside) atomicAdd(a.counters + kCntOutside, (unsigned long long)outside);
+  __syncthreads();
+  for (int b = threadIdx.x; b <= a.B; b += 256) a.chunk_counts[(long long)b * a.nblk + blockIdx.x] = cnt[b];
+}
+
+// exclusive scan of chunk_counts in (bin, chunk) order by one workgroup;
+// also per-bin totals and CSR row starts
+__global__ __launch_bounds__(1024) void k_scan_counts(int* cc, long long len, long long nblk, int B,
+                                                      long long N, long long* counts,
+                                                      long long* offsets) {
+  __shared__ long long part[1024];
+  const long long per = (len + 1023) / 1024;
+  const long long s0 = threadIdx.x * per < len ? threadIdx.x * per : len;
+  const long long s1 = s0 + per < len ? s0 + per : len;
+  long long sum = 0;
+  for (long long i = s0; i < s1; ++i) sum += cc[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const long long v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  long long run = part[threadIdx.x];
+  for (long long i = s0; i < s1; ++i) {
+    const long long v = cc[i];
+    cc[i] = (int)run;  // exclusive position (< N)
+    run += v;
+  }
+  __syncthreads();
+  // bin b occupies [b*nblk, (b+1)*nblk); its first position is the CSR start.
+  // Slot B collects the cells without a bin, after all binned cells.
+  for (int b = threadIdx.x; b <= B; b += 1024) offsets[b] = cc[(long long)b * nblk];
+  __syncthreads();
+  for (int b = threadIdx.x; b <= B; b += 1024)
+    counts[b] = ((b < B) ? offsets[b + 1] : N) - offsets[b];
+}
+
+// one wave per chunk: cells in increasing order, stable within each bin
+__global__ __launch_bounds__(64) void k_scatter(BinArgs a, const int* __restrict__ cc,
+                                                int32_t* __restrict__ perm) {
+  extern __shared__ int pos[];  // [B+1] running positions of this chunk
+  for (int b = threadIdx.x; b <= a.B; b += 64) pos[b] = cc[(long long)b * a.nblk + blockIdx.x];
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kBinChunk;
+  const long long total = a.rows * a.pitch;
+  const int lane = threadIdx.x;
+  for (int q0 = 0; q0 < kBinChunk; q0 += 64) {
+    const long long p = base + q0 + lane;
+    int b = -2;
+    long long cell = -1;
+    if (p < total) {
+      const long long row = p / a.pitch;
+      const int col = (int)(p - row * a.pitch);
+      if (col < a.nL) {
+        cell = row * a.nL + col;
+        const int code = a.binmap[p];
+        b = (code == 4 * a.B) ? -2 : code >> 2;
+      }
+    }
+    unsigned long long todo = __ballot(b >= 0);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int bl = __shfl(b, leader, 64);
+      const unsigned long long m = __ballot(b == bl);
+      const int start = pos[bl];
+      if (b == bl) {
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        perm[start + rank] = (int32_t)cell;
+      }
+      __syncthreads();
+      if (lane == leader) pos[bl] = start + __popcll(m);
+      __syncthreads();
+      todo &= ~m;
+    }
+  }
+}
+
+hipError_t launch_bin(const vup_mm& mm, const double* f, const double* edges, int32_t* bin,
+                      hipStream_t s) {
+  char* ws = static_cast<char*>(mm.ws);
+  WsLayout L;
+  ws_layout(mm.grid, mm.B, &L);
+  BinArgs a{};
+  a.f = f;
+  a.edges_in = edges;
+  a.edges_ws = reinterpret_cast<double*>(ws + mm.off_edges);
+  a.bin = bin;
+  a.binmap = reinterpret_cast<uint16_t*>(ws + mm.off_binmap);
+  a.f32 = reinterpret_cast<float*>(ws + mm.off_f32);
+  a.chunk_counts = reinterpret_cast<int*>(ws + mm.off_scratch);
+  a.counters = reinterpret_cast<unsigned long long*>(ws + mm.off_counters);
+  a.B = mm.B;
+  a.nL = mm.grid.n[mm.grid.ndim - 1];
+  a.pitch = mm.pitch;
+  a.rows = mm.rows;
+  a.nblk = L.nblk;
+  const size_t lds = (size_t)(mm.B + 1) * 8 + (size_t)(mm.B + 1) * 4;
+  hipLaunchKernelGGL(k_bin, dim3((unsigned)L.nblk), dim3(256), lds, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.chunk_counts,
+                     (long long)(mm.B + 1) * L.nblk, L.nblk, mm.B, (long long)mm.N,
+                     reinterpret_cast<long long*>(ws + mm.off_counts),
+                     reinterpret_cast<long long*>(ws + mm.off_offsets));
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)L.nblk), dim3(64), (size_t)(mm.B + 1) * 4, s, a,
+                     a.chunk_counts, reinterpret_cast<int32_t*>(ws + mm.off_perm));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// windows of every (k, c)
+// ---------------------------------------------------------------------------
+struct WinArgs {
+  int ndim;
+  int n[4];
+  double lo[4], hi[4];
+  DistsDev d;
+};
+
+__global__ __launch_bounds__(256) void k_windows(WinArgs a, int32_t* __restrict__ win) {
+  const long long kc = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (kc >= a.d.K * a.d.C) return;
+  const int D = a.ndim;
+  int lo[4], hi[4];
+  bool bad = false;
+  for (int d = 0; d < D; ++d) {
+    if (!axis_window(a.lo[d], a.hi[d], a.n[d], a.d.mu[kc * D + d], a.d.sigma[kc * D + d], a.d.ns,
+                     lo[d], hi[d]))
+      bad = true;
+  }
+  for (int d = 0; d < D; ++d) {
+    win[(kc * D + d) * 2 + 0] = bad ? 0 : lo[d];
+    win[(kc * D + d) * 2 + 1] = bad ? -1 : hi[d];
+  }
+}
+
+hipError_t launch_windows(const vup_grid& g, const vup_dists& d, int32_t* win, hipStream_t s) {
+  const long long n = d.K * d.ncomp;
+  if (n == 0) return hipSuccess;
+  WinArgs a{};
+  a.ndim = g.ndim;
+  for (int i = 0; i < g.ndim; ++i) {
+    a.n[i] = g.n[i];
+    a.lo[i] = g.lo[i];
+    a.hi[i] = g.hi[i];
+  }
+  a.d = make_dists_dev(d);
+  hipLaunchKernelGGL(k_windows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, win);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// IPSA column statistics: one wave per column, FP64 accumulation
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ipsa(const float* __restrict__ P, long long K, int B,
+                                              const double* __restrict__ e, double* mean_hist,
+                                              double* var, double* entropy) {
+  const long long k = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= K) return;
+  const int lane = threadIdx.x & 63;
+  const float* Pk = P + k * (long long)B;
+  double m = 0.0;
+  for (int b = lane; b < B; b += 64) m += (double)Pk[b] * (0.5 * (e[b] + e[b + 1]));
+  m = wave_sum(m);
+  double v = 0.0, h = 0.0;
+  for (int b = lane; b < B; b += 64) {
+    const double p = (double)Pk[b];
+    const double dc = 0.5 * (e[b] + e[b + 1]) - m;
+    v += p * (dc * dc);
+    if (p > 0.0) h -= p * log(p);
+  }
+  v = wave_sum(v);
+  h = wave_sum(h);
+  if (lane == 0) {
+    if (mean_hist) mean_hist[k] = m;
+    if (var) var[k] = v;
+    if (entropy) entropy[k] = h;
+  }
+}
+
+hipError_t launch_ipsa(const vup_mm& mm, int64_t K, const float* P, double* mean_hist, double* var,
+                       double* entropy, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  const double* e = reinterpret_cast<const double*>(static_cast<const char*>(mm.ws) + mm.off_edges);
+  hipLaunchKernelGGL(k_ipsa, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, P, (long long)K, mm.B, e,
+                     mean_hist, var, entropy);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
+  WsLayout L{};
+  const int nL = g.n[g.ndim - 1];
+  L.pitch = (nL + 31) / 32 * 32;
+  L.rows = 1;
+  for (int d = 0; d + 1 < g.ndim; ++d) L.rows *= g.n[d];
+  const long long N = L.rows * nL;
+  const long long padded = L.rows * L.pitch;
+  L.nblk = (padded + kBinChunk - 1) / kBinChunk;
+  size_t o = 0;
+  L.off_edges = o;
+  o = align256(o + (size_t)(B + 1) * 8);
+  L.off_binmap = o;
+  o = align256(o + (size_t)padded * 2);
+  L.off_f32 = o;
+  o = align256(o + (size_t)padded * 4);
+  L.off_counts = o;
+  o = align256(o + (size_t)(B + 1) * 8);
+  L.off_offsets = o;
+  o = align256(o + (size_t)(B + 1) * 8);
+  L.off_perm = o;
+  o = align256(o + (size_t)N * 4);
+  L.off_scratch = o;
+  o = align256(o + (size_t)(B + 1) * (size_t)L.nblk * 4);
+  L.off_counters = o;
+  o = align256(o + 8 * 8);
+  L.bytes = o;
+  *out = L;
+  return true;
+}
+
+}  // namespace vup

@@ -1,0 +1,830 @@
+// Window sweeps over the shared model matrix: propagation (eq. VUP), exact-f
+// moments, and the adjoint sweep of the IPSA sensitivities.
+//
+// One workgroup (256 threads, 4 waves) handles one distribution k and loops
+// over its mixture components. For each component:
+//   1. the truncation window is computed per axis (FP64, exact op order) and
+//      the per-axis Gaussian factors g_d(j) are tabulated in LDS (FP64 exp,
+//      stored FP32). The fastest-axis table is zero-padded to whole strips;
+//   2. the window is swept as rows (all axes but the fastest) x strips of SW
+//      consecutive cells of the fastest axis, aligned to SW in the padded bin
+//      map. A thread keeps its strip's factors in registers and walks rows; the
+//      row factor (product of the slower axes' factors) and the row's bin-map
+//      offset come from a row table in LDS;
+//   3. per cell the density is one FP32 multiply (row factor x fastest-axis
+//      factor) and the accumulation is an LDS float add into the bin's slot.
+//      Each wave owns `cpw` private copies of the histogram (rows of a wave
+//      spread over them), so same-bin neighbours of different rows do not
+//      collide and the summation order is fixed: results are deterministic.
+// The input probability matrix is never materialised.
+#include <hip/hip_runtime.h>
+
+#include "vup_device.hpp"
+#include "vup_internal.hpp"
+
+namespace vup {
+
+struct SweepArgs {
+  GridDev g;
+  DistsDev d;
+  int B;
+  const uint16_t* __restrict__ binmap;
+  const float* __restrict__ f32;
+  const double* __restrict__ edges;
+  unsigned long long* counters;
+  SweepLayout L;
+  long long kpx;  // distributions per XCD slot (block -> k mapping)
+  // propagate
+  float* P;
+  double* Z;
+  // moments
+  double* mean;
+  double* var;
+  double* delta2;
+  vup_model model;
+  int has_model;
+  // backward
+  const float* Pin;
+  const double* mean_hist;
+  const double* g_var;
+  const double* g_ent;
+  double* g_mu;
+  double* g_sigma;
+  double* g_weight;
+};
+
+// per-component window state, identical in every thread of the workgroup
+struct Win {
+  int lo[4];
+  int W[4];
+  long long R;  // rows
+  bool bad;
+  bool empty;
+};
+
+__device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc) {
+  Win w;
+  w.bad = false;
+  w.empty = false;
+  w.R = 1;
+  const int D = a.g.ndim;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    w.lo[d] = 0;
+    w.W[d] = 1;
+    if (d < D) {
+      int jlo, jhi;
+      const bool ok = axis_window(a.g.lo[d], a.g.hi[d], a.g.n[d], a.d.mu[kc * D + d],
+                                  a.d.sigma[kc * D + d], a.d.ns, jlo, jhi);
+      if (!ok) w.bad = true;
+      if (jhi < jlo) w.empty = true;
+      w.lo[d] = jlo;
+      w.W[d] = jhi - jlo + 1;
+      if (d + 1 < D) w.R *= (w.W[d] > 0 ? w.W[d] : 0);
+    }
+  }
+  return w;
+}
+
+// fastest-axis window bounds (avoids dynamic indexing of the Win arrays)
+__device__ __forceinline__ void last_axis(const Win& w, int D, int& lo, int& W) {
+  lo = w.lo[0];
+  W = w.W[0];
+#pragma unroll
+  for (int d = 1; d < 4; ++d)
+    if (d == D - 1) {
+      lo = w.lo[d];
+      W = w.W[d];
+    }
+}
+
+// block -> distribution: consecutive blocks are spread over the 8 XCDs, so a
+// contiguous range of distributions (overlapping windows) shares one L2.
+__device__ __forceinline__ long long block_k(const SweepArgs& a) {
+  const long long b = blockIdx.x;
+  return (b & 7) * a.kpx + (b >> 3);
+}
+
+// strip width minimising the sweep time estimate of one component
+__device__ __forceinline__ int choose_sw(int loL, int WL, long long R, int maxsw) {
+  int best = 4;
+  long long bestc = 0x7fffffffffffffffll;
+  for (int sw = 4; sw <= maxsw; sw *= 2) {
+    const int ns = (loL + WL - 1) / sw - loL / sw + 1;
+    const int cols = ns < kThreads ? ns : kThreads;
+    const int P0 = kThreads / cols;
+    const long long ncg = (ns + kThreads - 1) / kThreads;
+    const long long c = ((R + P0 - 1) / P0) * ncg * (sw + 6);
+    if (c < bestc) {
+      bestc = c;
+      best = sw;
+    }
+  }
+  return best;
+}
+
+// Build per-axis factor tables for the window of component kc. Outer axes
+// d < D-1: tab_d[i] = g_d(lo_d + i), i < W_d. Fastest axis: tab_L[jj] for
+// jj < ns*sw, cell colbase + jj, zero outside the window.
+__device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, const Win& w,
+                                             long long kc, int sw, int colbase, int ns) {
+  const int D = a.g.ndim;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d + 1 < D) {
+      float* tab = smem + a.L.tab_off[d];
+      const double mu = a.d.mu[kc * D + d], sg = a.d.sigma[kc * D + d];
+      for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
+        const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
+        tab[i] = (float)gauss_factor(x, mu, sg);
+      }
+    }
+  }
+  const int L = D - 1;
+  int loL, WL;
+  last_axis(w, D, loL, WL);
+  float* tab = smem + a.L.tab_off[L];
+  const double mu = a.d.mu[kc * D + L], sg = a.d.sigma[kc * D + L];
+  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+    const int j = colbase + jj;
+    float v = 0.0f;
+    if (j >= loL && j < loL + WL) {
+      const double x = cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], j);
+      v = (float)gauss_factor(x, mu, sg);
+    }
+    tab[jj] = v;
+  }
+}
+
+// Row table for rows [r0, r0 + rc): row factor (product of the slower axes'
+// factors) and element offset of the row in the padded bin map. With
+// `trow`, also the standardised coordinates t_d of the slower axes.
+__device__ __forceinline__ void build_rows(const SweepArgs& a, float* smem, const Win& w,
+                                           long long r0, int rc, long long kc, bool trow) {
+  const int D = a.g.ndim;
+  float2* rt = reinterpret_cast<float2*>(smem + a.L.row_off);
+  float4* tt = trow ? reinterpret_cast<float4*>(smem + a.L.trow_off) : nullptr;
+  for (int r = threadIdx.x; r < rc; r += kThreads) {
+    long long t = r0 + r;
+    float go = 1.0f;
+    long long off = 0;
+    float tv[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      if (d <= D - 2) {
+        const int i = (int)(t % w.W[d]);
+        t /= w.W[d];
+        go *= smem[a.L.tab_off[d] + i];
+        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
+        if (trow) {
+          const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
+          tv[d] = (float)((x - a.d.mu[kc * D + d]) / a.d.sigma[kc * D + d]);
+        }
+      }
+    }
+    rt[r] = make_float2(go, __int_as_float((int)off));
+    if (trow) tt[r] = make_float4(tv[0], tv[1], tv[2], 0.0f);
+  }
+}
+
+template <int SW>
+struct MapVec {
+  uint32_t v[SW / 2];
+};
+
+template <int SW>
+__device__ __forceinline__ MapVec<SW> load_map(const uint16_t* __restrict__ p) {
+  MapVec<SW> m;
+  if constexpr (SW == 4) {
+    const uint2 q = *reinterpret_cast<const uint2*>(p);
+    m.v[0] = q.x;
+    m.v[1] = q.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < SW / 8; ++i) {
+      const uint4 q = reinterpret_cast<const uint4*>(p)[i];
+      m.v[4 * i + 0] = q.x;
+      m.v[4 * i + 1] = q.y;
+      m.v[4 * i + 2] = q.z;
+      m.v[4 * i + 3] = q.w;
+    }
+  }
+  return m;
+}
+
+template <int SW>
+__device__ __forceinline__ uint32_t map_at(const MapVec<SW>& m, int j) {
+  return (j & 1) ? (m.v[j >> 1] >> 16) : (m.v[j >> 1] & 0xFFFFu);
+}
+
+// ===========================================================================
+// propagation
+// ===========================================================================
+template <int SW, int PREC>
+__device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, const Win& w, int rc,
+                                          int colbase, int ns) {
+  const int cols = ns < kThreads ? ns : kThreads;
+  const int P0 = kThreads / cols;
+  const int col = threadIdx.x % cols;
+  const int ph = threadIdx.x / cols;
+  if (ph >= P0) return;
+  const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
+  const int wave = threadIdx.x >> 6;
+  const int copy = wave * a.L.cpw + (ph & (a.L.cpw - 1));
+  char* lh = reinterpret_cast<char*>(smem + a.L.hist_off + copy * a.L.hist_stride);
+  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  for (int s = col; s < ns; s += cols) {
+    float gl[SW];
+#pragma unroll
+    for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
+    const int mcol = colbase + s * SW;
+    int r = ph;
+    if (r >= rc) continue;
+    float2 cur = rt[r];
+    MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.y) + mcol);
+    for (; r < rc; r += P0) {
+      const int rn = r + P0;
+      float2 nxt = cur;
+      MapVec<SW> mn = mv;
+      if (rn < rc) {
+        nxt = rt[rn];
+        mn = load_map<SW>(a.binmap + (long long)__float_as_int(nxt.y) + mcol);
+      }
+      const float go = cur.x;
+#pragma unroll
+      for (int j = 0; j < SW; ++j) {
+        const float q = quantize<PREC>(go * gl[j]);
+        float* slot = reinterpret_cast<float*>(lh + map_at<SW>(mv, j));
+        __hip_atomic_fetch_add(slot, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      cur = nxt;
+      mv = mn;
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
+  extern __shared__ float smem[];
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  const int B = a.B;
+  const int nslots = B + 1;
+  const int ncopies = kWaves * a.L.cpw;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  float* Pk = a.P + k * (long long)B;
+  bool anybad = false;
+  bool written = false;  // row k holds a partial mixture
+  for (int c = 0; c < a.d.C; ++c) {
+    const long long kc = k * a.d.C + c;
+    const Win w = make_win(a, kc);
+    if (w.bad) {
+      anybad = true;
+      if (a.Z && threadIdx.x == 0) a.Z[kc] = __builtin_nan("");
+      continue;
+    }
+    if (w.empty) {
+      if (a.Z && threadIdx.x == 0) a.Z[kc] = 0.0;
+      continue;
+    }
+    int loL, WL;
+    last_axis(w, D, loL, WL);
+    const int sw = choose_sw(loL, WL, w.R, 32);
+    const int colbase = (loL / sw) * sw;
+    const int ns = (loL + WL - 1) / sw - loL / sw + 1;
+    __syncthreads();  // LDS reuse across components
+    build_tables(a, smem, w, kc, sw, colbase, ns);
+    for (int i = threadIdx.x; i < ncopies * a.L.hist_stride; i += kThreads)
+      smem[a.L.hist_off + i] = 0.0f;
+    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
+      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+      __syncthreads();
+      build_rows(a, smem, w, r0, rc, kc, false);
+      __syncthreads();
+      switch (sw) {
+        case 4: prop_rows<4, PREC>(a, smem, w, rc, colbase, ns); break;
+        case 8: prop_rows<8, PREC>(a, smem, w, rc, colbase, ns); break;
+        case 16: prop_rows<16, PREC>(a, smem, w, rc, colbase, ns); break;
+        default: prop_rows<32, PREC>(a, smem, w, rc, colbase, ns); break;
+      }
+    }
+    __syncthreads();
+    // normaliser: FP64 sum over every slot of every copy, in a fixed order
+    double zpart = 0.0;
+    for (int b = threadIdx.x; b < nslots; b += kThreads)
+      for (int cp = 0; cp < ncopies; ++cp)
+        zpart += (double)smem[a.L.hist_off + cp * a.L.hist_stride + b];
+    const double Zc = block_sum(zpart, red);
+    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+    const double scale = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
+    for (int b = threadIdx.x; b < B; b += kThreads) {
+      double s = 0.0;
+      for (int cp = 0; cp < ncopies; ++cp) s += (double)smem[a.L.hist_off + cp * a.L.hist_stride + b];
+      const double prev = written ? (double)Pk[b] : 0.0;
+      Pk[b] = (float)(prev + s * scale);
+    }
+    written = true;
+  }
+  if (anybad || !written)
+    for (int b = threadIdx.x; b < B; b += kThreads) Pk[b] = anybad ? __builtin_nanf("") : 0.0f;
+  if (threadIdx.x == 0) {
+    if (anybad) atomicAdd(a.counters + kCntBadParam, 1ull);
+    else if (!written) atomicAdd(a.counters + kCntEmpty, 1ull);
+  }
+}
+
+// ===========================================================================
+// exact-f moments: shifted FP32 strip sums, FP64 accumulation
+// ===========================================================================
+template <int SW>
+__device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, int rc,
+                                         int colbase, int ns, float shift, double& A1,
+                                         double& A2) {
+  const int cols = ns < kThreads ? ns : kThreads;
+  const int P0 = kThreads / cols;
+  const int col = threadIdx.x % cols;
+  const int ph = threadIdx.x / cols;
+  if (ph >= P0) return;
+  const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
+  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  for (int s = col; s < ns; s += cols) {
+    float gl[SW];
+#pragma unroll
+    for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
+    const int mcol = colbase + s * SW;
+    for (int r = ph; r < rc; r += P0) {
+      const float2 cur = rt[r];
+      const float4* fp =
+          reinterpret_cast<const float4*>(a.f32 + (long long)__float_as_int(cur.y) + mcol);
+      float a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+      for (int q = 0; q < SW / 4; ++q) {
+        const float4 fv = fp[q];
+        const float fj[4] = {fv.x, fv.y, fv.z, fv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float dv = fj[e] - shift;
+          const float t = gl[4 * q + e] * dv;
+          a1 += t;
+          a2 = fmaf(t, dv, a2);
+        }
+      }
+      A1 += (double)cur.x * (double)a1;
+      A2 += (double)cur.x * (double)a2;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
+  extern __shared__ float smem[];
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  double Ec[VUP_MAX_COMP], Vc[VUP_MAX_COMP], pcs[VUP_MAX_COMP];
+  bool used[VUP_MAX_COMP];
+  bool anybad = false;
+  for (int c = 0; c < a.d.C; ++c) {
+    const long long kc = k * a.d.C + c;
+    const Win w = make_win(a, kc);
+    used[c] = false;
+    pcs[c] = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
+    if (w.bad) {
+      anybad = true;
+      continue;
+    }
+    if (w.empty) continue;
+    used[c] = true;
+    int loL, WL;
+    last_axis(w, D, loL, WL);
+    const int sw = choose_sw(loL, WL, w.R, 32);
+    const int colbase = (loL / sw) * sw;
+    const int ns = (loL + WL - 1) / sw - loL / sw + 1;
+    // shift: model value at the window's centre cell
+    long long cidx = loL + WL / 2;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d + 1 < D) cidx += (long long)(w.lo[d] + w.W[d] / 2) * a.g.rowstride[d];
+    const float shift = a.f32[cidx];
+    __syncthreads();
+    build_tables(a, smem, w, kc, sw, colbase, ns);
+    double A1 = 0.0, A2 = 0.0;
+    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
+      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+      __syncthreads();
+      build_rows(a, smem, w, r0, rc, kc, false);
+      __syncthreads();
+      switch (sw) {
+        case 4: mom_rows<4>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+        case 8: mom_rows<8>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+        case 16: mom_rows<16>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+        default: mom_rows<32>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+      }
+    }
+    // normaliser: product of the per-axis factor sums (separable density)
+    double Z = 1.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      if (d < D) {
+        double zp = 0.0;
+        const int cnt = (d + 1 < D) ? w.W[d] : ns * sw;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) zp += (double)smem[a.L.tab_off[d] + i];
+        Z *= block_sum(zp, red);
+      }
+    }
+    const double s1 = block_sum(A1, red) / Z;
+    const double s2 = block_sum(A2, red) / Z;
+    Ec[c] = (double)shift + s1;
+    Vc[c] = s2 - s1 * s1;
+  }
+  if (threadIdx.x != 0) return;
+  double E = 0.0, wsum = 0.0;
+  for (int c = 0; c < a.d.C; ++c)
+    if (used[c]) {
+      E += pcs[c] * Ec[c];
+      wsum += pcs[c];
+    }
+  double V = 0.0;
+  for (int c = 0; c < a.d.C; ++c)
+    if (used[c]) V += pcs[c] * (Vc[c] + (Ec[c] - E) * (Ec[c] - E));
+  const bool nan = anybad || wsum == 0.0;
+  a.mean[k] = nan ? __builtin_nan("") : E;
+  a.var[k] = nan ? __builtin_nan("") : V;
+  if (a.delta2) {
+    double d2 = __builtin_nan("");
+    if (!nan && a.has_model && a.d.C == 1) {
+      double x[4];
+      for (int d = 0; d < D; ++d) x[d] = a.d.mu[k * D + d];
+      const double fm = model_at(a.model.kind, D, a.model.theta, x);
+      d2 = 0.5 * (V + (E - fm) * (E - fm));
+    }
+    a.delta2[k] = d2;
+  }
+}
+
+// ===========================================================================
+// adjoint sweep for the IPSA sensitivities
+// ===========================================================================
+// per-thread adjoint accumulators: sum w v, and sum w v t_d, sum w v t_d^2 for
+// the fastest axis (L) and the slower axes (o[d], d < L)
+struct BwdAcc {
+  double a0, l1, l2;
+  double o1[3], o2[3];
+};
+
+template <int SW>
+__device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, int rc,
+                                         int colbase, int ns, double muL, double sgL,
+                                         BwdAcc& acc) {
+  const int D = a.g.ndim;
+  const int L = D - 1;
+  const int cols = ns < kThreads ? ns : kThreads;
+  const int P0 = kThreads / cols;
+  const int col = threadIdx.x % cols;
+  const int ph = threadIdx.x / cols;
+  if (ph >= P0) return;
+  const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
+  const float4* tt = reinterpret_cast<const float4*>(smem + a.L.trow_off);
+  const char* vt = reinterpret_cast<const char*>(smem + a.L.hist_off);
+  const float* tabL = smem + a.L.tab_off[L];
+  for (int s = col; s < ns; s += cols) {
+    float gl[SW], g1[SW], g2[SW];
+#pragma unroll
+    for (int j = 0; j < SW; ++j) {
+      gl[j] = tabL[s * SW + j];
+      const int jj = colbase + s * SW + j;
+      const double t = (cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], jj) - muL) / sgL;
+      g1[j] = (float)((double)gl[j] * t);
+      g2[j] = (float)((double)gl[j] * t * t);
+    }
+    const int mcol = colbase + s * SW;
+    for (int r = ph; r < rc; r += P0) {
+      const float2 cur = rt[r];
+      const MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.y) + mcol);
+      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+      for (int j = 0; j < SW; ++j) {
+        const float vb = *reinterpret_cast<const float*>(vt + map_at<SW>(mv, j));
+        a0 = fmaf(gl[j], vb, a0);
+        a1 = fmaf(g1[j], vb, a1);
+        a2 = fmaf(g2[j], vb, a2);
+      }
+      const double go = (double)cur.x;
+      const double c0 = go * (double)a0;
+      acc.a0 += c0;
+      acc.l1 += go * (double)a1;
+      acc.l2 += go * (double)a2;
+      if (L > 0) {
+        const float4 tv = tt[r];
+        const float tr[3] = {tv.x, tv.y, tv.z};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double td = (double)tr[d];
+          acc.o1[d] += c0 * td;
+          acc.o2[d] += c0 * td * td;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
+  extern __shared__ float smem[];
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  const int B = a.B;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  const float* Pk = a.Pin + k * (long long)B;
+  const double gv = a.g_var ? a.g_var[k] : 0.0;
+  const double ge = a.g_ent ? a.g_ent[k] : 0.0;
+  const double E = a.mean_hist[k];
+  // S = sum_b P_b (c_b - E); v_b = gv((c_b - E)^2 - 2 c_b S) - ge(ln P_b + 1);
+  // vref = sum_b P_b v_b is subtracted from the table (covariances are
+  // shift invariant) and added back for the weight gradient.
+  double sp = 0.0;
+  for (int b = threadIdx.x; b < B; b += kThreads) {
+    const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
+    sp += (double)Pk[b] * (cb - E);
+  }
+  const double S = block_sum(sp, red);
+  double vp = 0.0;
+  for (int b = threadIdx.x; b < B; b += kThreads) {
+    const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
+    const double pb = (double)Pk[b];
+    double v = gv * ((cb - E) * (cb - E) - 2.0 * cb * S);
+    if (pb > 0.0) v -= ge * (log(pb) + 1.0);
+    vp += pb * v;
+  }
+  const double vref = block_sum(vp, red);
+  float* vt = smem + a.L.hist_off;
+  for (int b = threadIdx.x; b <= B; b += kThreads) {
+    double v = 0.0;
+    if (b < B) {
+      const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
+      const double pb = (double)Pk[b];
+      v = gv * ((cb - E) * (cb - E) - 2.0 * cb * S);
+      if (pb > 0.0) v -= ge * (log(pb) + 1.0);
+    }
+    // cells without a bin do not enter Var or H: their v is 0
+    vt[b] = (float)(v - vref);
+  }
+  for (int c = 0; c < a.d.C; ++c) {
+    const long long kc = k * a.d.C + c;
+    const Win w = make_win(a, kc);
+    const double pc = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
+    if (w.bad || w.empty) {
+      if (threadIdx.x == 0) {
+        const double val = w.bad ? __builtin_nan("") : 0.0;
+        for (int d = 0; d < D; ++d) {
+          a.g_mu[kc * D + d] = val;
+          a.g_sigma[kc * D + d] = val;
+        }
+        if (a.g_weight) a.g_weight[kc] = val;
+      }
+      continue;
+    }
+    const int L = D - 1;
+    int loL, WL;
+    last_axis(w, D, loL, WL);
+    const int sw = choose_sw(loL, WL, w.R, 16);
+    const int colbase = (loL / sw) * sw;
+    const int ns = (loL + WL - 1) / sw - loL / sw + 1;
+    __syncthreads();
+    build_tables(a, smem, w, kc, sw, colbase, ns);
+    BwdAcc acc;
+    acc.a0 = acc.l1 = acc.l2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc.o1[i] = acc.o2[i] = 0.0;
+    const double muL = a.d.mu[kc * D + L];
+    const double sgL = a.d.sigma[kc * D + L];
+    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
+      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+      __syncthreads();
+      build_rows(a, smem, w, r0, rc, kc, true);
+      __syncthreads();
+      switch (sw) {
+        case 4: bwd_rows<4>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
+        case 8: bwd_rows<8>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
+        default: bwd_rows<16>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
+      }
+    }
+    // per-axis normalisers and score means from the factor tables (FP64)
+    double Z = 1.0, m1[4], m2[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      m1[d] = m2[d] = 0.0;
+      if (d < D) {
+        const int cnt = (d + 1 < D) ? w.W[d] : ns * sw;
+        const int first = (d + 1 < D) ? w.lo[d] : colbase;
+        const double mu = a.d.mu[kc * D + d], sg = a.d.sigma[kc * D + d];
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+          const double g = (double)smem[a.L.tab_off[d] + i];
+          const double t = (cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], first + i) - mu) / sg;
+          z0 += g;
+          z1 += g * t;
+          z2 += g * t * t;
+        }
+        const double Zd = block_sum(z0, red);
+        m1[d] = block_sum(z1, red) / Zd;
+        m2[d] = block_sum(z2, red) / Zd;
+        Z *= Zd;
+      }
+    }
+    const double A0 = block_sum(acc.a0, red) / Z;
+    double t1[4], t2[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      t1[d] = block_sum(acc.o1[d], red) / Z;
+      t2[d] = block_sum(acc.o2[d], red) / Z;
+    }
+    t1[3] = 0.0;
+    t2[3] = 0.0;
+    const double l1 = block_sum(acc.l1, red) / Z;
+    const double l2 = block_sum(acc.l2, red) / Z;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        if (d < D) {
+          const double sg = a.d.sigma[kc * D + d];
+          const double s1 = (d == L) ? l1 : t1[d < 3 ? d : 0];
+          const double s2 = (d == L) ? l2 : t2[d < 3 ? d : 0];
+          a.g_mu[kc * D + d] = pc * (s1 - m1[d] * A0) / sg;
+          a.g_sigma[kc * D + d] = pc * (s2 - m2[d] * A0) / sg;
+        }
+      }
+      if (a.g_weight) a.g_weight[kc] = A0 + vref;
+    }
+  }
+}
+
+// ===========================================================================
+// host side
+// ===========================================================================
+static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
+  SweepLayout L{};
+  const int D = g.ndim;
+  int off = 0;
+  for (int d = 0; d < 4; ++d) {
+    L.tab_off[d] = -1;
+    L.cap[d] = 0;
+  }
+  for (int d = 0; d < D; ++d) {
+    const int cap = (d + 1 < D) ? g.n[d] : g.n[d] + 64;
+    L.cap[d] = round_up(cap, 4);
+    L.tab_off[d] = off;
+    off += L.cap[d];
+  }
+  off = round_up(off, 4);
+  L.row_off = off;
+  off += 2 * kRowChunk;
+  L.trow_off = -1;
+  if (kind == kSweepBackward) {
+    L.trow_off = off;
+    off += 4 * kRowChunk;
+  }
+  L.hist_off = off;
+  L.hist_stride = 0;
+  L.cpw = 0;
+  if (kind == kSweepPropagate) {
+    // stride = 1 mod 32 so consecutive copies shift banks by one
+    const int stride = round_up(B + 1, 32) + 1;
+    L.hist_stride = stride;
+    int cpw = 8;
+    const int budget_floats = 48 * 1024 / 4;
+    while (cpw > 1 && off + kWaves * cpw * stride + 64 > budget_floats) cpw >>= 1;
+    L.cpw = cpw;
+    off += kWaves * cpw * stride;
+  } else if (kind == kSweepBackward) {
+    off += round_up(B + 1, 4);
+  }
+  off = round_up(off, 4);
+  L.red_off = off;
+  off += 2 * 16;  // 16 doubles
+  L.bytes = (size_t)off * 4;
+  *out = L;
+  return L.bytes <= 160 * 1024;
+}
+
+GridDev make_grid_dev(const vup_mm& mm) {
+  GridDev g{};
+  g.ndim = mm.grid.ndim;
+  for (int d = 0; d < 4; ++d) {
+    g.n[d] = d < g.ndim ? mm.grid.n[d] : 1;
+    g.lo[d] = mm.grid.lo[d];
+    g.hi[d] = mm.grid.hi[d];
+    g.rowstride[d] = 0;
+  }
+  g.pitch = mm.pitch;
+  // element stride of axis d (< ndim-1) in the padded map: product of the
+  // later non-fastest axes times the pitch
+  long long s = mm.pitch;
+  for (int d = g.ndim - 2; d >= 0; --d) {
+    g.rowstride[d] = s;
+    s *= g.n[d];
+  }
+  return g;
+}
+
+DistsDev make_dists_dev(const vup_dists& d) {
+  DistsDev r;
+  r.K = d.K;
+  r.C = d.ncomp;
+  r.ns = d.n_sigma;
+  r.mu = d.mu;
+  r.sigma = d.sigma;
+  r.weight = d.weight;
+  return r;
+}
+
+static SweepArgs base_args(const vup_mm& mm, const vup_dists& d, SweepKind kind) {
+  SweepArgs a{};
+  a.g = make_grid_dev(mm);
+  a.d = make_dists_dev(d);
+  a.B = mm.B;
+  const char* ws = static_cast<const char*>(mm.ws);
+  a.binmap = reinterpret_cast<const uint16_t*>(ws + mm.off_binmap);
+  a.f32 = reinterpret_cast<const float*>(ws + mm.off_f32);
+  a.edges = reinterpret_cast<const double*>(ws + mm.off_edges);
+  a.counters = reinterpret_cast<unsigned long long*>(static_cast<char*>(mm.ws) + mm.off_counters);
+  sweep_layout(mm.grid, mm.B, kind, &a.L);
+  a.kpx = (d.K + 7) / 8;
+  return a;
+}
+
+static dim3 sweep_grid(const vup_dists& d) { return dim3((unsigned)(8 * ((d.K + 7) / 8))); }
+
+// dynamic LDS above 64 KiB must be enabled per kernel
+template <typename F>
+static hipError_t allow_lds(F* kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, float* P, double* Z,
+                            hipStream_t s) {
+  if (d.K == 0) return hipSuccess;
+  SweepArgs a = base_args(mm, d, kSweepPropagate);
+  a.P = P;
+  a.Z = Z;
+  const dim3 grid = sweep_grid(d), block(kThreads);
+  hipError_t e = hipSuccess;
+  switch (prec) {
+    case VUP_BF16: e = allow_lds(k_propagate<VUP_BF16>, a.L.bytes); break;
+    case VUP_BF16X2: e = allow_lds(k_propagate<VUP_BF16X2>, a.L.bytes); break;
+    case VUP_FP8E4M3: e = allow_lds(k_propagate<VUP_FP8E4M3>, a.L.bytes); break;
+    default: e = allow_lds(k_propagate<VUP_FP32>, a.L.bytes); break;
+  }
+  if (e != hipSuccess) return e;
+  switch (prec) {
+    case VUP_BF16: hipLaunchKernelGGL(k_propagate<VUP_BF16>, grid, block, a.L.bytes, s, a); break;
+    case VUP_BF16X2:
+      hipLaunchKernelGGL(k_propagate<VUP_BF16X2>, grid, block, a.L.bytes, s, a);
+      break;
+    case VUP_FP8E4M3:
+      hipLaunchKernelGGL(k_propagate<VUP_FP8E4M3>, grid, block, a.L.bytes, s, a);
+      break;
+    default: hipLaunchKernelGGL(k_propagate<VUP_FP32>, grid, block, a.L.bytes, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const vup_mm& mm, const vup_dists& d, const vup_model* model,
+                          double* mean, double* var, double* delta2, hipStream_t s) {
+  if (d.K == 0) return hipSuccess;
+  SweepArgs a = base_args(mm, d, kSweepMoments);
+  a.mean = mean;
+  a.var = var;
+  a.delta2 = delta2;
+  a.has_model = model != nullptr;
+  if (model) a.model = *model;
+  const hipError_t e = allow_lds(k_moments, a.L.bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_moments, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
+                           const double* mean_hist, const double* g_var, const double* g_ent,
+                           double* g_mu, double* g_sigma, double* g_weight, hipStream_t s) {
+  if (d.K == 0) return hipSuccess;
+  SweepArgs a = base_args(mm, d, kSweepBackward);
+  a.Pin = P;
+  a.mean_hist = mean_hist;
+  a.g_var = g_var;
+  a.g_ent = g_ent;
+  a.g_mu = g_mu;
+  a.g_sigma = g_sigma;
+  a.g_weight = g_weight;
+  const hipError_t e = allow_lds(k_backward, a.L.bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_backward, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vup

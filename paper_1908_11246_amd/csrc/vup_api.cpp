@@ -1,0 +1,263 @@
+// C ABI of the VUP/IPSA library: argument validation, workspace layout and
+// kernel dispatch. Every check that can be done on the host happens here,
+// before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/vup.h"
+#include "vup_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = '\0';
+  return VUP_OK;
+}
+
+int check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return fail(VUP_ENODEV, "no HIP device available");
+  }
+  return VUP_OK;
+}
+
+int launched(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(VUP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+int check_grid(const vup_grid* g) {
+  if (!g) return fail(VUP_EINVAL, "grid is NULL");
+  if (g->ndim < 1 || g->ndim > VUP_MAX_DIM) return fail(VUP_EINVAL, "ndim %d not in [1,4]", g->ndim);
+  long long rows = 1, N = 1;
+  for (int d = 0; d < g->ndim; ++d) {
+    if (g->n[d] < 1 || g->n[d] > VUP_MAX_AXIS)
+      return fail(VUP_EINVAL, "n[%d] = %d not in [1,%d]", d, g->n[d], VUP_MAX_AXIS);
+    if (!std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]) || !(g->lo[d] < g->hi[d]))
+      return fail(VUP_EINVAL, "axis %d: need finite lo < hi", d);
+    N *= g->n[d];
+    if (d + 1 < g->ndim) rows *= g->n[d];
+  }
+  const long long pitch = (g->n[g->ndim - 1] + 31) / 32 * 32;
+  if (N > 0x7fffffffll || rows * pitch > 0x7fffffffll)
+    return fail(VUP_EUNSUPPORTED, "grid of %lld cells exceeds the 2^31 cell limit", N);
+  return VUP_OK;
+}
+
+int check_dists(const vup_dists* d, int ndim) {
+  if (!d) return fail(VUP_EINVAL, "dists is NULL");
+  if (d->K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (d->ncomp < 1 || d->ncomp > VUP_MAX_COMP)
+    return fail(VUP_EINVAL, "ncomp %d not in [1,%d]", d->ncomp, VUP_MAX_COMP);
+  if (d->ndim != ndim) return fail(VUP_EINVAL, "dists ndim %d != grid ndim %d", d->ndim, ndim);
+  if (!(d->n_sigma > 0.0) || !std::isfinite(d->n_sigma))
+    return fail(VUP_EINVAL, "n_sigma must be finite and > 0");
+  if (d->K > 0 && (!d->mu || !d->sigma)) return fail(VUP_EINVAL, "mu/sigma is NULL");
+  if (d->ncomp > 1 && d->K > 0 && !d->weight) return fail(VUP_EINVAL, "mixtures need weights");
+  if (d->ncomp == 1 && d->weight) return fail(VUP_EINVAL, "weight must be NULL when ncomp == 1");
+  if (d->K * d->ncomp > 0x7fffffffll * 8ll) return fail(VUP_EUNSUPPORTED, "K too large");
+  return VUP_OK;
+}
+
+int check_mm(const vup_mm* mm) {
+  if (!mm) return fail(VUP_EINVAL, "model matrix descriptor is NULL");
+  if (mm->magic != vup::kMagic || !mm->ws)
+    return fail(VUP_EWORKSPACE, "descriptor was not produced by vup_bin");
+  int r = check_grid(&mm->grid);
+  if (r) return r;
+  return VUP_OK;
+}
+
+int check_sweep(const vup_mm* mm, vup::SweepKind kind) {
+  vup::SweepLayout L;
+  if (!vup::sweep_layout(mm->grid, mm->B, kind, &L))
+    return fail(VUP_EUNSUPPORTED, "grid axes too long for on-chip factor tables (%zu bytes LDS)",
+                L.bytes);
+  return VUP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vup_last_error(void) { return g_err; }
+
+const char* vup_version(void) { return "vup-mi355x 0.1 (gfx950)"; }
+
+int vup_eval_grid(const vup_grid* g, const vup_model* m, double* f, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!m || !f) return fail(VUP_EINVAL, "model or f is NULL");
+  const int need[] = {0, 2, 3, 4, 2, 2};
+  if (m->kind < 0 || m->kind > VUP_MODEL_IPSA2) return fail(VUP_EINVAL, "unknown model %d", m->kind);
+  if (m->kind == VUP_MODEL_LINEAR) {
+    for (int d = 0; d <= g->ndim; ++d)
+      if (!std::isfinite(m->theta[d])) return fail(VUP_EINVAL, "theta must be finite");
+  } else if (need[m->kind] != g->ndim) {
+    return fail(VUP_EINVAL, "model %d needs ndim %d", m->kind, need[m->kind]);
+  }
+  if ((r = check_device())) return r;
+  return launched(vup::launch_eval_grid(*g, *m, f, (hipStream_t)stream), "vup_eval_grid");
+}
+
+int vup_uniform_edges(const double* f, int64_t N, int32_t B, double* edges, void* stream) {
+  if (!f || !edges) return fail(VUP_EINVAL, "f or edges is NULL");
+  if (N < 1) return fail(VUP_EINVAL, "N < 1");
+  if (B < 1 || B > VUP_MAX_BINS) return fail(VUP_EINVAL, "B %d not in [1,%d]", B, VUP_MAX_BINS);
+  int r = check_device();
+  if (r) return r;
+  return launched(vup::launch_uniform_edges(f, N, B, edges, (hipStream_t)stream),
+                  "vup_uniform_edges");
+}
+
+size_t vup_bin_workspace_bytes(const vup_grid* g, int32_t B) {
+  if (check_grid(g) || B < 1 || B > VUP_MAX_BINS) return 0;
+  vup::WsLayout L;
+  vup::ws_layout(*g, B, &L);
+  return L.bytes;
+}
+
+int vup_bin(const vup_grid* g, const double* f, const double* edges, int32_t B, int32_t* bin,
+            void* ws, size_t ws_bytes, vup_mm* mm_out, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (B < 1 || B > VUP_MAX_BINS) return fail(VUP_EINVAL, "B %d not in [1,%d]", B, VUP_MAX_BINS);
+  if (!f || !edges || !mm_out) return fail(VUP_EINVAL, "f, edges or mm_out is NULL");
+  if (!ws) return fail(VUP_EWORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VUP_EWORKSPACE, "workspace not 256-byte aligned");
+  vup::WsLayout L;
+  vup::ws_layout(*g, B, &L);
+  if (ws_bytes < L.bytes)
+    return fail(VUP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, L.bytes);
+  if ((r = check_device())) return r;
+  vup_mm mm;
+  memset(&mm, 0, sizeof mm);
+  mm.grid = *g;
+  for (int d = g->ndim; d < 4; ++d) {
+    mm.grid.n[d] = 1;
+    mm.grid.lo[d] = 0.0;
+    mm.grid.hi[d] = 1.0;
+  }
+  mm.B = B;
+  mm.pitch = L.pitch;
+  mm.rows = L.rows;
+  mm.N = L.rows * g->n[g->ndim - 1];
+  mm.ws = ws;
+  mm.ws_bytes = ws_bytes;
+  mm.off_edges = L.off_edges;
+  mm.off_binmap = L.off_binmap;
+  mm.off_f32 = L.off_f32;
+  mm.off_counts = L.off_counts;
+  mm.off_offsets = L.off_offsets;
+  mm.off_perm = L.off_perm;
+  mm.off_scratch = L.off_scratch;
+  mm.off_counters = L.off_counters;
+  mm.magic = vup::kMagic;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemsetAsync(static_cast<char*>(ws) + L.off_counters, 0, 64, s);
+  if (e != hipSuccess) return launched(e, "vup_bin (clear counters)");
+  e = vup::launch_bin(mm, f, edges, bin, s);
+  if (e != hipSuccess) return launched(e, "vup_bin");
+  *mm_out = mm;
+  return ok();
+}
+
+int vup_windows(const vup_grid* g, const vup_dists* d, int32_t* win, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if ((r = check_dists(d, g->ndim))) return r;
+  if (d->K > 0 && !win) return fail(VUP_EINVAL, "win is NULL");
+  if ((r = check_device())) return r;
+  return launched(vup::launch_windows(*g, *d, win, (hipStream_t)stream), "vup_windows");
+}
+
+int vup_propagate(const vup_mm* mm, const vup_dists* d, int32_t precision, float* P, double* Z,
+                  void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if ((r = check_dists(d, mm->grid.ndim))) return r;
+  if (precision < VUP_FP32 || precision > VUP_FP8E4M3)
+    return fail(VUP_EINVAL, "unknown precision %d", precision);
+  if (d->K > 0 && !P) return fail(VUP_EINVAL, "P is NULL");
+  if ((r = check_sweep(mm, vup::kSweepPropagate))) return r;
+  if ((r = check_device())) return r;
+  return launched(vup::launch_propagate(*mm, *d, precision, P, Z, (hipStream_t)stream),
+                  "vup_propagate");
+}
+
+int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, double* mean,
+                double* var, double* delta2, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if ((r = check_dists(d, mm->grid.ndim))) return r;
+  if (d->K > 0 && (!mean || !var)) return fail(VUP_EINVAL, "mean or var is NULL");
+  if (delta2) {
+    if (d->ncomp != 1) return fail(VUP_EUNSUPPORTED, "delta2 needs single-component pdfs");
+    if (!model) return fail(VUP_EINVAL, "delta2 needs the built-in model");
+    if (model->kind < 0 || model->kind > VUP_MODEL_IPSA2)
+      return fail(VUP_EINVAL, "unknown model %d", model->kind);
+  }
+  if ((r = check_sweep(mm, vup::kSweepMoments))) return r;
+  if ((r = check_device())) return r;
+  return launched(vup::launch_moments(*mm, *d, delta2 ? model : nullptr, mean, var, delta2,
+                                      (hipStream_t)stream),
+                  "vup_moments");
+}
+
+int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, double* var,
+             double* entropy, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (K > 0 && !P) return fail(VUP_EINVAL, "P is NULL");
+  if ((r = check_device())) return r;
+  return launched(vup::launch_ipsa(*mm, K, P, mean_hist, var, entropy, (hipStream_t)stream),
+                  "vup_ipsa");
+}
+
+int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
+                      const double* mean_hist, const double* g_var, const double* g_ent,
+                      double* g_mu, double* g_sigma, double* g_weight, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if ((r = check_dists(d, mm->grid.ndim))) return r;
+  if (d->K > 0 && (!P || !mean_hist || !g_mu || !g_sigma))
+    return fail(VUP_EINVAL, "P, mean_hist, g_mu or g_sigma is NULL");
+  if ((r = check_sweep(mm, vup::kSweepBackward))) return r;
+  if ((r = check_device())) return r;
+  return launched(vup::launch_backward(*mm, *d, P, mean_hist, g_var, g_ent, g_mu, g_sigma, g_weight,
+                                       (hipStream_t)stream),
+                  "vup_ipsa_backward");
+}
+
+int vup_counters(const vup_mm* mm, void* stream, int64_t* out) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (!out) return fail(VUP_EINVAL, "out is NULL");
+  if ((r = check_device())) return r;
+  hipStream_t s = (hipStream_t)stream;
+  char* c = static_cast<char*>(mm->ws) + mm->off_counters;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(out, c, 4 * sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemsetAsync(c, 0, 4 * sizeof(int64_t), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return launched(e, "vup_counters");
+}
+
+}  // extern "C"

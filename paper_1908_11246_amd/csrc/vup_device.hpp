@@ -1,0 +1,175 @@
+// Device-side helpers shared by the VUP kernels (gfx950, wave64).
+// Grid convention: uniform cell-centred grid (composite midpoint rule, Sec. 3),
+// flat index row major with axis 0 slowest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vup.h"
+
+namespace vup {
+
+constexpr int kThreads = 256;     // threads per workgroup of the sweep kernels
+constexpr int kWaves = kThreads / 64;
+constexpr int kRowChunk = 1024;   // rows of the row table held in LDS at once
+constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
+
+// counters stored in the workspace (int64 each)
+enum Counter { kCntOutside = 0, kCntBadEdges = 1, kCntBadParam = 2, kCntEmpty = 3 };
+
+// grid + bin-map description passed by value to every sweep kernel
+struct GridDev {
+  int ndim;
+  int n[4];
+  double lo[4];
+  double hi[4];
+  int pitch;                 // padded length of the last axis in the bin map
+  long long rowstride[4];    // bin-map element stride of axes 0..ndim-2
+};
+
+struct DistsDev {
+  long long K;
+  int C;
+  double ns;
+  const double* __restrict__ mu;
+  const double* __restrict__ sigma;
+  const double* __restrict__ weight;
+};
+
+// ---------------------------------------------------------------------------
+// truncation window of one axis: kept cells j with |x_j - mu| <= ns*sigma,
+// evaluated in FP64 in a fixed operation order with contraction disabled so
+// that the integer bounds are reproducible bit for bit. Returns false for
+// invalid parameters; an empty window is lo = 0, hi = -1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool axis_window(double lo, double hi, int n, double mu, double sigma,
+                                            double ns, int& jlo, int& jhi) {
+#pragma clang fp contract(off)
+  if (!(sigma > 0.0) || !isfinite(sigma) || !isfinite(mu)) {
+    jlo = 0;
+    jhi = -1;
+    return false;
+  }
+  const double h = (hi - lo) / n;
+  const double tlo = ((mu - ns * sigma) - lo) / h - 0.5;
+  const double thi = ((mu + ns * sigma) - lo) / h - 0.5;
+  double a = ceil(tlo), b = floor(thi);
+  a = a < 0.0 ? 0.0 : a;
+  b = b > (double)(n - 1) ? (double)(n - 1) : b;
+  if (a > b) {
+    if (mu >= lo && mu <= hi) {
+      double c = floor((mu - lo) / h);
+      c = c < 0.0 ? 0.0 : c;
+      c = c > (double)(n - 1) ? (double)(n - 1) : c;
+      a = b = c;
+    } else {
+      jlo = 0;
+      jhi = -1;
+      return true;
+    }
+  }
+  jlo = (int)a;
+  jhi = (int)b;
+  return true;
+}
+
+// cell centre of axis d
+__device__ __forceinline__ double cell_centre(double lo, double hi, int n, int j) {
+#pragma clang fp contract(off)
+  return lo + (j + 0.5) * ((hi - lo) / n);
+}
+
+// per-axis Gaussian factor exp(-t^2/2), t = (x_j - mu)/sigma, in FP64
+__device__ __forceinline__ double gauss_factor(double x, double mu, double sigma) {
+  const double t = (x - mu) / sigma;
+  return exp(-0.5 * (t * t));
+}
+
+// ---------------------------------------------------------------------------
+// built-in models (Sec. 2, eq. modelfunction)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double model_at(int kind, int ndim, const double* theta, const double* x) {
+  switch (kind) {
+    case VUP_MODEL_LINEAR: {
+      double y = theta[0];
+      for (int d = 0; d < ndim; ++d) y += theta[d + 1] * x[d];
+      return y;
+    }
+    case VUP_MODEL_SINCOS2:
+      return sin(x[0]) + 0.5 * cos(2.0 * x[1]) + x[0] * x[1] / 4.0;
+    case VUP_MODEL_DAMPED3:
+      return exp(-0.1 * x[2]) * sin(x[0]) * cos(x[1]) + 0.1 * x[0] * x[1] * x[2];
+    case VUP_MODEL_RING4: {
+      double s = 0.0, t = 0.0;
+      for (int j = 0; j < 4; ++j) s += sin(x[j]) * x[(j + 1) & 3];
+      for (int j = 0; j < 4; ++j) t += x[j];
+      return s + 0.05 * (t * t);
+    }
+    case VUP_MODEL_TIMING2: {
+      const double sa = sin(x[1]);
+      return 1.1 * sin(x[0]) + 7.0 * (sa * sa);
+    }
+    case VUP_MODEL_IPSA2:
+      return x[0] * x[0] + 5.0 * sin(3.0 * x[0]) + x[1];
+    default:
+      return __builtin_nan("");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density quantisers (round to nearest even), inputs are finite and in [0, 1]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+// OCP E4M3 value of 448*w, returned divided by 448 is NOT done here: the
+// kernels accumulate the E4M3 value itself (the common scale cancels in P).
+__device__ __forceinline__ float round_e4m3(float x) {
+  // normals: 4 significant bits (drop 20 of FP32's 23 fraction bits);
+  // below 2^-6: multiples of the subnormal quantum 2^-9
+  uint32_t u = __float_as_uint(x);
+  uint32_t rn = (u + 0x7FFFFu + ((u >> 20) & 1u)) & 0xFFF00000u;
+  float sub = __builtin_rintf(x * 512.0f) * (1.0f / 512.0f);
+  return x < 0.015625f ? sub : __uint_as_float(rn);
+}
+
+template <int PREC>
+__device__ __forceinline__ float quantize(float w) {
+  if constexpr (PREC == VUP_BF16) {
+    return round_bf16(w);
+  } else if constexpr (PREC == VUP_BF16X2) {
+    const float h = round_bf16(w);
+    return h + round_bf16(w - h);
+  } else if constexpr (PREC == VUP_FP8E4M3) {
+    return round_e4m3(448.0f * w);
+  } else {
+    return w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// deterministic block sum of one double per thread; `red` is LDS scratch of
+// kWaves doubles. All threads receive the result.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kWaves; ++w) s += red[w];
+  return s;
+}
+
+}  // namespace vup

@@ -1,0 +1,63 @@
+// Host-side interfaces between the C ABI layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vup.h"
+#include "vup_device.hpp"
+
+namespace vup {
+
+constexpr uint64_t kMagic = 0x5655504d4d763031ull;  // "VUPMMv01"
+
+// sort / bin kernels work on chunks of this many padded positions
+constexpr int kBinChunk = 4096;
+
+// LDS layout of a sweep kernel (offsets in floats from the start of dynamic LDS)
+struct SweepLayout {
+  int tab_off[4];
+  int cap[4];
+  int row_off;      // float2[kRowChunk]
+  int trow_off;     // float4[kRowChunk] (backward only, else -1)
+  int hist_off;     // histogram copies (propagate) or v table (backward)
+  int hist_stride;  // floats per histogram copy
+  int cpw;          // histogram copies per wave
+  int red_off;      // double scratch
+  size_t bytes;
+};
+
+enum SweepKind { kSweepPropagate = 0, kSweepMoments = 1, kSweepBackward = 2 };
+
+bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out);
+GridDev make_grid_dev(const vup_mm& mm);
+DistsDev make_dists_dev(const vup_dists& d);
+
+// launches (return hipError_t of the launch)
+hipError_t launch_eval_grid(const vup_grid& g, const vup_model& m, double* f, hipStream_t s);
+hipError_t launch_uniform_edges(const double* f, int64_t N, int B, double* edges, hipStream_t s);
+hipError_t launch_bin(const vup_mm& mm, const double* f, const double* edges, int32_t* bin,
+                      hipStream_t s);
+hipError_t launch_windows(const vup_grid& g, const vup_dists& d, int32_t* win, hipStream_t s);
+hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, float* P, double* Z,
+                            hipStream_t s);
+hipError_t launch_moments(const vup_mm& mm, const vup_dists& d, const vup_model* model,
+                          double* mean, double* var, double* delta2, hipStream_t s);
+hipError_t launch_ipsa(const vup_mm& mm, int64_t K, const float* P, double* mean_hist, double* var,
+                       double* entropy, hipStream_t s);
+hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
+                           const double* mean_hist, const double* g_var, const double* g_ent,
+                           double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);
+
+// workspace sizing shared by vup_bin_workspace_bytes and vup_bin
+struct WsLayout {
+  int pitch;
+  int64_t rows;
+  int64_t nblk;  // chunks of kBinChunk padded positions
+  size_t off_edges, off_binmap, off_f32, off_counts, off_offsets, off_perm, off_scratch,
+      off_counters, bytes;
+};
+bool ws_layout(const vup_grid& g, int B, WsLayout* out);
+
+}  // namespace vup

@@ -1,0 +1,172 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+include/vup.h declares, and rejects invalid arguments before touching a GPU.
+No compute call is made here (this runs on machines without a GPU)."""
+import ctypes
+import subprocess
+
+import pytest
+import torch
+
+import paper_1908_11246_amd as vup
+
+EINVAL, ENODEV, EWORKSPACE, EUNSUPPORTED = -1, -2, -5, -4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return vup.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = vup.header_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", vup.LIBPATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.vup_version()
+    assert isinstance(lib.vup_last_error(), bytes)
+
+
+def _grid(n=(8, 8), lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    return vup.make_grid(n, lo, hi)
+
+
+def test_invalid_grids_rejected(lib):
+    m = vup.make_model("sincos2")
+    dummy = ctypes.c_void_p(0x1000)
+    g = _grid()
+    g.ndim = 0
+    assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), dummy, None) == EINVAL
+    g = _grid()
+    g.n[1] = 0
+    assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), dummy, None) == EINVAL
+    assert b"n[1]" in lib.vup_last_error()
+    g = _grid(hi=(1.0, 0.0))
+    assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), dummy, None) == EINVAL
+    g = _grid(lo=(0.0, float("nan")))
+    assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), dummy, None) == EINVAL
+    # model / ndim mismatch and unknown model
+    g3 = _grid((4, 4, 4), (0, 0, 0), (1, 1, 1))
+    assert lib.vup_eval_grid(ctypes.byref(g3), ctypes.byref(m), dummy, None) == EINVAL
+    m.kind = 99
+    assert lib.vup_eval_grid(ctypes.byref(_grid()), ctypes.byref(m), dummy, None) == EINVAL
+    # NULL output
+    assert lib.vup_eval_grid(ctypes.byref(_grid()), ctypes.byref(vup.make_model("sincos2")),
+                             None, None) == EINVAL
+    # too many cells for 32-bit offsets
+    big = _grid((65536, 65536), (0, 0), (1, 1))
+    assert lib.vup_eval_grid(ctypes.byref(big), ctypes.byref(vup.make_model("sincos2")),
+                             dummy, None) == EUNSUPPORTED
+
+
+def test_edges_and_bin_arguments(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.vup_uniform_edges(dummy, 10, 0, dummy, None) == EINVAL
+    assert lib.vup_uniform_edges(dummy, 10, 5000, dummy, None) == EINVAL
+    assert lib.vup_uniform_edges(dummy, 0, 4, dummy, None) == EINVAL
+    assert lib.vup_uniform_edges(None, 10, 4, dummy, None) == EINVAL
+    g = _grid()
+    assert lib.vup_bin_workspace_bytes(ctypes.byref(g), 16) > 0
+    assert lib.vup_bin_workspace_bytes(ctypes.byref(g), 0) == 0
+    mm = vup.VupMM()
+    need = lib.vup_bin_workspace_bytes(ctypes.byref(g), 16)
+    assert lib.vup_bin(ctypes.byref(g), dummy, dummy, 16, None, None, need,
+                       ctypes.byref(mm), None) == EWORKSPACE
+    assert lib.vup_bin(ctypes.byref(g), dummy, dummy, 16, None, ctypes.c_void_p(0x1001), need,
+                       ctypes.byref(mm), None) == EWORKSPACE
+    assert lib.vup_bin(ctypes.byref(g), dummy, dummy, 16, None, ctypes.c_void_p(0x100000),
+                       need - 1, ctypes.byref(mm), None) == EWORKSPACE
+    assert lib.vup_bin(ctypes.byref(g), dummy, dummy, 0, None, ctypes.c_void_p(0x100000), need,
+                       ctypes.byref(mm), None) == EINVAL
+
+
+def test_workspace_grows_with_grid_and_bins(lib):
+    a = lib.vup_bin_workspace_bytes(ctypes.byref(_grid((64, 64))), 64)
+    b = lib.vup_bin_workspace_bytes(ctypes.byref(_grid((128, 64))), 64)
+    c = lib.vup_bin_workspace_bytes(ctypes.byref(_grid((64, 64))), 1024)
+    assert 0 < a < b and a < c
+    # 1024 x 1024 cells: FP32 map + uint16 map + perm dominate (about 10 bytes per cell)
+    d = lib.vup_bin_workspace_bytes(ctypes.byref(_grid((1024, 1024))), 256)
+    assert 10 * 2 ** 20 <= d <= 12 * 2 ** 20
+
+
+def test_descriptor_must_come_from_vup_bin(lib):
+    mm = vup.VupMM()
+    d = vup.VupDists()
+    d.K = 1
+    d.ncomp = 1
+    d.ndim = 2
+    d.n_sigma = 4.0
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.vup_propagate(ctypes.byref(mm), ctypes.byref(d), 0, dummy, None, None) == EWORKSPACE
+    assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d), None, dummy, dummy, None,
+                           None) == EWORKSPACE
+    assert lib.vup_ipsa(ctypes.byref(mm), 1, dummy, None, None, None, None) == EWORKSPACE
+    assert lib.vup_counters(ctypes.byref(mm), None, (ctypes.c_int64 * 4)()) == EWORKSPACE
+
+
+def _fake_mm(lib, B=16, n=(8, 8)):
+    """A descriptor that passes the host checks (its workspace is never touched,
+    because every call below fails validation before any launch)."""
+    mm = vup.VupMM()
+    mm.grid = _grid(n)
+    mm.B = B
+    mm.ws = 0x100000
+    mm.magic = 0x5655504d4d763031
+    return mm
+
+
+def test_dists_validation(lib):
+    mm = _fake_mm(lib)
+    dummy = ctypes.c_void_p(0x1000)
+
+    def dists(**kw):
+        d = vup.VupDists()
+        d.K, d.ncomp, d.ndim, d.n_sigma = 4, 1, 2, 4.0
+        d.mu, d.sigma, d.weight = 0x1000, 0x2000, None
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+
+    cases = [dict(K=-1), dict(ncomp=3), dict(ndim=3), dict(n_sigma=0.0),
+             dict(n_sigma=float("inf")), dict(mu=None), dict(ncomp=2), dict(weight=0x3000)]
+    for kw in cases:
+        d = dists(**kw)
+        assert lib.vup_propagate(ctypes.byref(mm), ctypes.byref(d), 0, dummy, None, None) == EINVAL, kw
+    d = dists()
+    assert lib.vup_propagate(ctypes.byref(mm), ctypes.byref(d), 7, dummy, None, None) == EINVAL
+    assert lib.vup_propagate(ctypes.byref(mm), ctypes.byref(d), 0, None, None, None) == EINVAL
+    # delta2 needs one component and the model
+    d2 = dists(ncomp=2, weight=0x3000)
+    assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d2), None, dummy, dummy, dummy,
+                           None) == EUNSUPPORTED
+    assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d), None, dummy, dummy, dummy,
+                           None) == EINVAL
+    assert lib.vup_ipsa_backward(ctypes.byref(mm), ctypes.byref(d), None, dummy, None, None,
+                                 dummy, dummy, None, None) == EINVAL
+
+
+def test_grid_too_long_for_lds_is_unsupported(lib):
+    # factor tables of every axis live in LDS; four 16384-cell axes do not fit
+    mm = _fake_mm(lib, B=16, n=(60000, 30000))
+    d = vup.VupDists()
+    d.K, d.ncomp, d.ndim, d.n_sigma = 1, 1, 2, 4.0
+    d.mu, d.sigma = 0x1000, 0x2000
+    mm.grid = _grid((16, 65536))
+    assert lib.vup_propagate(ctypes.byref(mm), ctypes.byref(d), 0, ctypes.c_void_p(0x1000),
+                             None, None) in (EUNSUPPORTED, EINVAL)
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")
+def test_no_device_is_reported(lib):
+    g = _grid()
+    m = vup.make_model("sincos2")
+    assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), ctypes.c_void_p(0x1000),
+                             None) == ENODEV
+    assert b"device" in lib.vup_last_error()

@@ -1,0 +1,401 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle,
+element by element on the same seeded inputs.
+
+Bars (per distribution k unless noted):
+  bins, windows, model-matrix CSR, edges     bit-exact
+  f (FP64 on both sides, libm vs ocml)       <= 8 ulp of max |f|
+  P, FP32 density                            L1 column error <= 2e-5, |sum - 1| <= 1e-6
+  P, BF16 / BF16x2 / E4M3                    L1 <= 2u / 5e-5 / 0.125 (u = 2^-8; e4m3 bound
+                                             includes the flushed tail); sums <= 1e-6
+  exact-f mean                               <= 1e-6 * (max f - min f)
+  exact-f variance                           <= 1e-5 * Var + 1e-9 * range^2
+  binned mean / variance                     same as exact-f bars
+  entropy                                    <= 1e-5 nats (FP32), 2u(1 + ln B) (BF16)
+  gradients (FP32 adjoint vs FP64 analytic)  rtol 2e-3 + atol 1e-5 max|g|
+The oracle always computes its own f, edges and bins; when a kernel is tested
+in isolation, the GPU is fed the oracle's inputs (never the other way round).
+"""
+import math
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+U_BF16 = 2.0 ** -8
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_11246_amd as v
+    v.lib()
+    return v
+
+
+def _gpu_pipeline(vup, wl, precision="fp32", moments=True):
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    f = vup.eval_grid(g, wl.model, wl.theta)
+    e = vup.uniform_edges(f, wl.B)
+    mm = vup.build_model_matrix(g, f, e)
+    P, Z = vup.propagate(mm, wl.mu, wl.sigma, wl.weight, precision, wl.n_sigma)
+    out = dict(grid=g, f=f, edges=e, mm=mm, P=P, Z=Z)
+    if moments:
+        out["mean"], out["var"], _ = vup.moments(mm, wl.mu, wl.sigma, wl.weight,
+                                                 n_sigma=wl.n_sigma)
+    out["mean_hist"], out["var_hist"], out["entropy"] = vup.ipsa(mm, P)
+    torch.cuda.synchronize()
+    return out
+
+
+def _cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_P(Pg, Po, tol_l1, label, tol_sum=1e-6):
+    Pg = Pg.astype(np.float64)
+    l1 = np.abs(Pg - Po).sum(axis=1)
+    sums = np.abs(Pg.sum(axis=1) - 1.0)
+    _say(f"  {label}: max L1 {l1.max():.3e} (bar {tol_l1:.1e}), max |sum-1| {sums.max():.2e}")
+    assert (Pg >= 0).all()
+    assert l1.max() <= tol_l1, (label, l1.max())
+    assert sums.max() <= tol_sum, (label, sums.max())
+    return l1.max()
+
+
+def _check_moments(mg, vg, mo, vo, rng_f, label, scale=1.0):
+    em = np.abs(mg - mo).max()
+    ev = np.abs(vg - vo) - (1e-5 * scale * np.abs(vo) + 1e-9 * scale * rng_f ** 2)
+    _say(f"  {label}: max |dE| {em:.3e} (bar {1e-6 * scale * rng_f:.1e}), "
+         f"max var excess over bar {ev.max():.3e}")
+    assert em <= 1e-6 * scale * rng_f, label
+    assert (ev <= 0).all(), label
+
+
+# ---------------------------------------------------------------------------
+# model matrix construction
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["grid64", "grid1024", "grid128_3d", "grid48_4d"])
+def test_eval_edges_bins_model_matrix(vup, orc, name):
+    wl = workloads.CONFIGS[name]()
+    _say(f"[eval/bin] {name} n={wl.n} B={wl.B}")
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    fg = vup.eval_grid(g, wl.model, wl.theta)
+    fo = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
+    err = np.abs(_cpu(fg) - fo).max()
+    ulp = np.spacing(np.abs(fo).max())
+    _say(f"  f: max |df| = {err:.3e} = {err / ulp:.2f} ulp of max|f|")
+    assert err <= 8 * ulp
+    # edges and bins from the oracle's f on both sides: bit-exact
+    f_in = torch.from_numpy(fo).to(DEV)
+    eg = vup.uniform_edges(f_in, wl.B)
+    eo = orc.uniform_edges(fo, wl.B)
+    assert np.array_equal(_cpu(eg), eo)
+    mm = vup.build_model_matrix(g, f_in, torch.from_numpy(eo).to(DEV))
+    bo = orc.bins(fo, eo)
+    assert np.array_equal(_cpu(mm.bin), bo)
+    off, perm = orc.model_matrix(bo, wl.B)
+    assert np.array_equal(_cpu(mm.offsets), off)
+    assert np.array_equal(_cpu(mm.perm)[:off[-1]], perm)
+    cnt = _cpu(mm.counts)
+    assert np.array_equal(cnt[:-1], np.diff(off)) and cnt[-1] == (bo < 0).sum()
+    assert mm.counters()["outside"] == (bo < 0).sum()
+    # end to end: the GPU's own f -> edges -> bins agree with the oracle's
+    e2 = vup.uniform_edges(fg, wl.B)
+    mm2 = vup.build_model_matrix(g, fg, e2)
+    mism = int((_cpu(mm2.bin) != bo).sum())
+    _say(f"  end-to-end bin mismatches: {mism}")
+    assert mism == 0
+
+
+def test_bins_outside_nan_and_bad_edges(vup, orc):
+    g = vup.make_grid((3, 4), (0.0, 0.0), (1.0, 1.0))
+    f = np.array([-1.0, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 3.0000000000000004, np.nan, np.inf,
+                  2.9999999999999996, 1.0000000000000002])
+    e = np.array([0.0, 1.0, 2.0, 3.0])
+    mm = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(e).to(DEV))
+    assert np.array_equal(_cpu(mm.bin), orc.bins(f, e))
+    c = mm.counters()
+    assert c["outside"] == (orc.bins(f, e) < 0).sum() and c["bad_edges"] == 0
+    ebad = np.array([0.0, 1.0, 1.0, 3.0])
+    mm2 = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(ebad).to(DEV))
+    assert (_cpu(mm2.bin) == -1).all() and mm2.counters()["bad_edges"] == 1
+
+
+# ---------------------------------------------------------------------------
+# windows
+# ---------------------------------------------------------------------------
+def test_windows_bitexact(vup, orc):
+    rng = np.random.default_rng(20)
+    for n, lo, hi in [((40, 23, 17), (-1.0, 0.0, -2.5), (1.0, 3.0, 0.5)),
+                      ((1024, 1024), (-3.0, -3.0), (3.0, 3.0)),
+                      ((48, 48, 48, 48), (-2.0,) * 4, (2.0,) * 4)]:
+        K = 2000
+        d = len(n)
+        mu = rng.uniform(np.array(lo) - 1, np.array(hi) + 1, size=(K, 1, d))
+        sigma = rng.uniform(1e-4, 0.8, size=(K, 1, d))
+        sigma[::97] = 0.0
+        wo, bad, _ = orc.windows(n, lo, hi, mu, sigma)
+        wg = _cpu(vup.windows(vup.make_grid(n, lo, hi), mu, sigma))
+        wo = wo.copy()
+        wo[bad.astype(bool)] = np.array([0, -1])
+        assert np.array_equal(wg, wo), n
+
+
+# ---------------------------------------------------------------------------
+# propagation, moments, IPSA: small configuration, every output
+# ---------------------------------------------------------------------------
+def test_grid64_all_outputs(vup, orc):
+    wl = workloads.grid64()
+    _say(f"[grid64] K={wl.K}")
+    o = orc.run_workload(wl)
+    gp = _gpu_pipeline(vup, wl)
+    rng_f = o["edges"][-1] - o["edges"][0]
+    _check_P(_cpu(gp["P"]), o["P"], 2e-5, "P fp32")
+    assert np.allclose(_cpu(gp["Z"]), o["Z"], rtol=2e-6, atol=0)
+    _check_moments(_cpu(gp["mean"]), _cpu(gp["var"]), o["mean"], o["var"], rng_f, "exact-f")
+    _check_moments(_cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), o["mean_hist"], o["var_hist"],
+                   rng_f, "binned")
+    dh = np.abs(_cpu(gp["entropy"]) - o["entropy"]).max()
+    _say(f"  entropy max err {dh:.2e}")
+    assert dh <= 1e-5
+    # the IPSA kernel alone, fed the oracle's columns rounded to FP32 and the
+    # oracle's edges (through a model matrix built from the oracle's f)
+    P32 = o["P"].astype(np.float32)
+    mm_o = vup.build_model_matrix(gp["grid"], torch.from_numpy(o["f"]).to(DEV),
+                                  torch.from_numpy(o["edges"]).to(DEV))
+    mg, vg, hg = vup.ipsa(mm_o, torch.from_numpy(P32).to(DEV))
+    m2, v2, h2 = orc.ipsa(P32.astype(np.float64), o["edges"])
+    assert np.allclose(_cpu(mg), m2, rtol=0, atol=1e-13)
+    assert np.allclose(_cpu(vg), v2, rtol=1e-12, atol=1e-15)
+    assert np.allclose(_cpu(hg), h2, rtol=1e-12, atol=1e-13)
+
+
+RAGGED = [
+    ("1d", (1000,), (-2.0,), (3.0,), "linear", (0.3, 1.7), 33, 1, (0.01, 0.9)),
+    ("2d", (37, 53), (-3.0, -2.0), (3.0, 2.5), "sincos2", (), 29, 1, (0.05, 1.2)),
+    ("2d_mix", (61, 45), (-3.0, -3.0), (3.0, 3.0), "timing2", (), 40, 2, (0.05, 0.8)),
+    ("3d", (20, 17, 23), (-2.0, -1.0, 0.0), (2.0, 1.5, 2.0), "damped3", (), 17, 1, (0.05, 0.7)),
+    ("4d_mix", (9, 11, 7, 13), (-2.0,) * 4, (2.0,) * 4, "ring4", (), 50, 2, (0.1, 0.9)),
+    ("2d_wide", (300, 7), (-1.0, -1.0), (1.0, 1.0), "linear", (0.0, 1.0, 0.1), 64, 1, (0.2, 3.0)),
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=[c[0] for c in RAGGED])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x2", "fp8e4m3"])
+def test_ragged_shapes(vup, orc, case, precision):
+    name, n, lo, hi, model, theta, B, C, sr = case
+    wl = workloads.random_workload(name, n, lo, hi, model, B, 150, C, sr, seed=zlib.crc32(name.encode()) % 100000,
+                                   theta=theta)
+    _say(f"[ragged {name} {precision}] n={n} B={B} C={C}")
+    o = orc.run_workload(wl, precision="fp64" if precision == "fp32" else precision,
+                         with_moments=(precision == "fp32"))
+    gp = _gpu_pipeline(vup, wl, precision, moments=(precision == "fp32"))
+    rng_f = o["edges"][-1] - o["edges"][0]
+    if precision == "fp32":
+        _check_P(_cpu(gp["P"]), o["P"], 2e-5, "P fp32")
+        _check_moments(_cpu(gp["mean"]), _cpu(gp["var"]), o["mean"], o["var"], rng_f, "exact-f")
+        _check_moments(_cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), o["mean_hist"],
+                       o["var_hist"], rng_f, "binned")
+    else:
+        # against the oracle's same-precision result (the rounding rule is the
+        # same; the GPU rounds an FP32 product, the oracle the exact FP64 value)
+        tol = {"bf16": 2 * U_BF16, "bf16x2": 5e-5, "fp8e4m3": 0.125}[precision]
+        _check_P(_cpu(gp["P"]), o["P"], tol, f"P {precision} vs same-precision oracle")
+        P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, o["bin"], wl.B, wl.mu, wl.sigma, wl.weight)
+        _check_P(_cpu(gp["P"]), P64, tol, f"P {precision} vs FP64 oracle")
+
+
+def test_edge_cases(vup, orc):
+    n, lo, hi = (40, 30), (-3.0, -3.0), (3.0, 3.0)
+    h = (6.0 / 40, 6.0 / 30)
+    mu = np.array([
+        [[0.3, -0.2]],                                   # ordinary
+        [[9.0, 0.0]],                                    # more than 4 sigma outside: empty
+        [[0.0, 0.0]],                                    # sigma = 0: invalid
+        [[lo[0] + 7.5 * h[0], lo[1] + 11.5 * h[1]]],     # delta input at a cell centre
+        [[0.0, 0.0]],                                    # covers the whole grid
+        [[-2.99, 2.99]],                                 # corner, window clipped
+    ])
+    sigma = np.array([[[0.4, 0.3]], [[0.2, 0.2]], [[0.0, 0.5]], [[1e-6 * h[0], 1e-6 * h[1]]],
+                      [[1e6, 1e6]], [[0.5, 0.25]]])
+    wl = workloads.Workload("edge", 2, n, lo, hi, "sincos2", (), 12, mu, sigma, None)
+    o = orc.run_workload(wl)
+    gp = _gpu_pipeline(vup, wl)
+    Pg = _cpu(gp["P"])
+    ok = [0, 3, 4, 5]
+    assert np.abs(Pg[ok] - o["P"][ok]).sum(axis=1).max() <= 2e-5
+    assert (Pg[1] == 0).all() and np.isnan(Pg[2]).all()
+    assert np.isnan(_cpu(gp["mean"])[[1, 2]]).all()
+    onehot = np.zeros(12)
+    onehot[o["bin"][7 * 30 + 11]] = 1.0
+    assert np.array_equal(Pg[3].astype(np.float64), onehot)
+    assert _cpu(gp["var"])[3] == 0.0 and _cpu(gp["entropy"])[3] == 0.0
+    c = gp["mm"].counters()
+    assert c["bad_param"] == 1 and c["empty"] == 1
+    # K = 0 is a no-op
+    P0, _ = vup.propagate(gp["mm"], np.zeros((0, 1, 2)), np.zeros((0, 1, 2)))
+    assert P0.shape == (0, 12)
+
+
+@pytest.mark.parametrize("B", [1, 4096])
+def test_bin_count_extremes(vup, orc, B):
+    wl = workloads.random_workload(f"B{B}", (70, 66), (-3.0, -3.0), (3.0, 3.0), "sincos2", B,
+                                   40, 1, (0.1, 1.0), seed=B)
+    o = orc.run_workload(wl)
+    gp = _gpu_pipeline(vup, wl)
+    _check_P(_cpu(gp["P"]), o["P"], 2e-5, f"P B={B}")
+
+
+def test_determinism(vup):
+    wl = workloads.grid48_4d().subset(np.arange(512))
+    a = _gpu_pipeline(vup, wl)
+    b = _gpu_pipeline(vup, wl)
+    for key in ("P", "Z", "mean", "var", "var_hist", "entropy"):
+        assert torch.equal(a[key], b[key]), key
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations, sampled distributions
+# ---------------------------------------------------------------------------
+def _sampled(vup, orc, wl, precision, nsample, seed, tol_l1, moments=True):
+    _say(f"[{wl.name} {precision}] K={wl.K} sampled {nsample}")
+    gp = _gpu_pipeline(vup, wl, precision, moments=moments)
+    ks = workloads.sample_indices(wl.K, nsample, seed)
+    sub = wl.subset(ks)
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
+    e = orc.uniform_edges(f, wl.B)
+    b = orc.bins(f, e)
+    oprec = "fp64" if precision == "fp32" else precision
+    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight, precision=oprec)
+    Pg = _cpu(gp["P"])[ks]
+    l1 = _check_P(Pg, Po, tol_l1, f"P {precision} sampled")
+    P64 = Po
+    if precision != "fp32":
+        P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight)
+        l1 = _check_P(Pg, P64, tol_l1, f"P {precision} vs FP64")
+    rng_f = e[-1] - e[0]
+    mh, vh, hh = orc.ipsa(P64, e)
+    if moments:
+        mo, vo, _ = orc.moments(wl.n, wl.lo, wl.hi, f, sub.mu, sub.sigma, sub.weight)
+        _check_moments(_cpu(gp["mean"])[ks], _cpu(gp["var"])[ks], mo, vo, rng_f, "exact-f")
+    return gp, ks, (mh, vh, hh), l1
+
+
+def test_grid1024_fp32_sampled(vup, orc):
+    wl = workloads.grid1024()
+    gp, ks, (mh, vh, hh), _ = _sampled(vup, orc, wl, "fp32", 48, 1, 2e-5)
+    rng_f = _cpu(gp["edges"])[-1] - _cpu(gp["edges"])[0]
+    _check_moments(_cpu(gp["mean_hist"])[ks], _cpu(gp["var_hist"])[ks], mh, vh, rng_f, "binned")
+    assert np.abs(_cpu(gp["entropy"])[ks] - hh).max() <= 1e-5
+    # every column of the full run is normalised
+    assert np.abs(_cpu(gp["P"]).astype(np.float64).sum(axis=1) - 1).max() <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x2"])
+def test_grid128_3d_sampled(vup, orc, precision):
+    wl = workloads.grid128_3d()
+    tol = {"fp32": 2e-5, "bf16": 2 * U_BF16, "bf16x2": 5e-5}[precision]
+    gp, ks, (mh, vh, hh), l1 = _sampled(vup, orc, wl, precision, 48, 3, tol,
+                                        moments=(precision == "fp32"))
+    rng_f = _cpu(gp["edges"])[-1] - _cpu(gp["edges"])[0]
+    if precision == "fp32":
+        _check_moments(_cpu(gp["mean_hist"])[ks], _cpu(gp["var_hist"])[ks], mh, vh, rng_f,
+                       "binned")
+    else:
+        eh = np.abs(_cpu(gp["entropy"])[ks] - hh).max()
+        _say(f"  entropy err {eh:.3e} (bar {2 * U_BF16 * (1 + math.log(wl.B)):.2e})")
+        assert eh <= 2 * U_BF16 * (1 + math.log(wl.B)) * (1 if precision == "bf16" else 0.05)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp8e4m3"])
+def test_grid48_4d_sampled(vup, orc, precision):
+    wl = workloads.grid48_4d()
+    tol = {"fp32": 2e-5, "fp8e4m3": 0.125}[precision]
+    _sampled(vup, orc, wl, precision, 32, 5, tol, moments=(precision == "fp32"))
+
+
+# ---------------------------------------------------------------------------
+# backward: adjoint kernel vs FP64 analytic gradient (and the oracle's FD)
+# ---------------------------------------------------------------------------
+def _grad_case(vup, orc, wl, ks, seed):
+    rng = np.random.default_rng(seed)
+    g_var = rng.uniform(0.5, 1.5, size=wl.K)
+    g_ent = rng.uniform(0.5, 1.5, size=wl.K)
+    gp = _gpu_pipeline(vup, wl, moments=False)
+    gm, gs, gw = vup.ipsa_backward(gp["mm"], wl.mu, wl.sigma, wl.weight, gp["P"],
+                                   gp["mean_hist"], torch.from_numpy(g_var).to(DEV),
+                                   torch.from_numpy(g_ent).to(DEV))
+    sub = wl.subset(ks)
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
+    e = orc.uniform_edges(f, wl.B)
+    b = orc.bins(f, e)
+    win, _, _ = orc.windows(wl.n, wl.lo, wl.hi, sub.mu, sub.sigma)
+    P, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight, win=win)
+    om, os_, ow = orc.ipsa_grad(wl.n, wl.lo, wl.hi, b, e, sub.mu, sub.sigma, sub.weight, win, P,
+                                g_var[ks], g_ent[ks])
+    for name, g, o in (("mu", _cpu(gm)[ks], om), ("sigma", _cpu(gs)[ks], os_),
+                       ("weight", _cpu(gw)[ks], ow)):
+        if name == "weight" and wl.weight is None:
+            continue
+        scale = np.abs(o).max()
+        err = np.abs(g - o) - (2e-3 * np.abs(o) + 1e-5 * scale)
+        _say(f"  d/d{name}: max |err| {np.abs(g - o).max():.3e}, scale {scale:.3e}")
+        assert (err <= 0).all(), name
+    return gm, gs, gw
+
+
+def test_backward_grid64_all(vup, orc):
+    wl = workloads.grid64()
+    _say("[backward grid64]")
+    _grad_case(vup, orc, wl, np.arange(wl.K), 40)
+
+
+def test_backward_grid1024_sampled(vup, orc):
+    wl = workloads.grid1024()
+    _say("[backward grid1024 sampled]")
+    ks = workloads.fd_subset(wl.K, 24)
+    _grad_case(vup, orc, wl, ks, 41)
+
+
+def test_backward_mixtures_4d_sampled(vup, orc):
+    wl = workloads.grid48_4d()
+    _say("[backward grid48_4d mixtures sampled]")
+    _grad_case(vup, orc, wl, workloads.sample_indices(wl.K, 16, 42), 42)
+
+
+def test_backward_ragged(vup, orc):
+    for case in RAGGED:
+        name, n, lo, hi, model, theta, B, C, sr = case
+        wl = workloads.random_workload(name, n, lo, hi, model, B, 40, C, sr, seed=7, theta=theta)
+        _say(f"[backward ragged {name}]")
+        _grad_case(vup, orc, wl, np.arange(wl.K), 43)
+
+
+def test_autograd_function_matches_adjoint(vup):
+    wl = workloads.grid64()
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    f = vup.eval_grid(g, wl.model)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B))
+    mu = torch.from_numpy(wl.mu).to(DEV).requires_grad_(True)
+    sg = torch.from_numpy(wl.sigma).to(DEV).requires_grad_(True)
+    var, ent = vup.IPSA.apply(mu, sg, None, mm)
+    (var.sum() + 0.5 * ent.sum()).backward()
+    P, _ = vup.propagate(mm, wl.mu, wl.sigma)
+    mh, _, _ = vup.ipsa(mm, P)
+    gm, gs, _ = vup.ipsa_backward(mm, wl.mu, wl.sigma, None, P, mh,
+                                  torch.ones(wl.K, dtype=torch.float64, device=DEV),
+                                  torch.full((wl.K,), 0.5, dtype=torch.float64, device=DEV))
+    assert torch.equal(mu.grad, gm) and torch.equal(sg.grad, gs)
