@@ -4,18 +4,20 @@
 // One workgroup (256 threads, 4 waves) handles one distribution k and loops
 // over its mixture components. For each component:
 //   1. the truncation window is computed per axis (FP64, exact op order) and
-//      the per-axis Gaussian factors g_d(j) are tabulated in LDS (FP64 exp,
-//      stored FP32). The fastest-axis table is zero-padded to whole strips;
+//      the per-axis Gaussian factors g_d(j) are tabulated in LDS (FP32). The
+//      fastest-axis table is zero-padded to whole strips;
 //   2. the window is swept as rows (all axes but the fastest) x strips of SW
 //      consecutive cells of the fastest axis, aligned to SW in the padded bin
 //      map. A thread keeps its strip's factors in registers and walks rows; the
 //      row factor (product of the slower axes' factors) and the row's bin-map
 //      offset come from a row table in LDS;
 //   3. per cell the density is one FP32 multiply (row factor x fastest-axis
-//      factor) and the accumulation is an LDS float add into the bin's slot.
-//      Each wave owns `cpw` private copies of the histogram (rows of a wave
-//      spread over them), so same-bin neighbours of different rows do not
-//      collide and the summation order is fixed: results are deterministic.
+//      factor); it is accumulated into the bin's LDS slot as a 32-bit
+//      fixed-point integer (LDS float atomics are two orders of magnitude
+//      slower than integer ones on gfx950). Cells are split into magnitude
+//      classes with one histogram and one scale each, so tail cells keep a
+//      fine quantum (see the fixed-point notes below). Integer sums are exact,
+//      so results do not depend on scheduling.
 // The input probability matrix is never materialised.
 #include <hip/hip_runtime.h>
 
@@ -136,7 +138,7 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
       const double mu = a.d.mu[kc * D + d], sg = a.d.sigma[kc * D + d];
       for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
         const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
-        tab[i] = (float)gauss_factor(x, mu, sg);
+        tab[i] = gauss_factor(x, mu, sg);
       }
     }
   }
@@ -150,7 +152,7 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
     float v = 0.0f;
     if (j >= loL && j < loL + WL) {
       const double x = cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], j);
-      v = (float)gauss_factor(x, mu, sg);
+      v = gauss_factor(x, mu, sg);
     }
     tab[jj] = v;
   }
@@ -220,42 +222,196 @@ __device__ __forceinline__ uint32_t map_at(const MapVec<SW>& m, int j) {
 // ===========================================================================
 // propagation
 // ===========================================================================
+// Sum of the tabulated per-axis factors of the current window, multiplied
+// over the axes (FP64): the total weight of the separable truncated density.
+__device__ __forceinline__ double table_mass(const SweepArgs& a, const float* smem, const Win& w,
+                                             int ns, int sw, double* red) {
+  const int D = a.g.ndim;
+  double Z = 1.0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (d < D) {
+      double zp = 0.0;
+      const int cnt = (d + 1 < D) ? w.W[d] : ns * sw;
+      for (int i = threadIdx.x; i < cnt; i += kThreads) zp += (double)smem[a.L.tab_off[d] + i];
+      Z *= block_sum(zp, red);
+    }
+  }
+  return Z;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-point histogram accumulation.
+// The density of a cell is the product go * gl of its row factor and its
+// fastest-axis factor. Cells are split into 3 x 3 magnitude classes by the row
+// factor (go >= 2^-4, >= 2^-8, smaller) and by the largest factor of their
+// strip; every class has its own LDS histogram and its own scale
+//     scale[rc][cc] = K / (qfac * rowbound[rc] * colmass[cc]),
+// where colmass is the exact factor sum of the strips in class cc, rowbound an
+// upper bound of the row factors' sum in class rc, qfac >= 1 the largest
+// relative increase of a density by the precision's rounding, and
+// K = 2^32 - 2^20 - (cells). A cell adds floor(w * scale + u) with a fixed
+// dither u = (j + 1/2)/SW that depends only on its position j in the strip, so
+// no class total can exceed 2^32: nothing overflows, tail cells keep a fine
+// quantum, and rounding is unbiased on average. Integer adds are exact, so
+// the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr float kClassT1 = 0.0625f;      // 2^-4
+constexpr float kClassT2 = 0.00390625f;  // 2^-8
+
+__device__ __forceinline__ int mag_class(float g) {
+  return g >= kClassT1 ? 0 : (g >= kClassT2 ? 1 : 2);
+}
+
+template <int PREC>
+__host__ __device__ constexpr double prec_qfac() {
+  return PREC == VUP_BF16 ? 1.0 + 1.0 / 256 : PREC == VUP_BF16X2 ? 1.0 + 1.0 / 65536
+         : PREC == VUP_FP8E4M3 ? 1.125 : 1.0 + 1.0 / 1048576;
+}
+
+// per-component scales shared by all threads (LDS): srow[3], scol[3], inv[9]
+struct PropScales {
+  float srow[3];
+  float scol[3];
+  double unscale[9];  // 1 / scale of each class (FP64)
+};
+
+template <int PREC>
+__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
+                                            int sw, double* red, PropScales* ps) {
+  const int D = a.g.ndim;
+  const float* tabL = smem + a.L.tab_off[D - 1];
+  // column classes: by the largest factor of each strip
+  double cm[3] = {0.0, 0.0, 0.0};
+  for (int st = threadIdx.x; st < ns; st += kThreads) {
+    float gmax = 0.0f;
+    double sum = 0.0;
+    for (int j = 0; j < sw; ++j) {
+      const float g = tabL[st * sw + j];
+      gmax = fmaxf(gmax, g);
+      sum += (double)g;
+    }
+    const int cc = mag_class(gmax);
+    cm[0] += cc == 0 ? sum : 0.0;
+    cm[1] += cc == 1 ? sum : 0.0;
+    cm[2] += cc == 2 ? sum : 0.0;
+  }
+  double colmass[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) colmass[c] = block_sum(cm[c], red);
+  // row factor sum bound per class: total row mass, and rows * class ceiling
+  double Zrows = 1.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d + 1 < D) {
+      double zp = 0.0;
+      for (int i = threadIdx.x; i < w.W[d]; i += kThreads) zp += (double)smem[a.L.tab_off[d] + i];
+      Zrows *= block_sum(zp, red);
+    }
+  }
+  const double R = (double)w.R;
+  const double cells = R * (double)(ns * sw);
+  double K = 4294967296.0 - 1048576.0 - cells;
+  if (PREC == VUP_FP8E4M3) K *= 0.5;  // subnormal rounding of tiny values
+  if (threadIdx.x == 0) {
+    if (a.L.ncls > 1) {
+      const double rowbound[3] = {Zrows, fmin(Zrows, R * (double)kClassT1),
+                                  fmin(Zrows, R * (double)kClassT2)};
+      for (int r = 0; r < 3; ++r) ps->srow[r] = (float)(K / (prec_qfac<PREC>() * rowbound[r]));
+      for (int c = 0; c < 3; ++c) ps->scol[c] = colmass[c] > 0.0 ? (float)(1.0 / colmass[c]) : 0.0f;
+    } else {
+      // a single class: one scale for the whole window
+      const double cmass = colmass[0] + colmass[1] + colmass[2];
+      for (int r = 0; r < 3; ++r) ps->srow[r] = (float)(K / (prec_qfac<PREC>() * Zrows));
+      for (int c = 0; c < 3; ++c) ps->scol[c] = (float)(1.0 / cmass);
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        ps->unscale[r * 3 + c] =
+            ps->scol[c] > 0.0f ? 1.0 / ((double)ps->srow[r] * (double)ps->scol[c]) : 0.0;
+  }
+}
+
+// Row table of the propagation: (go, go * srow[class], map offset, class).
+__device__ __forceinline__ void build_rows_prop(const SweepArgs& a, float* smem, const Win& w,
+                                                long long r0, int rc, const PropScales* ps) {
+  const int D = a.g.ndim;
+  float4* rt = reinterpret_cast<float4*>(smem + a.L.row_off);
+  for (int r = threadIdx.x; r < rc; r += kThreads) {
+    long long t = r0 + r;
+    float go = 1.0f;
+    long long off = 0;
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      if (d <= D - 2) {
+        const int i = (int)(t % w.W[d]);
+        t /= w.W[d];
+        go *= smem[a.L.tab_off[d] + i];
+        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
+      }
+    }
+    const int cls = a.L.ncls > 1 ? mag_class(go) : 0;
+    rt[r] = make_float4(go, go * ps->srow[cls], __int_as_float((int)off), __int_as_float(cls));
+  }
+}
+
 template <int SW, int PREC>
-__device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, const Win& w, int rc,
-                                          int colbase, int ns) {
+__device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int rc, int colbase,
+                                          int ns, const PropScales* ps) {
   const int cols = ns < kThreads ? ns : kThreads;
   const int P0 = kThreads / cols;
   const int col = threadIdx.x % cols;
   const int ph = threadIdx.x / cols;
   if (ph >= P0) return;
-  const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
-  const int wave = threadIdx.x >> 6;
-  const int copy = wave * a.L.cpw + (ph & (a.L.cpw - 1));
-  char* lh = reinterpret_cast<char*>(smem + a.L.hist_off + copy * a.L.hist_stride);
+  const float4* rt = reinterpret_cast<const float4*>(smem + a.L.row_off);
+  const int cpc = a.L.cpw;  // copies per class
+  const int strideb = a.L.hist_stride * 4;
+  // byte offset between row classes (3 column classes x cpc copies each)
+  const int rcstep = 3 * cpc * strideb;
+  char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off) + (ph & (cpc - 1)) * strideb;
   const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
   for (int s = col; s < ns; s += cols) {
     float gl[SW];
+    float gmax = 0.0f;
 #pragma unroll
-    for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
+    for (int j = 0; j < SW; ++j) {
+      gl[j] = tabL[s * SW + j];
+      gmax = fmaxf(gmax, gl[j]);
+    }
+    const int cc = a.L.ncls > 1 ? mag_class(gmax) : 0;
+    const float scol = ps->scol[cc];
+    char* lh = hbase + cc * cpc * strideb;
     const int mcol = colbase + s * SW;
     int r = ph;
     if (r >= rc) continue;
-    float2 cur = rt[r];
-    MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.y) + mcol);
+    float4 cur = rt[r];
+    MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.z) + mcol);
     for (; r < rc; r += P0) {
       const int rn = r + P0;
-      float2 nxt = cur;
+      float4 nxt = cur;
       MapVec<SW> mn = mv;
       if (rn < rc) {
         nxt = rt[rn];
-        mn = load_map<SW>(a.binmap + (long long)__float_as_int(nxt.y) + mcol);
+        mn = load_map<SW>(a.binmap + (long long)__float_as_int(nxt.z) + mcol);
       }
-      const float go = cur.x;
+      const int rcl = a.L.ncls > 1 ? __float_as_int(cur.w) : 0;
+      char* lr = lh + rcl * rcstep;
+      const float gos = cur.y * scol;
+      float qs = 0.0f;
+      if constexpr (PREC != VUP_FP32) {
+        qs = ps->srow[rcl] * scol * (PREC == VUP_FP8E4M3 ? (1.0f / 448.0f) : 1.0f);
+      }
 #pragma unroll
       for (int j = 0; j < SW; ++j) {
-        const float q = quantize<PREC>(go * gl[j]);
-        float* slot = reinterpret_cast<float*>(lh + map_at<SW>(mv, j));
-        __hip_atomic_fetch_add(slot, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const float u = ((float)j + 0.5f) * (1.0f / (float)SW);
+        float v;
+        if constexpr (PREC == VUP_FP32) {
+          v = fmaf(gos, gl[j], u);
+        } else {
+          v = fmaf(quantize<PREC>(cur.x * gl[j]), qs, u);
+        }
+        uint32_t* slot = reinterpret_cast<uint32_t*>(lr + map_at<SW>(mv, j));
+        __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       cur = nxt;
       mv = mn;
@@ -271,8 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
   const int D = a.g.ndim;
   const int B = a.B;
   const int nslots = B + 1;
-  const int ncopies = kWaves * a.L.cpw;
+  const int ncls = a.L.ncls;
+  const int cpc = a.L.cpw;
   double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  PropScales* ps = reinterpret_cast<PropScales*>(red + 16);
+  const uint32_t* hist = reinterpret_cast<const uint32_t*>(smem + a.L.hist_off);
   float* Pk = a.P + k * (long long)B;
   bool anybad = false;
   bool written = false;  // row k holds a partial mixture
@@ -290,39 +449,51 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
     }
     int loL, WL;
     last_axis(w, D, loL, WL);
-    const int sw = choose_sw(loL, WL, w.R, 32);
+    const int sw = choose_sw(loL, WL, w.R, kMaxSW);
     const int colbase = (loL / sw) * sw;
     const int ns = (loL + WL - 1) / sw - loL / sw + 1;
     __syncthreads();  // LDS reuse across components
     build_tables(a, smem, w, kc, sw, colbase, ns);
-    for (int i = threadIdx.x; i < ncopies * a.L.hist_stride; i += kThreads)
+    for (int i = threadIdx.x; i < ncls * cpc * a.L.hist_stride; i += kThreads)
       smem[a.L.hist_off + i] = 0.0f;
+    __syncthreads();
+    prop_scales<PREC>(a, smem, w, ns, sw, red, ps);
     for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
       const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
       __syncthreads();
-      build_rows(a, smem, w, r0, rc, kc, false);
+      build_rows_prop(a, smem, w, r0, rc, ps);
       __syncthreads();
       switch (sw) {
-        case 4: prop_rows<4, PREC>(a, smem, w, rc, colbase, ns); break;
-        case 8: prop_rows<8, PREC>(a, smem, w, rc, colbase, ns); break;
-        case 16: prop_rows<16, PREC>(a, smem, w, rc, colbase, ns); break;
-        default: prop_rows<32, PREC>(a, smem, w, rc, colbase, ns); break;
+        case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
+        case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
+        default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
       }
     }
     __syncthreads();
-    // normaliser: FP64 sum over every slot of every copy, in a fixed order
+    // unscale each class, sum its copies; the normaliser is the sum over all
+    // slots (cells without a bin included)
     double zpart = 0.0;
-    for (int b = threadIdx.x; b < nslots; b += kThreads)
-      for (int cp = 0; cp < ncopies; ++cp)
-        zpart += (double)smem[a.L.hist_off + cp * a.L.hist_stride + b];
+    for (int b = threadIdx.x; b < nslots; b += kThreads) {
+      double v = 0.0;
+      for (int cl = 0; cl < ncls; ++cl) {
+        uint64_t cnt = 0;
+        for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * a.L.hist_stride + b];
+          v += (double)cnt * ps->unscale[cl];
+      }
+      zpart += v;
+    }
     const double Zc = block_sum(zpart, red);
     if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
-    const double scale = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
+    const double f = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
     for (int b = threadIdx.x; b < B; b += kThreads) {
-      double s = 0.0;
-      for (int cp = 0; cp < ncopies; ++cp) s += (double)smem[a.L.hist_off + cp * a.L.hist_stride + b];
+      double v = 0.0;
+      for (int cl = 0; cl < ncls; ++cl) {
+        uint64_t cnt = 0;
+        for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * a.L.hist_stride + b];
+        v += (double)cnt * ps->unscale[cl];
+      }
       const double prev = written ? (double)Pk[b] : 0.0;
-      Pk[b] = (float)(prev + s * scale);
+      Pk[b] = (float)(prev + v * f);
     }
     written = true;
   }
@@ -398,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
     used[c] = true;
     int loL, WL;
     last_axis(w, D, loL, WL);
-    const int sw = choose_sw(loL, WL, w.R, 32);
+    const int sw = choose_sw(loL, WL, w.R, kMaxSW);
     const int colbase = (loL / sw) * sw;
     const int ns = (loL + WL - 1) / sw - loL / sw + 1;
     // shift: model value at the window's centre cell
@@ -418,8 +589,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
       switch (sw) {
         case 4: mom_rows<4>(a, smem, rc, colbase, ns, shift, A1, A2); break;
         case 8: mom_rows<8>(a, smem, rc, colbase, ns, shift, A1, A2); break;
-        case 16: mom_rows<16>(a, smem, rc, colbase, ns, shift, A1, A2); break;
-        default: mom_rows<32>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+        default: mom_rows<16>(a, smem, rc, colbase, ns, shift, A1, A2); break;
       }
     }
     // normaliser: product of the per-axis factor sums (separable density)
@@ -681,7 +851,7 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   }
   off = round_up(off, 4);
   L.row_off = off;
-  off += 2 * kRowChunk;
+  off += (kind == kSweepPropagate ? 4 : 2) * kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;
@@ -690,21 +860,34 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   L.hist_off = off;
   L.hist_stride = 0;
   L.cpw = 0;
+  L.ncls = 1;
   if (kind == kSweepPropagate) {
     // stride = 1 mod 32 so consecutive copies shift banks by one
     const int stride = round_up(B + 1, 32) + 1;
     L.hist_stride = stride;
-    int cpw = 8;
-    const int budget_floats = 48 * 1024 / 4;
-    while (cpw > 1 && off + kWaves * cpw * stride + 64 > budget_floats) cpw >>= 1;
-    L.cpw = cpw;
-    off += kWaves * cpw * stride;
+    const int budget = 48 * 1024 / 4 - 64;
+    const int opts[5][2] = {{9, 2}, {9, 1}, {1, 4}, {1, 2}, {1, 1}};
+    int pick = 4;
+    for (int i = 0; i < 5; ++i)
+      if (off + opts[i][0] * opts[i][1] * stride <= budget) {
+        pick = i;
+        break;
+      }
+    if (pick == 4)  // nothing fits the occupancy budget: take the richest that fits at all
+      for (int i = 0; i < 5; ++i)
+        if (off + opts[i][0] * opts[i][1] * stride <= 160 * 1024 / 4 - 64) {
+          pick = i;
+          break;
+        }
+    L.ncls = opts[pick][0];
+    L.cpw = opts[pick][1];
+    off += L.ncls * L.cpw * stride;
   } else if (kind == kSweepBackward) {
     off += round_up(B + 1, 4);
   }
   off = round_up(off, 4);
   L.red_off = off;
-  off += 2 * 16;  // 16 doubles
+  off += 64;  // 16 doubles of reduction scratch + per-component scales
   L.bytes = (size_t)off * 4;
   *out = L;
   return L.bytes <= 160 * 1024;

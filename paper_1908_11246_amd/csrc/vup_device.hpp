@@ -12,7 +12,8 @@ namespace vup {
 
 constexpr int kThreads = 256;     // threads per workgroup of the sweep kernels
 constexpr int kWaves = kThreads / 64;
-constexpr int kRowChunk = 1024;   // rows of the row table held in LDS at once
+constexpr int kRowChunk = 512;    // rows of the row table held in LDS at once
+constexpr int kMaxSW = 16;        // widest strip of the fastest axis
 constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
 
 // counters stored in the workspace (int64 each)
@@ -80,10 +81,16 @@ __device__ __forceinline__ double cell_centre(double lo, double hi, int n, int j
   return lo + (j + 0.5) * ((hi - lo) / n);
 }
 
-// per-axis Gaussian factor exp(-t^2/2), t = (x_j - mu)/sigma, in FP64
-__device__ __forceinline__ double gauss_factor(double x, double mu, double sigma) {
+// per-axis Gaussian factor exp(-t^2/2), t = (x_j - mu)/sigma, rounded to
+// FP32. The argument is formed in FP64 and split into an FP32 head and tail,
+// exp(a) = exp(a_hi) (1 + a_lo), which keeps the result within about one FP32
+// ulp without the register cost of an FP64 exponential.
+__device__ __forceinline__ float gauss_factor(double x, double mu, double sigma) {
   const double t = (x - mu) / sigma;
-  return exp(-0.5 * (t * t));
+  const double arg = -0.5 * (t * t);
+  const float hi = (float)arg;
+  const float lo = (float)(arg - (double)hi);
+  return expf(hi) * (1.0f + lo);
 }
 
 // ---------------------------------------------------------------------------

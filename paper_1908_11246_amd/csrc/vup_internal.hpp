@@ -19,11 +19,12 @@ constexpr int kBinChunk = 4096;
 struct SweepLayout {
   int tab_off[4];
   int cap[4];
-  int row_off;      // float2[kRowChunk]
+  int row_off;      // float4[kRowChunk] (propagate) or float2[kRowChunk]
   int trow_off;     // float4[kRowChunk] (backward only, else -1)
   int hist_off;     // histogram copies (propagate) or v table (backward)
   int hist_stride;  // floats per histogram copy
-  int cpw;          // histogram copies per wave
+  int cpw;          // histogram copies per magnitude class
+  int ncls;         // magnitude classes (9, or 1 when LDS is short)
   int red_off;      // double scratch
   size_t bytes;
 };
