@@ -197,6 +197,39 @@ int vup_windows(const vup_grid* g, const vup_dists* d, int32_t* win, void* strea
 int vup_propagate(const vup_mm* mm, const vup_dists* d, int32_t precision, float* P, double* Z,
                   void* stream);
 
+/* Tensor-product family of 2-D Gaussians for vup_propagate_separable:
+ * distribution k = mx * M[1] + my has mean (mu[0][mx], mu[1][my]) and
+ * deviations (sigma[0][mx], sigma[1][my]); e.g. measurement locations on a
+ * subgrid of the input domain (Sec. 5.3 evaluates one pdf per location). */
+typedef struct vup_sepdists {
+  int32_t M[2];            /* locations per axis, >= 1                          */
+  double n_sigma;          /* truncation half-width in standard deviations, > 0 */
+  const double* mu[2];     /* dev [M[d]] FP64                                    */
+  const double* sigma[2];  /* dev [M[d]] FP64; <= 0 or non-finite -> NaN rows    */
+} vup_sepdists;
+
+/* --------------------------------------------------------------------------
+ * vup_separable_workspace_bytes - device workspace for vup_propagate_separable
+ * (factor matrices, per-axis sums and the partial contraction T, whose size
+ * is n[0] * B * M[1] floats). 0 for invalid arguments.
+ * ------------------------------------------------------------------------ */
+size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My);
+
+/* --------------------------------------------------------------------------
+ * vup_propagate_separable - eq. VUP for a tensor-product family on a 2-D grid,
+ * with the input probability matrix factorised into per-axis truncated
+ * Gaussian factors A_x[ix][mx], A_y[iy][my]:
+ *   P[k][b] = sum_ix A_x[ix][mx] T[ix][b][my] / (Zx[mx] Zy[my]),
+ *   T[ix][b][my] = sum_{iy : bin(ix,iy) = b} A_y[iy][my].
+ * T is a scatter over one axis; the contraction over the other is a banded
+ * dense product evaluated on the matrix cores (FP32 MFMA). Same outputs and
+ * conventions as vup_propagate with K = M[0]*M[1], ncomp = 1 (Z[k] =
+ * Zx[mx] * Zy[my], the window mass). Needs ndim == 2 and B <= 512.
+ *   ws: dev, 256-byte aligned, ws_bytes >= vup_separable_workspace_bytes.
+ * ------------------------------------------------------------------------ */
+int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, size_t ws_bytes,
+                            float* P, double* Z, void* stream);
+
 /* --------------------------------------------------------------------------
  * vup_moments - output moments of each propagated pdf from the exact model
  * values (quadrature form of the marginalisation integral, eq. UP):

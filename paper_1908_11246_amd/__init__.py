@@ -54,6 +54,11 @@ class VupDists(ctypes.Structure):
                 ("sigma", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
 
 
+class VupSepDists(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32 * 2), ("n_sigma", ctypes.c_double),
+                ("mu", ctypes.c_void_p * 2), ("sigma", ctypes.c_void_p * 2)]
+
+
 class VupMM(ctypes.Structure):
     _fields_ = [("grid", VupGrid), ("B", ctypes.c_int32), ("pitch", ctypes.c_int32),
                 ("N", ctypes.c_int64), ("rows", ctypes.c_int64), ("ws", ctypes.c_void_p),
@@ -92,6 +97,10 @@ def _load():
     lib.vup_ipsa_backward.argtypes = [_P(VupMM), _P(VupDists), _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]
     lib.vup_counters.argtypes = [_P(VupMM), _vp, _P(ctypes.c_int64)]
+    lib.vup_separable_workspace_bytes.restype = ctypes.c_size_t
+    lib.vup_separable_workspace_bytes.argtypes = [_P(VupMM), ctypes.c_int32, ctypes.c_int32]
+    lib.vup_propagate_separable.argtypes = [_P(VupMM), _P(VupSepDists), _vp, ctypes.c_size_t, _vp,
+                                            _vp, _vp]
     _lib = lib
     return lib
 
@@ -260,6 +269,41 @@ def propagate(mm: ModelMatrix, mu, sigma, weight=None, precision: str = "fp32",
     _check(_load().vup_propagate(ctypes.byref(mm.mm), ctypes.byref(d), PRECISIONS[precision],
                                  _ptr(P), _ptr(Z), _vp(_stream())))
     return P, Z
+
+
+class SeparableWorkspace:
+    """Device workspace of the separable (banded MFMA) propagation."""
+
+    def __init__(self, mm: ModelMatrix, Mx: int, My: int):
+        n = _load().vup_separable_workspace_bytes(ctypes.byref(mm.mm), int(Mx), int(My))
+        if n == 0:
+            raise VupError(-1, "separable form needs a 2-D model matrix")
+        self.buf = torch.empty(n + 256, dtype=torch.uint8, device=mm.device)
+        self.ptr = (self.buf.data_ptr() + 255) // 256 * 256
+        self.nbytes = n
+        self.M = (int(Mx), int(My))
+
+
+def propagate_separable(mm: ModelMatrix, mu_x, mu_y, sigma_x, sigma_y, n_sigma: float = 4.0,
+                        ws: Optional[SeparableWorkspace] = None, want_Z: bool = True):
+    """eq. VUP for the tensor-product family k = mx*My + my (banded MFMA form)."""
+    mx = _dev_f64(mu_x, mm.device)
+    my = _dev_f64(mu_y, mm.device)
+    sx = _dev_f64(sigma_x, mm.device)
+    sy = _dev_f64(sigma_y, mm.device)
+    Mx, My = mx.numel(), my.numel()
+    if ws is None or ws.M != (Mx, My):
+        ws = SeparableWorkspace(mm, Mx, My)
+    P = torch.empty((Mx * My, mm.B), dtype=torch.float32, device=mm.device)
+    Z = torch.empty(Mx * My, dtype=torch.float64, device=mm.device) if want_Z else None
+    s = VupSepDists()
+    s.M[0], s.M[1] = Mx, My
+    s.n_sigma = float(n_sigma)
+    s.mu[0], s.mu[1] = mx.data_ptr(), my.data_ptr()
+    s.sigma[0], s.sigma[1] = sx.data_ptr(), sy.data_ptr()
+    _check(_load().vup_propagate_separable(ctypes.byref(mm.mm), ctypes.byref(s), _vp(ws.ptr),
+                                           ws.nbytes, _ptr(P), _ptr(Z), _vp(_stream())))
+    return P, Z, ws
 
 
 def moments(mm: ModelMatrix, mu, sigma, weight=None, model: Optional[str] = None,

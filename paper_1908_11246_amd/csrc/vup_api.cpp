@@ -201,6 +201,34 @@ int vup_propagate(const vup_mm* mm, const vup_dists* d, int32_t precision, float
                   "vup_propagate");
 }
 
+size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My) {
+  if (check_mm(mm) || mm->grid.ndim != 2 || Mx < 1 || My < 1) return 0;
+  return vup::sep_workspace_bytes(mm->grid, mm->B, Mx, My);
+}
+
+int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, size_t ws_bytes,
+                            float* P, double* Z, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (mm->grid.ndim != 2) return fail(VUP_EUNSUPPORTED, "separable form needs a 2-D grid");
+  if (mm->B > 512) return fail(VUP_EUNSUPPORTED, "separable form needs B <= 512");
+  if (!s) return fail(VUP_EINVAL, "sepdists is NULL");
+  if (s->M[0] < 1 || s->M[1] < 1 || s->M[0] > 65535 || s->M[1] > 65535)
+    return fail(VUP_EINVAL, "M must be in [1, 65535]");
+  if (!(s->n_sigma > 0.0) || !std::isfinite(s->n_sigma))
+    return fail(VUP_EINVAL, "n_sigma must be finite and > 0");
+  if (!s->mu[0] || !s->mu[1] || !s->sigma[0] || !s->sigma[1] || !P)
+    return fail(VUP_EINVAL, "mu, sigma or P is NULL");
+  if (!ws) return fail(VUP_EWORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VUP_EWORKSPACE, "workspace not 256-byte aligned");
+  const size_t need = vup::sep_workspace_bytes(mm->grid, mm->B, s->M[0], s->M[1]);
+  if (ws_bytes < need) return fail(VUP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  if ((r = check_device())) return r;
+  return launched(vup::launch_separable(*mm, s->M[0], s->M[1], s->mu[0], s->mu[1], s->sigma[0],
+                                        s->sigma[1], s->n_sigma, ws, P, Z, (hipStream_t)stream),
+                  "vup_propagate_separable");
+}
+
 int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, double* mean,
                 double* var, double* delta2, void* stream) {
   int r = check_mm(mm);

@@ -51,6 +51,11 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            const double* mean_hist, const double* g_var, const double* g_ent,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);
 
+size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My);
+hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x,
+                            const double* mu_y, const double* sg_x, const double* sg_y,
+                            double ns, void* ws, float* P, double* Z, hipStream_t s);
+
 // workspace sizing shared by vup_bin_workspace_bytes and vup_bin
 struct WsLayout {
   int pitch;

@@ -399,3 +399,61 @@ def test_autograd_function_matches_adjoint(vup):
                                   torch.ones(wl.K, dtype=torch.float64, device=DEV),
                                   torch.full((wl.K,), 0.5, dtype=torch.float64, device=DEV))
     assert torch.equal(mu.grad, gm) and torch.equal(sg.grad, gs)
+
+
+# ---------------------------------------------------------------------------
+# separable (banded MFMA) form for tensor-product families
+# ---------------------------------------------------------------------------
+def _sep_case(vup, orc, n, lo, hi, model, B, mux, muy, sgx, sgy, label):
+    _say(f"[separable {label}] n={n} B={B} M=({len(mux)},{len(muy)})")
+    g = vup.make_grid(n, lo, hi)
+    f = vup.eval_grid(g, model)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, B))
+    P, Z, _ = vup.propagate_separable(mm, mux, muy, sgx, sgy)
+    # the same K = Mx*My distributions through the general path and the oracle
+    Mx, My = len(mux), len(muy)
+    mu = np.zeros((Mx * My, 1, 2))
+    sg = np.zeros((Mx * My, 1, 2))
+    mu[:, 0, 0] = np.repeat(mux, My)
+    mu[:, 0, 1] = np.tile(muy, Mx)
+    sg[:, 0, 0] = np.repeat(sgx, My)
+    sg[:, 0, 1] = np.tile(sgy, Mx)
+    fo = orc.eval_grid(n, lo, hi, model)
+    eo = orc.uniform_edges(fo, B)
+    Po, Zo = orc.propagate(n, lo, hi, orc.bins(fo, eo), B, mu, sg)
+    torch.cuda.synchronize()
+    return _cpu(P), _cpu(Z), Po, Zo[:, 0], mm, mu, sg
+
+
+def test_separable_grid64(vup, orc):
+    wl = workloads.grid64()
+    m = workloads.subgrid_midpoints(-3.0, 3.0, 16)
+    s = np.full(16, 0.25)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, wl.n, wl.lo, wl.hi, wl.model, wl.B, m, m, s, s,
+                                           "grid64")
+    _check_P(Pg, Po, 2e-5, "P separable vs oracle")
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+    Pgen, _ = vup.propagate(mm, mu, sg)
+    d = np.abs(Pg.astype(np.float64) - _cpu(Pgen)).sum(axis=1).max()
+    _say(f"  separable vs general kernel: max L1 {d:.2e}")
+    assert d <= 2e-5
+
+
+def test_separable_ragged_and_edge_cases(vup, orc):
+    rng = np.random.default_rng(50)
+    n, lo, hi = (61, 75), (-3.0, -2.0), (3.0, 2.5)
+    mux = rng.uniform(-3.2, 3.2, 37)
+    muy = rng.uniform(-2.2, 2.7, 21)
+    sgx = rng.uniform(0.05, 1.0, 37)
+    sgy = rng.uniform(0.05, 1.0, 21)
+    mux[3] = 30.0          # empty window on x: whole row block of k is zero
+    sgy[5] = 0.0           # invalid: NaN rows
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "timing2", 45, mux, muy, sgx,
+                                           sgy, "ragged")
+    k = np.arange(37 * 21)
+    bad = (k % 21) == 5
+    empty = (k // 21) == 3
+    ok = ~bad & ~empty
+    _check_P(Pg[ok], Po[ok], 2e-5, "P separable ragged")
+    assert np.isnan(Pg[bad]).all() and np.isnan(Zg[bad]).all()
+    assert (Pg[empty & ~bad] == 0).all() and (Zg[empty & ~bad] == 0).all()
