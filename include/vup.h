@@ -119,8 +119,12 @@ typedef struct vup_mm {
   size_t off_counts;    /* int64[B+1]       cells per bin; [B] = outside        */
   size_t off_offsets;   /* int64[B+1]       CSR row starts of the model matrix  */
   size_t off_perm;      /* int32[N]         cells sorted by bin (stable)        */
-  size_t off_scratch;   /* int32 scratch for the sort                           */
+  size_t off_scratch;   /* int32 scratch for the sort and the run count         */
   size_t off_counters;  /* int64[8]         device-side event counters          */
+  size_t off_runs;      /* uint32[]  runs of equal bin along the fastest axis:
+                           (first cell) | (4*bin << 16), one terminator per row */
+  size_t off_rowptr;    /* int32[rows+1]    first run of each row               */
+  size_t off_runidx;    /* uint16[rows*pitch] run of each cell, relative to row */
   uint64_t magic;
 } vup_mm;
 
@@ -287,6 +291,19 @@ int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
  *   [3] distributions whose every window is empty (vup_propagate).
  * ------------------------------------------------------------------------ */
 int vup_counters(const vup_mm* mm, void* stream, int64_t* out);
+
+/* --------------------------------------------------------------------------
+ * vup_set_sweep_mode - how vup_propagate (FP32 densities) accumulates over a
+ * model matrix: VUP_SWEEP_AUTO (default after vup_bin) uses the run form when
+ * the mean run of equal bin along the fastest axis is >= 3 cells, else the
+ * per-cell form; VUP_SWEEP_CELLS / VUP_SWEEP_RUNS force one form (both give
+ * the same results up to rounding). Stored in the workspace, enqueued on
+ * `stream`.
+ * ------------------------------------------------------------------------ */
+#define VUP_SWEEP_AUTO 0
+#define VUP_SWEEP_CELLS 1
+#define VUP_SWEEP_RUNS 2
+int vup_set_sweep_mode(const vup_mm* mm, int32_t mode, void* stream);
 
 /* last error message of the calling thread ("" if none). */
 const char* vup_last_error(void);

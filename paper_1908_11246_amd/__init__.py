@@ -66,7 +66,9 @@ class VupMM(ctypes.Structure):
                 ("off_binmap", ctypes.c_size_t), ("off_f32", ctypes.c_size_t),
                 ("off_counts", ctypes.c_size_t), ("off_offsets", ctypes.c_size_t),
                 ("off_perm", ctypes.c_size_t), ("off_scratch", ctypes.c_size_t),
-                ("off_counters", ctypes.c_size_t), ("magic", ctypes.c_uint64)]
+                ("off_counters", ctypes.c_size_t), ("off_runs", ctypes.c_size_t),
+                ("off_rowptr", ctypes.c_size_t), ("off_runidx", ctypes.c_size_t),
+                ("magic", ctypes.c_uint64)]
 
 
 _lib = None
@@ -97,6 +99,7 @@ def _load():
     lib.vup_ipsa_backward.argtypes = [_P(VupMM), _P(VupDists), _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]
     lib.vup_counters.argtypes = [_P(VupMM), _vp, _P(ctypes.c_int64)]
+    lib.vup_set_sweep_mode.argtypes = [_P(VupMM), ctypes.c_int32, _vp]
     lib.vup_separable_workspace_bytes.restype = ctypes.c_size_t
     lib.vup_separable_workspace_bytes.argtypes = [_P(VupMM), ctypes.c_int32, ctypes.c_int32]
     lib.vup_propagate_separable.argtypes = [_P(VupMM), _P(VupSepDists), _vp, ctypes.c_size_t, _vp,
@@ -234,9 +237,29 @@ class ModelMatrix:
         return self._view(self.mm.off_offsets, torch.int64, self.B + 1)
 
     @property
+    def runs(self) -> torch.Tensor:
+        """run records (first cell | 4*bin << 16) of every row, one terminator per row."""
+        n = int(self.mm.N + self.mm.rows)
+        return self._view(self.mm.off_runs, torch.int32, n)
+
+    @property
+    def rowptr(self) -> torch.Tensor:
+        return self._view(self.mm.off_rowptr, torch.int32, int(self.mm.rows) + 1)
+
+    @property
+    def runidx(self) -> torch.Tensor:
+        """run of each cell (padded rows), relative to its row's first run."""
+        return self._view(self.mm.off_runidx, torch.int16, int(self.mm.rows * self.mm.pitch))
+
+    @property
     def perm(self) -> torch.Tensor:
         """binned cell indices sorted by bin, increasing within a bin."""
         return self._view(self.mm.off_perm, torch.int32, int(self.mm.N))
+
+    def set_sweep_mode(self, mode: str = "auto"):
+        """FP32 propagation form: "auto", "cells" (per-cell) or "runs" (run form)."""
+        m = {"auto": 0, "cells": 1, "runs": 2}[mode]
+        _check(_load().vup_set_sweep_mode(ctypes.byref(self.mm), m, _vp(_stream())))
 
     def counters(self) -> dict:
         out = (ctypes.c_int64 * 4)()
@@ -249,11 +272,15 @@ def build_model_matrix(grid: VupGrid, f: torch.Tensor, edges: torch.Tensor,
     return ModelMatrix(grid, f, edges, want_bin)
 
 
-def windows(grid: VupGrid, mu, sigma, n_sigma: float = 4.0, device="cuda") -> torch.Tensor:
-    mu, sigma, _ = _norm_params(mu, sigma, None, device)
+def windows(grid: VupGrid, mu, sigma, n_sigma: float = 4.0, device="cuda",
+            weight=None) -> torch.Tensor:
+    """Integer truncation windows [K][C][d][2] (inclusive; empty = (0, -1))."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, device)
     K, C, D = mu.shape
+    if C > 1 and w is None:
+        w = torch.full((K, C), 1.0 / C, dtype=torch.float64, device=device)
     win = torch.empty((K, C, D, 2), dtype=torch.int32, device=device)
-    d = _dists(mu, sigma, None, n_sigma)
+    d = _dists(mu, sigma, w, n_sigma)
     _check(_load().vup_windows(ctypes.byref(grid), ctypes.byref(d), _ptr(win), _vp(_stream())))
     return win
 

@@ -284,6 +284,8 @@ __global__ __launch_bounds__(64) void k_scatter(BinArgs a, const int* __restrict
   }
 }
 
+hipError_t launch_runs(const vup_mm& mm, hipStream_t s);
+
 hipError_t launch_bin(const vup_mm& mm, const double* f, const double* edges, int32_t* bin,
                       hipStream_t s) {
   char* ws = static_cast<char*>(mm.ws);
@@ -315,7 +317,9 @@ hipError_t launch_bin(const vup_mm& mm, const double* f, const double* edges, in
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)L.nblk), dim3(64), (size_t)(mm.B + 1) * 4, s, a,
                      a.chunk_counts, reinterpret_cast<int32_t*>(ws + mm.off_perm));
-  return hipGetLastError();
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_runs(mm, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,6 +416,7 @@ bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
   const long long N = L.rows * nL;
   const long long padded = L.rows * L.pitch;
   L.nblk = (padded + kBinChunk - 1) / kBinChunk;
+  const long long rowblocks = L.rows * (L.pitch / 32);
   size_t o = 0;
   L.off_edges = o;
   o = align256(o + (size_t)(B + 1) * 8);
@@ -426,12 +431,155 @@ bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
   L.off_perm = o;
   o = align256(o + (size_t)N * 4);
   L.off_scratch = o;
-  o = align256(o + (size_t)(B + 1) * (size_t)L.nblk * 4);
+  const size_t sort_scratch = (size_t)(B + 1) * (size_t)L.nblk * 4;
+  const size_t run_scratch = (size_t)rowblocks * 4;
+  o = align256(o + (sort_scratch > run_scratch ? sort_scratch : run_scratch));
   L.off_counters = o;
   o = align256(o + 8 * 8);
+  L.off_runs = o;
+  o = align256(o + (size_t)(N + L.rows) * 4);
+  L.off_rowptr = o;
+  o = align256(o + (size_t)(L.rows + 1) * 4);
+  L.off_runidx = o;
+  o = align256(o + (size_t)padded * 2);
   L.bytes = o;
   *out = L;
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// runs of equal bin along the fastest axis (a run-length form of the model
+// matrix's rows). One thread per (row, 32-cell block).
+// ---------------------------------------------------------------------------
+struct RunArgs {
+  const uint16_t* binmap;
+  uint32_t* runs;
+  int* rowptr;
+  uint16_t* runidx;
+  int* blockcnt;       // [rows * nb] counts, then exclusive positions
+  unsigned long long* counters;
+  long long rows;
+  int nL, pitch, nb, none;
+};
+
+__device__ __forceinline__ bool run_start(const uint16_t* row, int c) {
+  return c == 0 || row[c] != row[c - 1];
+}
+
+__global__ __launch_bounds__(256) void k_runs_count(RunArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long real = 0;
+  if (t < a.rows * a.nb) {
+    const long long r = t / a.nb;
+    const int q = (int)(t - r * a.nb);
+    const uint16_t* row = a.binmap + r * a.pitch;
+    int cnt = 0;
+    for (int c = q * 32; c < q * 32 + 32 && c < a.nL; ++c) cnt += run_start(row, c) ? 1 : 0;
+    real = cnt;
+    if (q == a.nb - 1) ++cnt;  // terminator of the row
+    a.blockcnt[t] = cnt;
+  }
+  for (int o = 32; o > 0; o >>= 1) real += __shfl_xor(real, o, 64);
+  if ((threadIdx.x & 63) == 0 && real) atomicAdd(a.counters + kCntRuns, real);
+}
+
+// exclusive prefix sum of n ints in place, one workgroup
+__global__ __launch_bounds__(1024) void k_scan_excl(int* v, long long n, int* total) {
+  __shared__ long long part[1024];
+  const long long per = (n + 1023) / 1024;
+  const long long s0 = threadIdx.x * per < n ? threadIdx.x * per : n;
+  const long long s1 = s0 + per < n ? s0 + per : n;
+  long long sum = 0;
+  for (long long i = s0; i < s1; ++i) sum += v[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const long long x = part[t];
+      part[t] = run;
+      run += x;
+    }
+    *total = (int)run;
+  }
+  __syncthreads();
+  long long run = part[threadIdx.x];
+  for (long long i = s0; i < s1; ++i) {
+    const long long x = v[i];
+    v[i] = (int)run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_runs_fill(RunArgs a) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.rows * a.nb) return;
+  const long long r = t / a.nb;
+  const int q = (int)(t - r * a.nb);
+  const uint16_t* row = a.binmap + r * a.pitch;
+  const int rowstart = a.blockcnt[r * a.nb];
+  int pos = a.blockcnt[t];
+  if (q == 0) a.rowptr[r] = rowstart;
+  int cur = pos - 1 - rowstart;  // run holding the cell before this block
+  for (int c = q * 32; c < q * 32 + 32; ++c) {
+    if (c < a.nL) {
+      if (run_start(row, c)) {
+        a.runs[pos] = (uint32_t)c | ((uint32_t)row[c] << 16);
+        cur = pos - rowstart;
+        ++pos;
+      }
+    } else if (c == a.nL) {
+      // terminator: first column past the row, no bin
+      a.runs[pos] = (uint32_t)a.nL | ((uint32_t)a.none << 16);
+      cur = pos - rowstart;
+      ++pos;
+    }
+    a.runidx[r * a.pitch + c] = (uint16_t)cur;
+  }
+  if (q == a.nb - 1 && a.nL == a.nb * 32) {
+    // row length is a multiple of 32: terminator after the last block
+    a.runs[pos] = (uint32_t)a.nL | ((uint32_t)a.none << 16);
+  }
+}
+
+__global__ void k_rowptr_end(int* rowptr, long long rows, const int* total) {
+  if (threadIdx.x == 0) rowptr[rows] = *total;
+}
+
+__global__ void k_set_mode(unsigned long long* counters, int mode) {
+  if (threadIdx.x == 0) counters[kCntMode] = (unsigned long long)mode;
+}
+
+hipError_t launch_set_mode(const vup_mm& mm, int mode, hipStream_t s) {
+  unsigned long long* c =
+      reinterpret_cast<unsigned long long*>(static_cast<char*>(mm.ws) + mm.off_counters);
+  hipLaunchKernelGGL(k_set_mode, dim3(1), dim3(64), 0, s, c, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_runs(const vup_mm& mm, hipStream_t s) {
+  char* ws = static_cast<char*>(mm.ws);
+  RunArgs a{};
+  a.binmap = reinterpret_cast<const uint16_t*>(ws + mm.off_binmap);
+  a.runs = reinterpret_cast<uint32_t*>(ws + mm.off_runs);
+  a.rowptr = reinterpret_cast<int*>(ws + mm.off_rowptr);
+  a.runidx = reinterpret_cast<uint16_t*>(ws + mm.off_runidx);
+  a.blockcnt = reinterpret_cast<int*>(ws + mm.off_scratch);
+  a.counters = reinterpret_cast<unsigned long long*>(ws + mm.off_counters);
+  a.rows = mm.rows;
+  a.nL = mm.grid.n[mm.grid.ndim - 1];
+  a.pitch = mm.pitch;
+  a.nb = mm.pitch / 32;
+  a.none = 4 * mm.B;
+  const long long n = a.rows * a.nb;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_runs_count, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, a.blockcnt, n,
+                     reinterpret_cast<int*>(a.counters + kCntScratch));
+  hipLaunchKernelGGL(k_runs_fill, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rowptr_end, dim3(1), dim3(64), 0, s, a.rowptr, a.rows,
+                     reinterpret_cast<const int*>(a.counters + kCntScratch));
+  return hipGetLastError();
 }
 
 }  // namespace vup

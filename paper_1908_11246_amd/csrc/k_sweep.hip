@@ -36,6 +36,12 @@ struct SweepArgs {
   unsigned long long* counters;
   SweepLayout L;
   long long kpx;  // distributions per XCD slot (block -> k mapping)
+  // run-length form of the model matrix (propagation, FP32)
+  const uint32_t* __restrict__ runs;
+  const int* __restrict__ rowptr;
+  const uint16_t* __restrict__ runidx;
+  long long ncells;
+  int allow_runs;
   // propagate
   float* P;
   double* Z;
@@ -274,27 +280,39 @@ struct PropScales {
   float srow[3];
   float scol[3];
   double unscale[9];  // 1 / scale of each class (FP64)
+  int peak;           // run form: index of the largest fastest-axis factor
 };
 
 template <int PREC>
 __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
-                                            int sw, double* red, PropScales* ps) {
+                                            int sw, double* red, PropScales* ps, bool runmode) {
   const int D = a.g.ndim;
   const float* tabL = smem + a.L.tab_off[D - 1];
-  // column classes: by the largest factor of each strip
   double cm[3] = {0.0, 0.0, 0.0};
-  for (int st = threadIdx.x; st < ns; st += kThreads) {
-    float gmax = 0.0f;
-    double sum = 0.0;
-    for (int j = 0; j < sw; ++j) {
-      const float g = tabL[st * sw + j];
-      gmax = fmaxf(gmax, g);
-      sum += (double)g;
+  if (!runmode) {
+    // column classes: by the largest factor of each strip
+    for (int st = threadIdx.x; st < ns; st += kThreads) {
+      float gmax = 0.0f;
+      double sum = 0.0;
+      for (int j = 0; j < sw; ++j) {
+        const float g = tabL[st * sw + j];
+        gmax = fmaxf(gmax, g);
+        sum += (double)g;
+      }
+      const int cc = mag_class(gmax);
+      cm[0] += cc == 0 ? sum : 0.0;
+      cm[1] += cc == 1 ? sum : 0.0;
+      cm[2] += cc == 2 ? sum : 0.0;
     }
-    const int cc = mag_class(gmax);
-    cm[0] += cc == 0 ? sum : 0.0;
-    cm[1] += cc == 1 ? sum : 0.0;
-    cm[2] += cc == 2 ? sum : 0.0;
+  } else {
+    // runs are classed by their largest factor, so a class-c run holds only
+    // columns below the class ceiling: bound by the sum of all such columns
+    for (int j = threadIdx.x; j < ns * sw; j += kThreads) {
+      const float g = tabL[j];
+      cm[0] += (double)g;
+      cm[1] += g < kClassT1 ? (double)g : 0.0;
+      cm[2] += g < kClassT2 ? (double)g : 0.0;
+    }
   }
   double colmass[3];
 #pragma unroll
@@ -419,6 +437,161 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Run form (FP32 densities): along the fastest axis the model matrix is a
+// sequence of runs of equal bin, and the density is separable, so a run's
+// mass is go * (G[e] - G[s]) with G the FP64 prefix sums of the fastest-axis
+// factors. Each lane handles one run (16 lanes per row); one integer atomic
+// then carries a whole run instead of one cell.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void build_prefix(const SweepArgs& a, float* smem, int len, double* red2,
+                                             int* pk) {
+  // G[0] = 0, G[j+1] = G[j] + tab_L[j] in FP64; also the index of the
+  // largest factor (smallest index among equal maxima)
+  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  double* G = reinterpret_cast<double*>(smem + a.L.g_off);
+  const int per = (len + kThreads - 1) / kThreads;
+  const int j0 = threadIdx.x * per < len ? threadIdx.x * per : len;
+  const int j1 = j0 + per < len ? j0 + per : len;
+  double sum = 0.0;
+  float best = -1.0f;
+  int bidx = 0x7fffffff;
+  for (int j = j0; j < j1; ++j) {
+    const float g = tabL[j];
+    sum += (double)g;
+    if (g > best) {
+      best = g;
+      bidx = j;
+    }
+  }
+  red2[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int t = 0; t < kThreads; ++t) {
+      const double x = red2[t];
+      red2[t] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  double run = red2[threadIdx.x];
+  if (threadIdx.x == 0) G[0] = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    run += (double)tabL[j];
+    G[j + 1] = run;
+  }
+  // argmax: (value, -index) maximum over the block
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bidx, o, 64);
+    if (ob > best || (ob == best && oi < bidx)) {
+      best = ob;
+      bidx = oi;
+    }
+  }
+  __syncthreads();
+  float* rb = reinterpret_cast<float*>(red2);
+  int* ri = reinterpret_cast<int*>(red2) + kWaves;
+  if ((threadIdx.x & 63) == 0) {
+    rb[threadIdx.x >> 6] = best;
+    ri[threadIdx.x >> 6] = bidx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = rb[0];
+    int i = ri[0];
+    for (int wv = 1; wv < kWaves; ++wv)
+      if (rb[wv] > b || (rb[wv] == b && ri[wv] < i)) {
+        b = rb[wv];
+        i = ri[wv];
+      }
+    *pk = i;
+  }
+  __syncthreads();
+}
+
+// row table of the run form: (go * srow[class], first run, end run, class)
+__device__ __forceinline__ void build_rows_runs(const SweepArgs& a, float* smem, const Win& w,
+                                                long long r0, int rc, const PropScales* ps,
+                                                int loL, int hiL) {
+  const int D = a.g.ndim;
+  float4* rt = reinterpret_cast<float4*>(smem + a.L.row_off);
+  for (int r = threadIdx.x; r < rc; r += kThreads) {
+    long long t = r0 + r;
+    float go = 1.0f;
+    long long off = 0;
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      if (d <= D - 2) {
+        const int i = (int)(t % w.W[d]);
+        t /= w.W[d];
+        go *= smem[a.L.tab_off[d] + i];
+        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
+      }
+    }
+    const long long gr = off / a.g.pitch;  // grid row
+    const int base = a.rowptr[gr];
+    const int r_a = base + (int)a.runidx[off + loL];
+    const int r_b = base + (int)a.runidx[off + hiL] + 1;
+    const int cls = a.L.ncls > 1 ? mag_class(go) : 0;
+    rt[r] = make_float4(go * ps->srow[cls], __int_as_float(r_a), __int_as_float(r_b),
+                        __int_as_float(cls));
+  }
+}
+
+// One row per 16-lane group; the row's m runs are split into contiguous
+// chunks of ceil(m/16) per lane, whose records (and the next record, for the
+// end column) are loaded together before any is used.
+__device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int rc, int colbase,
+                                          int loL, int hiL, int pk, const PropScales* ps) {
+  const int grp = threadIdx.x >> 4;
+  const int l = threadIdx.x & 15;
+  const float4* rt = reinterpret_cast<const float4*>(smem + a.L.row_off);
+  const double* G = reinterpret_cast<const double*>(smem + a.L.g_off);
+  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  const int strideb = a.L.hist_stride * 4;
+  const int rcstep = 3 * strideb;  // one copy per class in the run form
+  char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off);
+  const float sc0 = ps->scol[0], sc1 = ps->scol[1], sc2 = ps->scol[2];
+  const int hi1 = hiL + 1;
+  for (int r = grp; r < rc; r += kThreads / 16) {
+    const float4 t = rt[r];
+    const int ra = __float_as_int(t.y), rb = __float_as_int(t.z);
+    char* lr = hbase + (a.L.ncls > 1 ? __float_as_int(t.w) : 0) * rcstep;
+    const int per = (rb - ra + 15) >> 4;
+    int q = ra + l * per;
+    const int qe = min(q + per, rb);
+    while (q < qe) {
+      uint32_t rec[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) rec[i] = (q + i <= qe) ? a.runs[q + i] : 0u;
+      int s = ((int)(rec[0] & 0xFFFFu) > loL ? (int)(rec[0] & 0xFFFFu) : loL) - colbase;
+      double gs = G[s];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (q + i < qe) {
+          const int ce = (int)(rec[i + 1] & 0xFFFFu);
+          const int e = (ce < hi1 ? ce : hi1) - colbase;
+          const double ge = G[e];
+          const float val = (float)(ge - gs);
+          float gm = fmaxf(tabL[s], tabL[e - 1]);
+          if (s <= pk && pk < e) gm = 1.0f;
+          const int cc = a.L.ncls > 1 ? mag_class(gm) : 0;
+          const float scol = cc == 0 ? sc0 : (cc == 1 ? sc1 : sc2);
+          const float u = ((float)(l + 16 * i) + 0.5f) * (1.0f / 128.0f);
+          const float v = fmaf(val, t.x * scol, u - floorf(u));
+          uint32_t* slot = reinterpret_cast<uint32_t*>(lr + cc * strideb + (rec[i] >> 16));
+          __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          s = e;
+          gs = ge;
+        }
+      }
+      q += 8;
+    }
+  }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
   extern __shared__ float smem[];
@@ -428,13 +601,25 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
   const int B = a.B;
   const int nslots = B + 1;
   const int ncls = a.L.ncls;
-  const int cpc = a.L.cpw;
   double* red = reinterpret_cast<double*>(smem + a.L.red_off);
   PropScales* ps = reinterpret_cast<PropScales*>(red + 16);
   const uint32_t* hist = reinterpret_cast<const uint32_t*>(smem + a.L.hist_off);
   float* Pk = a.P + k * (long long)B;
   bool anybad = false;
   bool written = false;  // row k holds a partial mixture
+  // run form: FP32 densities and a model matrix whose runs along the fastest
+  // axis are at least kRunMinLength cells long on average
+  bool runmode = false;
+  if constexpr (PREC == VUP_FP32) {
+    const unsigned long long mode = a.counters[kCntMode];
+    const unsigned long long nruns = a.counters[kCntRuns];
+    runmode = a.allow_runs && nruns > 0 &&
+              (mode == VUP_SWEEP_RUNS ||
+               (mode == VUP_SWEEP_AUTO && (long long)nruns * kRunMinLength <= a.ncells));
+  }
+  // the run form keeps one histogram copy per class (its prefix tables use
+  // the space of the others)
+  const int cpc = runmode ? 1 : a.L.cpw;
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
     const Win w = make_win(a, kc);
@@ -457,16 +642,26 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
     for (int i = threadIdx.x; i < ncls * cpc * a.L.hist_stride; i += kThreads)
       smem[a.L.hist_off + i] = 0.0f;
     __syncthreads();
-    prop_scales<PREC>(a, smem, w, ns, sw, red, ps);
+    prop_scales<PREC>(a, smem, w, ns, sw, red, ps, runmode);
+    int pk = 0;
+    if (runmode) {
+      build_prefix(a, smem, ns * sw, reinterpret_cast<double*>(smem + a.L.scan_off), &ps->peak);
+      pk = ps->peak;
+    }
     for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
       const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
       __syncthreads();
-      build_rows_prop(a, smem, w, r0, rc, ps);
+      if (runmode) build_rows_runs(a, smem, w, r0, rc, ps, loL, loL + WL - 1);
+      else build_rows_prop(a, smem, w, r0, rc, ps);
       __syncthreads();
-      switch (sw) {
-        case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
-        case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
-        default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
+      if (runmode) {
+        prop_runs(a, smem, rc, colbase, loL, loL + WL - 1, pk, ps);
+      } else {
+        switch (sw) {
+          case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
+          case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
+          default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
+        }
       }
     }
     __syncthreads();
@@ -857,6 +1052,8 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     L.trow_off = off;
     off += 4 * kRowChunk;
   }
+  L.g_off = -1;
+  L.scan_off = -1;
   L.hist_off = off;
   L.hist_stride = 0;
   L.cpw = 0;
@@ -865,23 +1062,33 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     // stride = 1 mod 32 so consecutive copies shift banks by one
     const int stride = round_up(B + 1, 32) + 1;
     L.hist_stride = stride;
+    // the run form keeps one copy per class and places the FP64 prefix sums
+    // of the fastest-axis factors (and their scan scratch) behind it
+    const int gfl = 2 * (L.cap[D - 1] + 2) + 2 * kThreads + 2;
     const int budget = 48 * 1024 / 4 - 64;
     const int opts[5][2] = {{9, 2}, {9, 1}, {1, 4}, {1, 2}, {1, 1}};
+    auto need = [&](int i) {
+      const int h2 = opts[i][0] * opts[i][1] * stride;
+      const int h1 = round_up(opts[i][0] * stride, 2) + gfl;
+      return h2 > h1 ? h2 : h1;
+    };
     int pick = 4;
     for (int i = 0; i < 5; ++i)
-      if (off + opts[i][0] * opts[i][1] * stride <= budget) {
+      if (off + need(i) <= budget) {
         pick = i;
         break;
       }
     if (pick == 4)  // nothing fits the occupancy budget: take the richest that fits at all
       for (int i = 0; i < 5; ++i)
-        if (off + opts[i][0] * opts[i][1] * stride <= 160 * 1024 / 4 - 64) {
+        if (off + need(i) <= 160 * 1024 / 4 - 64) {
           pick = i;
           break;
         }
     L.ncls = opts[pick][0];
     L.cpw = opts[pick][1];
-    off += L.ncls * L.cpw * stride;
+    L.g_off = off + round_up(L.ncls * stride, 2);
+    L.scan_off = L.g_off + 2 * (L.cap[D - 1] + 2);
+    off += need(pick);
   } else if (kind == kSweepBackward) {
     off += round_up(B + 1, 4);
   }
@@ -936,6 +1143,11 @@ static SweepArgs base_args(const vup_mm& mm, const vup_dists& d, SweepKind kind)
   a.counters = reinterpret_cast<unsigned long long*>(static_cast<char*>(mm.ws) + mm.off_counters);
   sweep_layout(mm.grid, mm.B, kind, &a.L);
   a.kpx = (d.K + 7) / 8;
+  a.runs = reinterpret_cast<const uint32_t*>(ws + mm.off_runs);
+  a.rowptr = reinterpret_cast<const int*>(ws + mm.off_rowptr);
+  a.runidx = reinterpret_cast<const uint16_t*>(ws + mm.off_runidx);
+  a.ncells = mm.N;
+  a.allow_runs = mm.grid.n[mm.grid.ndim - 1] <= 65534;
   return a;
 }
 

@@ -168,6 +168,9 @@ int vup_bin(const vup_grid* g, const double* f, const double* edges, int32_t B, 
   mm.off_perm = L.off_perm;
   mm.off_scratch = L.off_scratch;
   mm.off_counters = L.off_counters;
+  mm.off_runs = L.off_runs;
+  mm.off_rowptr = L.off_rowptr;
+  mm.off_runidx = L.off_runidx;
   mm.magic = vup::kMagic;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemsetAsync(static_cast<char*>(ws) + L.off_counters, 0, 64, s);
@@ -272,6 +275,14 @@ int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
   return launched(vup::launch_backward(*mm, *d, P, mean_hist, g_var, g_ent, g_mu, g_sigma, g_weight,
                                        (hipStream_t)stream),
                   "vup_ipsa_backward");
+}
+
+int vup_set_sweep_mode(const vup_mm* mm, int32_t mode, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (mode < VUP_SWEEP_AUTO || mode > VUP_SWEEP_RUNS) return fail(VUP_EINVAL, "unknown mode %d", mode);
+  if ((r = check_device())) return r;
+  return launched(vup::launch_set_mode(*mm, mode, (hipStream_t)stream), "vup_set_sweep_mode");
 }
 
 int vup_counters(const vup_mm* mm, void* stream, int64_t* out) {

@@ -17,7 +17,20 @@ constexpr int kMaxSW = 16;        // widest strip of the fastest axis
 constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
 
 // counters stored in the workspace (int64 each)
-enum Counter { kCntOutside = 0, kCntBadEdges = 1, kCntBadParam = 2, kCntEmpty = 3 };
+// [4]: number of runs of equal bin along the fastest axis (set by vup_bin,
+// not cleared by vup_counters); the propagation uses the run form when the
+// mean run length is at least kRunMinLength cells.
+// [5]: scratch of the run construction; [6]: sweep mode (VUP_SWEEP_*).
+enum Counter {
+  kCntOutside = 0,
+  kCntBadEdges = 1,
+  kCntBadParam = 2,
+  kCntEmpty = 3,
+  kCntRuns = 4,
+  kCntScratch = 5,
+  kCntMode = 6
+};
+constexpr int kRunMinLength = 3;
 
 // grid + bin-map description passed by value to every sweep kernel
 struct GridDev {

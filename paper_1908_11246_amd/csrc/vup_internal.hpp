@@ -26,6 +26,8 @@ struct SweepLayout {
   int cpw;          // histogram copies per magnitude class
   int ncls;         // magnitude classes (9, or 1 when LDS is short)
   int red_off;      // double scratch
+  int g_off;        // FP64 prefix sums of the fastest-axis factors (propagate)
+  int scan_off;     // FP64 scan scratch, kThreads entries (propagate)
   size_t bytes;
 };
 
@@ -51,6 +53,7 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            const double* mean_hist, const double* g_var, const double* g_ent,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);
 
+hipError_t launch_set_mode(const vup_mm& mm, int mode, hipStream_t s);
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My);
 hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x,
                             const double* mu_y, const double* sg_x, const double* sg_y,
@@ -62,7 +65,7 @@ struct WsLayout {
   int64_t rows;
   int64_t nblk;  // chunks of kBinChunk padded positions
   size_t off_edges, off_binmap, off_f32, off_counts, off_offsets, off_perm, off_scratch,
-      off_counters, bytes;
+      off_counters, off_runs, off_rowptr, off_runidx, bytes;
 };
 bool ws_layout(const vup_grid& g, int B, WsLayout* out);
 

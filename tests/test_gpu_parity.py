@@ -457,3 +457,64 @@ def test_separable_ragged_and_edge_cases(vup, orc):
     _check_P(Pg[ok], Po[ok], 2e-5, "P separable ragged")
     assert np.isnan(Pg[bad]).all() and np.isnan(Zg[bad]).all()
     assert (Pg[empty & ~bad] == 0).all() and (Zg[empty & ~bad] == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# run form of the model matrix and the two accumulation forms
+# ---------------------------------------------------------------------------
+def _runs_reference(b2, B):
+    """runs of equal bin along each row: (first cell, 4*bin or 4*B), terminator."""
+    recs, ptr, idx = [], [0], []
+    none = 4 * B
+    for row in b2:
+        code = np.where(row >= 0, 4 * row, none)
+        starts = np.nonzero(np.r_[True, code[1:] != code[:-1]])[0]
+        for s0 in starts:
+            recs.append(int(s0) | (int(code[s0]) << 16))
+        recs.append(len(row) | (none << 16))
+        ptr.append(len(recs))
+        idx.append(np.searchsorted(starts, np.arange(len(row)), side="right") - 1)
+    return np.array(recs, dtype=np.int64), np.array(ptr), idx
+
+
+@pytest.mark.parametrize("n", [(64, 64), (37, 53), (9, 96), (5, 7, 33)])
+def test_run_structure_bitexact(vup, orc, n):
+    d = len(n)
+    lo, hi = (-3.0,) * d, (3.0,) * d
+    model = {2: "timing2", 3: "damped3"}[d]
+    fo = orc.eval_grid(n, lo, hi, model)
+    B = 23
+    eo = orc.uniform_edges(fo, B)
+    bo = orc.bins(fo, eo)
+    g = vup.make_grid(n, lo, hi)
+    mm = vup.build_model_matrix(g, torch.from_numpy(fo).to(DEV), torch.from_numpy(eo).to(DEV))
+    recs, ptr, idx = _runs_reference(bo.reshape(-1, n[-1]), B)
+    got = _cpu(mm.runs).astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(_cpu(mm.rowptr), ptr)
+    assert np.array_equal(got[:len(recs)], recs)
+    ri = _cpu(mm.runidx).astype(np.int64).reshape(-1, mm.mm.pitch)
+    for r, ref in enumerate(idx):
+        assert np.array_equal(ri[r, :n[-1]], ref)
+
+
+def test_run_and_cell_forms_agree(vup, orc):
+    for wl in (workloads.grid64(), workloads.grid1024().subset(workloads.sample_indices(65536, 40, 9)),
+               workloads.random_workload("runs2d", (57, 300), (-3, -3), (3, 3), "sincos2", 40, 60, 2,
+                                         (0.05, 0.9), seed=33),
+               workloads.random_workload("runs3d", (20, 17, 90), (-2, -2, -2), (2, 2, 2), "damped3",
+                                         30, 40, 1, (0.1, 0.8), seed=34)):
+        f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+        e = orc.uniform_edges(f, wl.B)
+        Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(f, e), wl.B, wl.mu, wl.sigma, wl.weight)
+        g = vup.make_grid(wl.n, wl.lo, wl.hi)
+        fg = vup.eval_grid(g, wl.model)
+        mm = vup.build_model_matrix(g, fg, vup.uniform_edges(fg, wl.B))
+        out = {}
+        for mode in ("cells", "runs"):
+            mm.set_sweep_mode(mode)
+            P, Z = vup.propagate(mm, wl.mu, wl.sigma, wl.weight)
+            out[mode] = _cpu(P)
+            _check_P(out[mode], Po, 2e-5, f"{wl.name} {mode} form")
+        mm.set_sweep_mode("auto")
+        d = np.abs(out["runs"].astype(np.float64) - out["cells"]).sum(axis=1).max()
+        _say(f"  runs vs cells: max L1 {d:.2e}")
