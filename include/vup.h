@@ -125,6 +125,8 @@ typedef struct vup_mm {
                            (first cell) | (4*bin << 16), one terminator per row */
   size_t off_rowptr;    /* int32[rows+1]    first run of each row               */
   size_t off_runidx;    /* uint16[rows*pitch] run of each cell, relative to row */
+  int32_t sweep;        /* form of vup_propagate's FP32 sweep (VUP_SWEEP_*)     */
+  int32_t reserved;
   uint64_t magic;
 } vup_mm;
 
@@ -294,16 +296,21 @@ int vup_counters(const vup_mm* mm, void* stream, int64_t* out);
 
 /* --------------------------------------------------------------------------
  * vup_set_sweep_mode - how vup_propagate (FP32 densities) accumulates over a
- * model matrix: VUP_SWEEP_AUTO (default after vup_bin) uses the run form when
- * the mean run of equal bin along the fastest axis is >= 3 cells, else the
- * per-cell form; VUP_SWEEP_CELLS / VUP_SWEEP_RUNS force one form (both give
- * the same results up to rounding). Stored in the workspace, enqueued on
- * `stream`.
+ * model matrix: per cell, or per run of equal bin along the fastest axis
+ * (both give the same results up to rounding).
+ *   VUP_SWEEP_CELLS / VUP_SWEEP_RUNS force one form; enqueued on `stream`.
+ *   VUP_SWEEP_AUTO synchronises `stream`, reads the run statistics of the
+ *   model matrix and fixes the form: runs when the mean run is at least 3
+ *   cells, else cells. It is meant for set-up time.
+ * Right after vup_bin, mm->sweep is VUP_SWEEP_AUTO and unresolved: each
+ * vup_propagate then enqueues both forms and the device picks one by the
+ * same rule (the other returns at once). The run form needs a fastest axis
+ * of at most 65534 cells and fewer than 2^30 cells; otherwise cells are used.
  * ------------------------------------------------------------------------ */
 #define VUP_SWEEP_AUTO 0
 #define VUP_SWEEP_CELLS 1
 #define VUP_SWEEP_RUNS 2
-int vup_set_sweep_mode(const vup_mm* mm, int32_t mode, void* stream);
+int vup_set_sweep_mode(vup_mm* mm, int32_t mode, void* stream);
 
 /* last error message of the calling thread ("" if none). */
 const char* vup_last_error(void);

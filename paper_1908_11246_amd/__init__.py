@@ -68,6 +68,7 @@ class VupMM(ctypes.Structure):
                 ("off_perm", ctypes.c_size_t), ("off_scratch", ctypes.c_size_t),
                 ("off_counters", ctypes.c_size_t), ("off_runs", ctypes.c_size_t),
                 ("off_rowptr", ctypes.c_size_t), ("off_runidx", ctypes.c_size_t),
+                ("sweep", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("magic", ctypes.c_uint64)]
 
 
@@ -201,7 +202,7 @@ class ModelMatrix:
     reused for every propagated distribution. Owns its device workspace."""
 
     def __init__(self, grid: VupGrid, f: torch.Tensor, edges: torch.Tensor,
-                 want_bin: bool = True):
+                 want_bin: bool = True, resolve_sweep: bool = True):
         lib_ = _load()
         self.grid = grid
         self.B = edges.numel() - 1
@@ -216,6 +217,10 @@ class ModelMatrix:
         _check(lib_.vup_bin(ctypes.byref(grid), _ptr(f), _ptr(edges), self.B, _ptr(self.bin),
                             _vp(self._ws_ptr), nbytes, ctypes.byref(self.mm), _vp(_stream())))
         self.device = f.device
+        if resolve_sweep:
+            # fix the FP32 sweep form now (one stream sync at set-up), so that
+            # each propagation launches only that form
+            self.set_sweep_mode("auto")
 
     def _view(self, off, dtype, count):
         start = self._ws_ptr - self.ws.data_ptr() + off
@@ -256,8 +261,14 @@ class ModelMatrix:
         """binned cell indices sorted by bin, increasing within a bin."""
         return self._view(self.mm.off_perm, torch.int32, int(self.mm.N))
 
+    @property
+    def sweep(self) -> str:
+        """FP32 propagation form in use: "auto" (unresolved), "cells" or "runs"."""
+        return {0: "auto", 1: "cells", 2: "runs"}[self.mm.sweep]
+
     def set_sweep_mode(self, mode: str = "auto"):
-        """FP32 propagation form: "auto", "cells" (per-cell) or "runs" (run form)."""
+        """FP32 propagation form: "auto" (resolve from the run statistics; syncs),
+        "cells" (per-cell) or "runs" (run form)."""
         m = {"auto": 0, "cells": 1, "runs": 2}[mode]
         _check(_load().vup_set_sweep_mode(ctypes.byref(self.mm), m, _vp(_stream())))
 
@@ -268,8 +279,8 @@ class ModelMatrix:
 
 
 def build_model_matrix(grid: VupGrid, f: torch.Tensor, edges: torch.Tensor,
-                       want_bin: bool = True) -> ModelMatrix:
-    return ModelMatrix(grid, f, edges, want_bin)
+                       want_bin: bool = True, resolve_sweep: bool = True) -> ModelMatrix:
+    return ModelMatrix(grid, f, edges, want_bin, resolve_sweep)
 
 
 def windows(grid: VupGrid, mu, sigma, n_sigma: float = 4.0, device="cuda",

@@ -437,7 +437,9 @@ bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
   L.off_counters = o;
   o = align256(o + 8 * 8);
   L.off_runs = o;
-  o = align256(o + (size_t)(N + L.rows) * 4);
+  // up to one record per cell plus a terminator per row, and 128 records of
+  // padding: the run sweep reads up to 79 records past a row segment's end
+  o = align256(o + (size_t)(N + L.rows + 128) * 4);
   L.off_rowptr = o;
   o = align256(o + (size_t)(L.rows + 1) * 4);
   L.off_runidx = o;

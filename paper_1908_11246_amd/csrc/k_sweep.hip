@@ -141,10 +141,10 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
   for (int d = 0; d < 3; ++d) {
     if (d + 1 < D) {
       float* tab = smem + a.L.tab_off[d];
-      const double mu = a.d.mu[kc * D + d], sg = a.d.sigma[kc * D + d];
+      const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
       for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
         const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
-        tab[i] = gauss_factor(x, mu, sg);
+        tab[i] = gauss_factor_r(x, mu, rsig);
       }
     }
   }
@@ -152,13 +152,13 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
   int loL, WL;
   last_axis(w, D, loL, WL);
   float* tab = smem + a.L.tab_off[L];
-  const double mu = a.d.mu[kc * D + L], sg = a.d.sigma[kc * D + L];
+  const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
   for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
     const int j = colbase + jj;
     float v = 0.0f;
     if (j >= loL && j < loL + WL) {
       const double x = cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], j);
-      v = gauss_factor(x, mu, sg);
+      v = gauss_factor_r(x, mu, rsig);
     }
     tab[jj] = v;
   }
@@ -173,24 +173,24 @@ __device__ __forceinline__ void build_rows(const SweepArgs& a, float* smem, cons
   float2* rt = reinterpret_cast<float2*>(smem + a.L.row_off);
   float4* tt = trow ? reinterpret_cast<float4*>(smem + a.L.trow_off) : nullptr;
   for (int r = threadIdx.x; r < rc; r += kThreads) {
-    long long t = r0 + r;
+    int t = (int)r0 + r;
     float go = 1.0f;
-    long long off = 0;
+    int off = 0;  // the padded bin map has fewer than 2^31 elements
     float tv[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int d = 2; d >= 0; --d) {
       if (d <= D - 2) {
-        const int i = (int)(t % w.W[d]);
-        t /= w.W[d];
+        const int i = d == 0 ? t : t % w.W[d];
+        if (d > 0) t /= w.W[d];
         go *= smem[a.L.tab_off[d] + i];
-        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
+        off += (w.lo[d] + i) * (int)a.g.rowstride[d];
         if (trow) {
           const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
           tv[d] = (float)((x - a.d.mu[kc * D + d]) / a.d.sigma[kc * D + d]);
         }
       }
     }
-    rt[r] = make_float2(go, __int_as_float((int)off));
+    rt[r] = make_float2(go, __int_as_float(off));
     if (trow) tt[r] = make_float4(tv[0], tv[1], tv[2], 0.0f);
   }
 }
@@ -228,24 +228,6 @@ __device__ __forceinline__ uint32_t map_at(const MapVec<SW>& m, int j) {
 // ===========================================================================
 // propagation
 // ===========================================================================
-// Sum of the tabulated per-axis factors of the current window, multiplied
-// over the axes (FP64): the total weight of the separable truncated density.
-__device__ __forceinline__ double table_mass(const SweepArgs& a, const float* smem, const Win& w,
-                                             int ns, int sw, double* red) {
-  const int D = a.g.ndim;
-  double Z = 1.0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    if (d < D) {
-      double zp = 0.0;
-      const int cnt = (d + 1 < D) ? w.W[d] : ns * sw;
-      for (int i = threadIdx.x; i < cnt; i += kThreads) zp += (double)smem[a.L.tab_off[d] + i];
-      Z *= block_sum(zp, red);
-    }
-  }
-  return Z;
-}
-
 // ---------------------------------------------------------------------------
 // Fixed-point histogram accumulation.
 // The density of a cell is the product go * gl of its row factor and its
@@ -275,49 +257,29 @@ __host__ __device__ constexpr double prec_qfac() {
          : PREC == VUP_FP8E4M3 ? 1.125 : 1.0 + 1.0 / 1048576;
 }
 
-// per-component scales shared by all threads (LDS): srow[3], scol[3], inv[9]
+// per-component scales shared by all threads (LDS)
 struct PropScales {
   float srow[3];
   float scol[3];
   double unscale[9];  // 1 / scale of each class (FP64)
-  int peak;           // run form: index of the largest fastest-axis factor
 };
 
-template <int PREC>
-__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
-                                            int sw, double* red, PropScales* ps, bool runmode) {
+// the model matrix's run form is used for this propagation (FP32 densities):
+// forced by the sweep mode, or chosen when runs along the fastest axis are at
+// least kRunMinLength cells long on average
+__device__ __forceinline__ bool runs_chosen(const SweepArgs& a) {
+  if (!a.allow_runs) return false;
+  const unsigned long long mode = a.counters[kCntMode];
+  const unsigned long long nruns = a.counters[kCntRuns];
+  return nruns > 0 && (mode == VUP_SWEEP_RUNS ||
+                       (mode == VUP_SWEEP_AUTO && (long long)nruns * kRunMinLength <= a.ncells));
+}
+
+// Row factor sum bound of the window: product over the slower axes of their
+// factor table sums (FP64).
+__device__ __forceinline__ double row_mass(const SweepArgs& a, const float* smem, const Win& w,
+                                           double* red) {
   const int D = a.g.ndim;
-  const float* tabL = smem + a.L.tab_off[D - 1];
-  double cm[3] = {0.0, 0.0, 0.0};
-  if (!runmode) {
-    // column classes: by the largest factor of each strip
-    for (int st = threadIdx.x; st < ns; st += kThreads) {
-      float gmax = 0.0f;
-      double sum = 0.0;
-      for (int j = 0; j < sw; ++j) {
-        const float g = tabL[st * sw + j];
-        gmax = fmaxf(gmax, g);
-        sum += (double)g;
-      }
-      const int cc = mag_class(gmax);
-      cm[0] += cc == 0 ? sum : 0.0;
-      cm[1] += cc == 1 ? sum : 0.0;
-      cm[2] += cc == 2 ? sum : 0.0;
-    }
-  } else {
-    // runs are classed by their largest factor, so a class-c run holds only
-    // columns below the class ceiling: bound by the sum of all such columns
-    for (int j = threadIdx.x; j < ns * sw; j += kThreads) {
-      const float g = tabL[j];
-      cm[0] += (double)g;
-      cm[1] += g < kClassT1 ? (double)g : 0.0;
-      cm[2] += g < kClassT2 ? (double)g : 0.0;
-    }
-  }
-  double colmass[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) colmass[c] = block_sum(cm[c], red);
-  // row factor sum bound per class: total row mass, and rows * class ceiling
   double Zrows = 1.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -327,6 +289,34 @@ __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, con
       Zrows *= block_sum(zp, red);
     }
   }
+  return Zrows;
+}
+
+template <int PREC>
+__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
+                                            int sw, double* red, PropScales* ps) {
+  const int D = a.g.ndim;
+  const float* tabL = smem + a.L.tab_off[D - 1];
+  // column classes: by the largest factor of each strip
+  double cm[3] = {0.0, 0.0, 0.0};
+  for (int st = threadIdx.x; st < ns; st += kThreads) {
+    float gmax = 0.0f;
+    double sum = 0.0;
+    for (int j = 0; j < sw; ++j) {
+      const float g = tabL[st * sw + j];
+      gmax = fmaxf(gmax, g);
+      sum += (double)g;
+    }
+    const int cc = mag_class(gmax);
+    cm[0] += cc == 0 ? sum : 0.0;
+    cm[1] += cc == 1 ? sum : 0.0;
+    cm[2] += cc == 2 ? sum : 0.0;
+  }
+  double colmass[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) colmass[c] = block_sum(cm[c], red);
+  // row factor sum bound per class: total row mass, and rows * class ceiling
+  const double Zrows = row_mass(a, smem, w, red);
   const double R = (double)w.R;
   const double cells = R * (double)(ns * sw);
   double K = 4294967296.0 - 1048576.0 - cells;
@@ -356,20 +346,20 @@ __device__ __forceinline__ void build_rows_prop(const SweepArgs& a, float* smem,
   const int D = a.g.ndim;
   float4* rt = reinterpret_cast<float4*>(smem + a.L.row_off);
   for (int r = threadIdx.x; r < rc; r += kThreads) {
-    long long t = r0 + r;
+    int t = (int)r0 + r;
     float go = 1.0f;
-    long long off = 0;
+    int off = 0;  // the padded bin map has fewer than 2^31 elements
 #pragma unroll
     for (int d = 2; d >= 0; --d) {
       if (d <= D - 2) {
-        const int i = (int)(t % w.W[d]);
-        t /= w.W[d];
+        const int i = d == 0 ? t : t % w.W[d];
+        if (d > 0) t /= w.W[d];
         go *= smem[a.L.tab_off[d] + i];
-        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
+        off += (w.lo[d] + i) * (int)a.g.rowstride[d];
       }
     }
     const int cls = a.L.ncls > 1 ? mag_class(go) : 0;
-    rt[r] = make_float4(go, go * ps->srow[cls], __int_as_float((int)off), __int_as_float(cls));
+    rt[r] = make_float4(go, go * ps->srow[cls], __int_as_float(off), __int_as_float(cls));
   }
 }
 
@@ -437,189 +427,66 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
   }
 }
 
-// ---------------------------------------------------------------------------
-// Run form (FP32 densities): along the fastest axis the model matrix is a
-// sequence of runs of equal bin, and the density is separable, so a run's
-// mass is go * (G[e] - G[s]) with G the FP64 prefix sums of the fastest-axis
-// factors. Each lane handles one run (16 lanes per row); one integer atomic
-// then carries a whole run instead of one cell.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void build_prefix(const SweepArgs& a, float* smem, int len, double* red2,
-                                             int* pk) {
-  // G[0] = 0, G[j+1] = G[j] + tab_L[j] in FP64; also the index of the
-  // largest factor (smallest index among equal maxima)
-  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
-  double* G = reinterpret_cast<double*>(smem + a.L.g_off);
-  const int per = (len + kThreads - 1) / kThreads;
-  const int j0 = threadIdx.x * per < len ? threadIdx.x * per : len;
-  const int j1 = j0 + per < len ? j0 + per : len;
-  double sum = 0.0;
-  float best = -1.0f;
-  int bidx = 0x7fffffff;
-  for (int j = j0; j < j1; ++j) {
-    const float g = tabL[j];
-    sum += (double)g;
-    if (g > best) {
-      best = g;
-      bidx = j;
+// Unscale the class histograms of component kc, normalise by the sum over all
+// slots (cells without a bin included) and add the weighted column into Pk.
+// Histogram copy i of class cl sits at hist + (cl * cpc + i) * stride.
+__device__ __forceinline__ void finish_component(const SweepArgs& a, const uint32_t* hist, int ncls,
+                                                 int cpc, const double* unscale, double* red,
+                                                 long long kc, float* Pk, bool written) {
+  const int B = a.B;
+  const int stride = a.L.hist_stride;
+  double zpart = 0.0;
+  for (int b = threadIdx.x; b <= B; b += kThreads) {
+    double v = 0.0;
+    for (int cl = 0; cl < ncls; ++cl) {
+      uint64_t cnt = 0;
+      for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * stride + b];
+      v += (double)cnt * unscale[cl];
     }
+    zpart += v;
   }
-  red2[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int t = 0; t < kThreads; ++t) {
-      const double x = red2[t];
-      red2[t] = run;
-      run += x;
+  const double Zc = block_sum(zpart, red);
+  if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+  const double f = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
+  for (int b = threadIdx.x; b < B; b += kThreads) {
+    double v = 0.0;
+    for (int cl = 0; cl < ncls; ++cl) {
+      uint64_t cnt = 0;
+      for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * stride + b];
+      v += (double)cnt * unscale[cl];
     }
-  }
-  __syncthreads();
-  double run = red2[threadIdx.x];
-  if (threadIdx.x == 0) G[0] = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    run += (double)tabL[j];
-    G[j + 1] = run;
-  }
-  // argmax: (value, -index) maximum over the block
-  for (int o = 32; o > 0; o >>= 1) {
-    const float ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bidx, o, 64);
-    if (ob > best || (ob == best && oi < bidx)) {
-      best = ob;
-      bidx = oi;
-    }
-  }
-  __syncthreads();
-  float* rb = reinterpret_cast<float*>(red2);
-  int* ri = reinterpret_cast<int*>(red2) + kWaves;
-  if ((threadIdx.x & 63) == 0) {
-    rb[threadIdx.x >> 6] = best;
-    ri[threadIdx.x >> 6] = bidx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float b = rb[0];
-    int i = ri[0];
-    for (int wv = 1; wv < kWaves; ++wv)
-      if (rb[wv] > b || (rb[wv] == b && ri[wv] < i)) {
-        b = rb[wv];
-        i = ri[wv];
-      }
-    *pk = i;
-  }
-  __syncthreads();
-}
-
-// row table of the run form: (go * srow[class], first run, end run, class)
-__device__ __forceinline__ void build_rows_runs(const SweepArgs& a, float* smem, const Win& w,
-                                                long long r0, int rc, const PropScales* ps,
-                                                int loL, int hiL) {
-  const int D = a.g.ndim;
-  float4* rt = reinterpret_cast<float4*>(smem + a.L.row_off);
-  for (int r = threadIdx.x; r < rc; r += kThreads) {
-    long long t = r0 + r;
-    float go = 1.0f;
-    long long off = 0;
-#pragma unroll
-    for (int d = 2; d >= 0; --d) {
-      if (d <= D - 2) {
-        const int i = (int)(t % w.W[d]);
-        t /= w.W[d];
-        go *= smem[a.L.tab_off[d] + i];
-        off += (long long)(w.lo[d] + i) * a.g.rowstride[d];
-      }
-    }
-    const long long gr = off / a.g.pitch;  // grid row
-    const int base = a.rowptr[gr];
-    const int r_a = base + (int)a.runidx[off + loL];
-    const int r_b = base + (int)a.runidx[off + hiL] + 1;
-    const int cls = a.L.ncls > 1 ? mag_class(go) : 0;
-    rt[r] = make_float4(go * ps->srow[cls], __int_as_float(r_a), __int_as_float(r_b),
-                        __int_as_float(cls));
+    const double prev = written ? (double)Pk[b] : 0.0;
+    Pk[b] = (float)(prev + v * f);
   }
 }
 
-// One row per 16-lane group; the row's m runs are split into contiguous
-// chunks of ceil(m/16) per lane, whose records (and the next record, for the
-// end column) are loaded together before any is used.
-__device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int rc, int colbase,
-                                          int loL, int hiL, int pk, const PropScales* ps) {
-  const int grp = threadIdx.x >> 4;
-  const int l = threadIdx.x & 15;
-  const float4* rt = reinterpret_cast<const float4*>(smem + a.L.row_off);
-  const double* G = reinterpret_cast<const double*>(smem + a.L.g_off);
-  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
-  const int strideb = a.L.hist_stride * 4;
-  const int rcstep = 3 * strideb;  // one copy per class in the run form
-  char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off);
-  const float sc0 = ps->scol[0], sc1 = ps->scol[1], sc2 = ps->scol[2];
-  const int hi1 = hiL + 1;
-  for (int r = grp; r < rc; r += kThreads / 16) {
-    const float4 t = rt[r];
-    const int ra = __float_as_int(t.y), rb = __float_as_int(t.z);
-    char* lr = hbase + (a.L.ncls > 1 ? __float_as_int(t.w) : 0) * rcstep;
-    const int per = (rb - ra + 15) >> 4;
-    int q = ra + l * per;
-    const int qe = min(q + per, rb);
-    while (q < qe) {
-      uint32_t rec[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) rec[i] = (q + i <= qe) ? a.runs[q + i] : 0u;
-      int s = ((int)(rec[0] & 0xFFFFu) > loL ? (int)(rec[0] & 0xFFFFu) : loL) - colbase;
-      double gs = G[s];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        if (q + i < qe) {
-          const int ce = (int)(rec[i + 1] & 0xFFFFu);
-          const int e = (ce < hi1 ? ce : hi1) - colbase;
-          const double ge = G[e];
-          const float val = (float)(ge - gs);
-          float gm = fmaxf(tabL[s], tabL[e - 1]);
-          if (s <= pk && pk < e) gm = 1.0f;
-          const int cc = a.L.ncls > 1 ? mag_class(gm) : 0;
-          const float scol = cc == 0 ? sc0 : (cc == 1 ? sc1 : sc2);
-          const float u = ((float)(l + 16 * i) + 0.5f) * (1.0f / 128.0f);
-          const float v = fmaf(val, t.x * scol, u - floorf(u));
-          uint32_t* slot = reinterpret_cast<uint32_t*>(lr + cc * strideb + (rec[i] >> 16));
-          __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          s = e;
-          gs = ge;
-        }
-      }
-      q += 8;
-    }
+// column of distribution k after all components: NaN for an invalid
+// parameter, zeros when every window is empty; counted
+__device__ __forceinline__ void finish_column(const SweepArgs& a, float* Pk, bool anybad,
+                                              bool written) {
+  if (anybad || !written)
+    for (int b = threadIdx.x; b < a.B; b += kThreads) Pk[b] = anybad ? __builtin_nanf("") : 0.0f;
+  if (threadIdx.x == 0) {
+    if (anybad) atomicAdd(a.counters + kCntBadParam, 1ull);
+    else if (!written) atomicAdd(a.counters + kCntEmpty, 1ull);
   }
 }
 
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
   extern __shared__ float smem[];
+  if (PREC == VUP_FP32 && runs_chosen(a)) return;  // k_propagate_runs does the work
   const long long k = block_k(a);
   if (k >= a.d.K) return;
   const int D = a.g.ndim;
-  const int B = a.B;
-  const int nslots = B + 1;
   const int ncls = a.L.ncls;
+  const int cpc = a.L.cpw;
   double* red = reinterpret_cast<double*>(smem + a.L.red_off);
   PropScales* ps = reinterpret_cast<PropScales*>(red + 16);
   const uint32_t* hist = reinterpret_cast<const uint32_t*>(smem + a.L.hist_off);
-  float* Pk = a.P + k * (long long)B;
+  float* Pk = a.P + k * (long long)a.B;
   bool anybad = false;
   bool written = false;  // row k holds a partial mixture
-  // run form: FP32 densities and a model matrix whose runs along the fastest
-  // axis are at least kRunMinLength cells long on average
-  bool runmode = false;
-  if constexpr (PREC == VUP_FP32) {
-    const unsigned long long mode = a.counters[kCntMode];
-    const unsigned long long nruns = a.counters[kCntRuns];
-    runmode = a.allow_runs && nruns > 0 &&
-              (mode == VUP_SWEEP_RUNS ||
-               (mode == VUP_SWEEP_AUTO && (long long)nruns * kRunMinLength <= a.ncells));
-  }
-  // the run form keeps one histogram copy per class (its prefix tables use
-  // the space of the others)
-  const int cpc = runmode ? 1 : a.L.cpw;
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
     const Win w = make_win(a, kc);
@@ -642,62 +509,274 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
     for (int i = threadIdx.x; i < ncls * cpc * a.L.hist_stride; i += kThreads)
       smem[a.L.hist_off + i] = 0.0f;
     __syncthreads();
-    prop_scales<PREC>(a, smem, w, ns, sw, red, ps, runmode);
-    int pk = 0;
-    if (runmode) {
-      build_prefix(a, smem, ns * sw, reinterpret_cast<double*>(smem + a.L.scan_off), &ps->peak);
-      pk = ps->peak;
+    prop_scales<PREC>(a, smem, w, ns, sw, red, ps);
+    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
+      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+      __syncthreads();
+      build_rows_prop(a, smem, w, r0, rc, ps);
+      __syncthreads();
+      switch (sw) {
+        case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
+        case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
+        default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
+      }
+    }
+    __syncthreads();
+    finish_component(a, hist, ncls, cpc, ps->unscale, red, kc, Pk, written);
+    written = true;
+  }
+  finish_column(a, Pk, anybad, written);
+}
+
+// ---------------------------------------------------------------------------
+// Run form (FP32 densities). Along the fastest axis a row of the model matrix
+// is a sequence of runs of equal bin, and the density is separable, so the
+// mass of the window part [s, e) of a run is go * (G[e] - G[s]), with G the
+// FP64 prefix sums of the fastest-axis factors over the window. One integer
+// atomic then carries a whole run instead of one cell. The fixed point has
+// three classes by row factor (as above) and no column classes: a class-r
+// scale is K / (rowbound[r] * G[W]), since the runs of a row telescope to
+// G[W]. The dither is per thread, u = (t + 1/2)/256.
+// G covers the whole fastest axis (flat outside the window), so no run needs
+// clipping. A 16-lane group walks one row: lane l takes runs l, l+16, ... of
+// the row's window segment, so record loads are coalesced. A run ends where
+// the next begins; lane l takes that record from lane l+1 (a DPP rotate
+// within the 16-lane row; lane 15 from lane 0's record of the next step).
+// The four groups of a wave walk rows a quarter of the row chunk apart, so
+// their atomics rarely meet in a bank.
+// ---------------------------------------------------------------------------
+struct RunRow {
+  double rs;  // row factor x class scale
+  int ra;     // first run of the row's window segment (index into the run records)
+  uint32_t meta;  // runs in the segment | byte offset of the class histogram << 16
+};
+
+struct RunScales {
+  double srow[3];
+  double unscale[3];
+};
+
+constexpr int kRunGroup = 16;  // lanes per row: one DPP row
+
+// G[c] = sum of the fastest-axis factors of the window columns below c, FP64,
+// for every column c = 0 .. n (0 up to loL, the window total from hiL + 1 on).
+// Thread t sums a contiguous slice of the window; slice totals are scanned.
+__device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* smem, long long kc,
+                                                  int loL, int WL, double* red) {
+  const int D = a.g.ndim;
+  const int L = D - 1;
+  const int nL = a.g.n[L];
+  double* G = reinterpret_cast<double*>(smem + a.L.g_off);
+  const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
+  const int per = (WL + kThreads - 1) / kThreads;
+  const int j0 = min((int)threadIdx.x * per, WL);
+  const int j1 = min(j0 + per, WL);
+  double* Gw = G + loL;  // Gw[j + 1] = sum over window columns loL .. loL + j
+  double sum = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double x = cell_centre(a.g.lo[L], a.g.hi[L], nL, loL + j);
+    const double g = (double)gauss_factor_r(x, mu, rsig);
+    Gw[j + 1] = g;
+    sum += g;
+  }
+  // inclusive scan of the slice sums within the wave, then across waves
+  const int lane = threadIdx.x & 63;
+  double incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) red[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  double run = incl - sum;
+  for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) run += red[wv];
+  for (int j = j0; j < j1; ++j) {
+    run += Gw[j + 1];
+    Gw[j + 1] = run;
+  }
+  const double total = red[0] + red[1] + red[2] + red[3];
+  static_assert(kWaves == 4, "scan of four waves");
+  for (int c = threadIdx.x; c <= loL; c += kThreads) G[c] = 0.0;
+  for (int c = loL + WL + 1 + threadIdx.x; c <= nL; c += kThreads) G[c] = total;
+  __syncthreads();
+}
+
+// Row table of the run form for rows [r0, r0 + rc) of the window.
+__device__ __forceinline__ void build_rows_runs(const SweepArgs& a, float* smem, const Win& w,
+                                                long long r0, int rc, const RunScales* ps,
+                                                int loL, int hiL) {
+  const int D = a.g.ndim;
+  RunRow* rt = reinterpret_cast<RunRow*>(smem + a.L.row_off);
+  const int hstrideb = a.L.hist_stride * 4;
+  for (int r = threadIdx.x; r < rc; r += kThreads) {
+    int t = (int)r0 + r;  // window rows and grid rows number below 2^31
+    float go = 1.0f;
+    int gr = 0;  // grid row (flat index over the slower axes)
+    int mul = 1;
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      if (d <= D - 2) {
+        // axis 0 is the slowest: what is left of t is its index
+        const int i = d == 0 ? t : t % w.W[d];
+        if (d > 0) t /= w.W[d];
+        go *= smem[a.L.tab_off[d] + i];
+        gr += (w.lo[d] + i) * mul;
+        mul *= a.g.n[d];
+      }
+    }
+    const int off = gr * a.g.pitch;
+    const int base = a.rowptr[gr];
+    const int ra = base + (int)a.runidx[off + loL];
+    const int rb = base + (int)a.runidx[off + hiL] + 1;
+    const int cls = mag_class(go);
+    RunRow e;
+    e.rs = (double)go * ps->srow[cls];
+    e.ra = ra;
+    e.meta = (uint32_t)(rb - ra) | ((uint32_t)(cls * hstrideb) << 16);
+    rt[r] = e;
+  }
+}
+
+// FP64 load from an LDS byte address. The run kernel uses no static LDS, so
+// its dynamic LDS (and the prefix sums at its start) begins at address 0.
+typedef const __attribute__((address_space(3))) double lds_f64;
+__device__ __forceinline__ double lds_load_f64(uint32_t byte_addr) {
+  return *(lds_f64*)(size_t)byte_addr;
+}
+
+// (x & 0xFFFF) * 8 in one VALU op (a shift with a 16-bit operand select),
+// which the compiler otherwise splits into a shift and a mask
+__device__ __forceinline__ uint32_t lo16_times8(uint32_t x) {
+  uint32_t r;
+  asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+      "src1_sel:WORD_0"
+      : "=v"(r)
+      : "v"(x));
+  return r;
+}
+
+// value of lane (l + 1) mod 16 within each 16-lane row (DPP row rotate)
+__device__ __forceinline__ uint32_t next_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F /* row_ror:15 */, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int rc) {
+  const int l = threadIdx.x & (kRunGroup - 1);
+  const int gi = (threadIdx.x >> 4) & 3;  // group within the wave
+  const int wv = threadIdx.x >> 6;
+  const RunRow* rt = reinterpret_cast<const RunRow*>(smem + a.L.row_off);
+  char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off);
+  const double u = ((double)threadIdx.x + 0.5) * (1.0 / kThreads);
+  const int bl = (rc + 3) >> 2;
+  const int rend = min((gi + 1) * bl, rc);
+  for (int r = gi * bl + wv; r < rend; r += kWaves) {
+    const RunRow row = rt[r];
+    const int cnt = (int)(row.meta & 0xFFFFu);
+    char* lh = hbase + (row.meta >> 16);
+    const uint32_t* rp = a.runs + row.ra;
+    // One run: this lane's record c; the run after it starts at lane l+1's
+    // record (dc = c rotated down one lane) or, for lane 15, at lane 0's
+    // record of the next step (dn). G is flat outside the window, so the
+    // part of a run inside the window is G[next start] - G[start] without
+    // clamping. `left` = runs of the row from this lane's current one on.
+    auto step = [&](uint32_t c, uint32_t dc, uint32_t dn, int left) {
+      const uint32_t nx = (l == kRunGroup - 1) ? dn : dc;
+      if (left > 0) {
+        const double v =
+            fma(lds_load_f64(lo16_times8(nx)) - lds_load_f64(lo16_times8(c)), row.rs, u);
+        uint32_t* slot = reinterpret_cast<uint32_t*>(lh + (c >> 16));
+        __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    };
+    // four runs per lane per pass: the four record loads are in flight
+    // together. Records past the segment (at most 79) are read but unused;
+    // the run buffer is padded for them.
+    uint32_t cur = rp[l];
+    uint32_t dcur = next_lane(cur);
+    for (int q0 = l; q0 - l < cnt; q0 += 4 * kRunGroup) {
+      const uint32_t* p = rp + q0;
+      const uint32_t r1 = p[kRunGroup];
+      const uint32_t r2 = p[2 * kRunGroup];
+      const uint32_t r3 = p[3 * kRunGroup];
+      const uint32_t r4 = p[4 * kRunGroup];
+      const uint32_t d1 = next_lane(r1), d2 = next_lane(r2);
+      const uint32_t d3 = next_lane(r3), d4 = next_lane(r4);
+      const int left = cnt - q0;
+      step(cur, dcur, d1, left);
+      step(r1, d1, d2, left - kRunGroup);
+      step(r2, d2, d3, left - 2 * kRunGroup);
+      step(r3, d3, d4, left - 3 * kRunGroup);
+      cur = r4;
+      dcur = d4;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_propagate_runs(SweepArgs a) {
+  extern __shared__ float smem[];
+  if (!runs_chosen(a)) return;  // k_propagate does the work
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  RunScales* ps = reinterpret_cast<RunScales*>(red + 16);
+  const uint32_t* hist = reinterpret_cast<const uint32_t*>(smem + a.L.hist_off);
+  float* Pk = a.P + k * (long long)a.B;
+  bool anybad = false;
+  bool written = false;
+  for (int c = 0; c < a.d.C; ++c) {
+    const long long kc = k * a.d.C + c;
+    const Win w = make_win(a, kc);
+    if (w.bad) {
+      anybad = true;
+      if (a.Z && threadIdx.x == 0) a.Z[kc] = __builtin_nan("");
+      continue;
+    }
+    if (w.empty) {
+      if (a.Z && threadIdx.x == 0) a.Z[kc] = 0.0;
+      continue;
+    }
+    int loL, WL;
+    last_axis(w, D, loL, WL);
+    __syncthreads();  // LDS reuse across components
+    // factor tables of the slower axes
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d + 1 < D) {
+        float* tab = smem + a.L.tab_off[d];
+        const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                  rsig);
+      }
+    }
+    for (int i = threadIdx.x; i < 3 * a.L.hist_stride; i += kThreads) smem[a.L.hist_off + i] = 0.0f;
+    build_prefix_runs(a, smem, kc, loL, WL, red);
+    const double Zrows = row_mass(a, smem, w, red);
+    if (threadIdx.x == 0) {
+      const double colmass = reinterpret_cast<const double*>(smem + a.L.g_off)[loL + WL];
+      const double R = (double)w.R;
+      const double K = 4294967296.0 - 1048576.0 - R * (double)WL;
+      const double rowbound[3] = {Zrows, fmin(Zrows, R * (double)kClassT1),
+                                  fmin(Zrows, R * (double)kClassT2)};
+      for (int r = 0; r < 3; ++r) {
+        ps->srow[r] = K / (prec_qfac<VUP_FP32>() * rowbound[r] * colmass);
+        ps->unscale[r] = 1.0 / ps->srow[r];
+      }
     }
     for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
       const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
       __syncthreads();
-      if (runmode) build_rows_runs(a, smem, w, r0, rc, ps, loL, loL + WL - 1);
-      else build_rows_prop(a, smem, w, r0, rc, ps);
+      build_rows_runs(a, smem, w, r0, rc, ps, loL, loL + WL - 1);
       __syncthreads();
-      if (runmode) {
-        prop_runs(a, smem, rc, colbase, loL, loL + WL - 1, pk, ps);
-      } else {
-        switch (sw) {
-          case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
-          case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
-          default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
-        }
-      }
+      prop_runs(a, smem, rc);
     }
     __syncthreads();
-    // unscale each class, sum its copies; the normaliser is the sum over all
-    // slots (cells without a bin included)
-    double zpart = 0.0;
-    for (int b = threadIdx.x; b < nslots; b += kThreads) {
-      double v = 0.0;
-      for (int cl = 0; cl < ncls; ++cl) {
-        uint64_t cnt = 0;
-        for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * a.L.hist_stride + b];
-          v += (double)cnt * ps->unscale[cl];
-      }
-      zpart += v;
-    }
-    const double Zc = block_sum(zpart, red);
-    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
-    const double f = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
-    for (int b = threadIdx.x; b < B; b += kThreads) {
-      double v = 0.0;
-      for (int cl = 0; cl < ncls; ++cl) {
-        uint64_t cnt = 0;
-        for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * a.L.hist_stride + b];
-        v += (double)cnt * ps->unscale[cl];
-      }
-      const double prev = written ? (double)Pk[b] : 0.0;
-      Pk[b] = (float)(prev + v * f);
-    }
+    finish_component(a, hist, 3, 1, ps->unscale, red, kc, Pk, written);
     written = true;
   }
-  if (anybad || !written)
-    for (int b = threadIdx.x; b < B; b += kThreads) Pk[b] = anybad ? __builtin_nanf("") : 0.0f;
-  if (threadIdx.x == 0) {
-    if (anybad) atomicAdd(a.counters + kCntBadParam, 1ull);
-    else if (!written) atomicAdd(a.counters + kCntEmpty, 1ull);
-  }
+  finish_column(a, Pk, anybad, written);
 }
 
 // ===========================================================================
@@ -1038,7 +1117,17 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     L.tab_off[d] = -1;
     L.cap[d] = 0;
   }
-  for (int d = 0; d < D; ++d) {
+  // the run form starts with the FP64 prefix sums G[0..n] of the fastest
+  // axis (at offset 0, so a column times 8 is its byte address)
+  L.g_off = -1;
+  if (kind == kSweepRuns) {
+    L.g_off = 0;
+    off = round_up(2 * (g.n[D - 1] + 1), 4);
+  }
+  // factor tables: every axis for the cell sweeps; the run form keeps the
+  // slower axes only
+  const int ntab = kind == kSweepRuns ? D - 1 : D;
+  for (int d = 0; d < ntab; ++d) {
     const int cap = (d + 1 < D) ? g.n[d] : g.n[d] + 64;
     L.cap[d] = round_up(cap, 4);
     L.tab_off[d] = off;
@@ -1046,14 +1135,12 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   }
   off = round_up(off, 4);
   L.row_off = off;
-  off += (kind == kSweepPropagate ? 4 : 2) * kRowChunk;
+  off += (kind == kSweepPropagate || kind == kSweepRuns ? 4 : 2) * kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;
     off += 4 * kRowChunk;
   }
-  L.g_off = -1;
-  L.scan_off = -1;
   L.hist_off = off;
   L.hist_stride = 0;
   L.cpw = 0;
@@ -1062,33 +1149,30 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     // stride = 1 mod 32 so consecutive copies shift banks by one
     const int stride = round_up(B + 1, 32) + 1;
     L.hist_stride = stride;
-    // the run form keeps one copy per class and places the FP64 prefix sums
-    // of the fastest-axis factors (and their scan scratch) behind it
-    const int gfl = 2 * (L.cap[D - 1] + 2) + 2 * kThreads + 2;
     const int budget = 48 * 1024 / 4 - 64;
     const int opts[5][2] = {{9, 2}, {9, 1}, {1, 4}, {1, 2}, {1, 1}};
-    auto need = [&](int i) {
-      const int h2 = opts[i][0] * opts[i][1] * stride;
-      const int h1 = round_up(opts[i][0] * stride, 2) + gfl;
-      return h2 > h1 ? h2 : h1;
-    };
     int pick = 4;
     for (int i = 0; i < 5; ++i)
-      if (off + need(i) <= budget) {
+      if (off + opts[i][0] * opts[i][1] * stride <= budget) {
         pick = i;
         break;
       }
     if (pick == 4)  // nothing fits the occupancy budget: take the richest that fits at all
       for (int i = 0; i < 5; ++i)
-        if (off + need(i) <= 160 * 1024 / 4 - 64) {
+        if (off + opts[i][0] * opts[i][1] * stride <= 160 * 1024 / 4 - 64) {
           pick = i;
           break;
         }
     L.ncls = opts[pick][0];
     L.cpw = opts[pick][1];
-    L.g_off = off + round_up(L.ncls * stride, 2);
-    L.scan_off = L.g_off + 2 * (L.cap[D - 1] + 2);
-    off += need(pick);
+    off += L.ncls * L.cpw * stride;
+  } else if (kind == kSweepRuns) {
+    // three row classes, one copy each
+    const int stride = round_up(B + 1, 32) + 1;
+    L.hist_stride = stride;
+    L.ncls = 3;
+    L.cpw = 1;
+    off += 3 * stride;
   } else if (kind == kSweepBackward) {
     off += round_up(B + 1, 4);
   }
@@ -1131,6 +1215,14 @@ DistsDev make_dists_dev(const vup_dists& d) {
   return r;
 }
 
+// run records hold 16-bit columns and are addressed with 32-bit offsets; the
+// run form's LDS (prefix sums of a whole fastest axis) must fit in 64 KiB
+bool runs_allowed(const vup_mm& mm) {
+  SweepLayout L;
+  return mm.grid.n[mm.grid.ndim - 1] <= 65534 && mm.N < (1ll << 30) &&
+         sweep_layout(mm.grid, mm.B, kSweepRuns, &L) && L.bytes <= 64 * 1024;
+}
+
 static SweepArgs base_args(const vup_mm& mm, const vup_dists& d, SweepKind kind) {
   SweepArgs a{};
   a.g = make_grid_dev(mm);
@@ -1147,7 +1239,7 @@ static SweepArgs base_args(const vup_mm& mm, const vup_dists& d, SweepKind kind)
   a.rowptr = reinterpret_cast<const int*>(ws + mm.off_rowptr);
   a.runidx = reinterpret_cast<const uint16_t*>(ws + mm.off_runidx);
   a.ncells = mm.N;
-  a.allow_runs = mm.grid.n[mm.grid.ndim - 1] <= 65534;
+  a.allow_runs = runs_allowed(mm);
   return a;
 }
 
@@ -1169,6 +1261,15 @@ hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, floa
   a.Z = Z;
   const dim3 grid = sweep_grid(d), block(kThreads);
   hipError_t e = hipSuccess;
+  if (prec == VUP_FP32 && a.allow_runs && mm.sweep != VUP_SWEEP_CELLS) {
+    // the run form returns at once unless the device-side mode and run
+    // statistics select it; the cell form below then returns at once
+    SweepArgs ar = a;
+    sweep_layout(mm.grid, mm.B, kSweepRuns, &ar.L);
+    hipLaunchKernelGGL(k_propagate_runs, grid, block, ar.L.bytes, s, ar);
+    e = hipGetLastError();
+    if (e != hipSuccess || mm.sweep == VUP_SWEEP_RUNS) return e;
+  }
   switch (prec) {
     case VUP_BF16: e = allow_lds(k_propagate<VUP_BF16>, a.L.bytes); break;
     case VUP_BF16X2: e = allow_lds(k_propagate<VUP_BF16X2>, a.L.bytes); break;

@@ -171,6 +171,8 @@ int vup_bin(const vup_grid* g, const double* f, const double* edges, int32_t B, 
   mm.off_runs = L.off_runs;
   mm.off_rowptr = L.off_rowptr;
   mm.off_runidx = L.off_runidx;
+  mm.sweep = VUP_SWEEP_AUTO;
+  mm.reserved = 0;
   mm.magic = vup::kMagic;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemsetAsync(static_cast<char*>(ws) + L.off_counters, 0, 64, s);
@@ -277,12 +279,26 @@ int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
                   "vup_ipsa_backward");
 }
 
-int vup_set_sweep_mode(const vup_mm* mm, int32_t mode, void* stream) {
+int vup_set_sweep_mode(vup_mm* mm, int32_t mode, void* stream) {
   int r = check_mm(mm);
   if (r) return r;
   if (mode < VUP_SWEEP_AUTO || mode > VUP_SWEEP_RUNS) return fail(VUP_EINVAL, "unknown mode %d", mode);
   if ((r = check_device())) return r;
-  return launched(vup::launch_set_mode(*mm, mode, (hipStream_t)stream), "vup_set_sweep_mode");
+  hipStream_t s = (hipStream_t)stream;
+  if (mode == VUP_SWEEP_AUTO) {
+    // resolve now from the run count vup_bin left in the counters
+    const char* c = static_cast<const char*>(mm->ws) + mm->off_counters;
+    int64_t nruns = 0;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+      e = hipMemcpy(&nruns, c + vup::kCntRuns * sizeof(int64_t), sizeof(nruns),
+                    hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return launched(e, "vup_set_sweep_mode");
+    const bool runs = vup::runs_allowed(*mm) && nruns > 0 && nruns * vup::kRunMinLength <= mm->N;
+    mode = runs ? VUP_SWEEP_RUNS : VUP_SWEEP_CELLS;
+  }
+  mm->sweep = mode;
+  return launched(vup::launch_set_mode(*mm, mode, s), "vup_set_sweep_mode");
 }
 
 int vup_counters(const vup_mm* mm, void* stream, int64_t* out) {

@@ -106,6 +106,16 @@ __device__ __forceinline__ float gauss_factor(double x, double mu, double sigma)
   return expf(hi) * (1.0f + lo);
 }
 
+// the same with t = (x - mu) * rsig, rsig = 1/sigma computed once per axis
+// (t then differs from the quotient by at most an FP64 ulp or so)
+__device__ __forceinline__ float gauss_factor_r(double x, double mu, double rsig) {
+  const double t = (x - mu) * rsig;
+  const double arg = -0.5 * (t * t);
+  const float hi = (float)arg;
+  const float lo = (float)(arg - (double)hi);
+  return expf(hi) * (1.0f + lo);
+}
+
 // ---------------------------------------------------------------------------
 // built-in models (Sec. 2, eq. modelfunction)
 // ---------------------------------------------------------------------------

@@ -19,19 +19,18 @@ constexpr int kBinChunk = 4096;
 struct SweepLayout {
   int tab_off[4];
   int cap[4];
-  int row_off;      // float4[kRowChunk] (propagate) or float2[kRowChunk]
+  int row_off;      // 16-byte entries [kRowChunk] (propagate, run form) or float2[kRowChunk]
   int trow_off;     // float4[kRowChunk] (backward only, else -1)
   int hist_off;     // histogram copies (propagate) or v table (backward)
   int hist_stride;  // floats per histogram copy
   int cpw;          // histogram copies per magnitude class
-  int ncls;         // magnitude classes (9, or 1 when LDS is short)
+  int ncls;         // magnitude classes (9, or 1 when LDS is short; 3 in the run form)
   int red_off;      // double scratch
-  int g_off;        // FP64 prefix sums of the fastest-axis factors (propagate)
-  int scan_off;     // FP64 scan scratch, kThreads entries (propagate)
+  int g_off;        // FP64 prefix sums of the fastest-axis factors (run form)
   size_t bytes;
 };
 
-enum SweepKind { kSweepPropagate = 0, kSweepMoments = 1, kSweepBackward = 2 };
+enum SweepKind { kSweepPropagate = 0, kSweepMoments = 1, kSweepBackward = 2, kSweepRuns = 3 };
 
 bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out);
 GridDev make_grid_dev(const vup_mm& mm);
@@ -54,6 +53,8 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);
 
 hipError_t launch_set_mode(const vup_mm& mm, int mode, hipStream_t s);
+// the run form of the FP32 propagation applies to this model matrix
+bool runs_allowed(const vup_mm& mm);
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My);
 hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x,
                             const double* mu_y, const double* sg_x, const double* sg_y,

@@ -516,5 +516,12 @@ def test_run_and_cell_forms_agree(vup, orc):
             out[mode] = _cpu(P)
             _check_P(out[mode], Po, 2e-5, f"{wl.name} {mode} form")
         mm.set_sweep_mode("auto")
+        assert mm.sweep in ("cells", "runs")
         d = np.abs(out["runs"].astype(np.float64) - out["cells"]).sum(axis=1).max()
-        _say(f"  runs vs cells: max L1 {d:.2e}")
+        _say(f"  runs vs cells: max L1 {d:.2e}; auto resolves to {mm.sweep}")
+        # unresolved auto mode: both forms are enqueued and the device picks the
+        # same one; results are bit-identical to the resolved form's
+        mm_u = vup.build_model_matrix(g, fg, vup.uniform_edges(fg, wl.B), resolve_sweep=False)
+        assert mm_u.sweep == "auto"
+        Pu, _ = vup.propagate(mm_u, wl.mu, wl.sigma, wl.weight)
+        assert np.array_equal(_cpu(Pu), out[mm.sweep])
