@@ -70,26 +70,35 @@ struct Win {
   bool empty;
 };
 
-__device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc) {
-  Win w;
-  w.bad = false;
-  w.empty = false;
-  w.R = 1;
+// Window of component kc. Lanes 0..3 of wave 0 compute one axis each (FP64,
+// the exact formula of axis_window) into LDS (`wsh`, 12 ints); every thread
+// then reads the result. Contains two workgroup barriers.
+__device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* wsh) {
   const int D = a.g.ndim;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    w.lo[d] = 0;
-    w.W[d] = 1;
+  __syncthreads();  // earlier readers of wsh are done
+  if (threadIdx.x < 4) {
+    const int d = threadIdx.x;
+    int jlo = 0, jhi = 0, flags = 0;
     if (d < D) {
-      int jlo, jhi;
       const bool ok = axis_window(a.g.lo[d], a.g.hi[d], a.g.n[d], a.d.mu[kc * D + d],
                                   a.d.sigma[kc * D + d], a.d.ns, jlo, jhi);
-      if (!ok) w.bad = true;
-      if (jhi < jlo) w.empty = true;
-      w.lo[d] = jlo;
-      w.W[d] = jhi - jlo + 1;
-      if (d + 1 < D) w.R *= (w.W[d] > 0 ? w.W[d] : 0);
+      flags = (ok ? 0 : 1) | (jhi < jlo ? 2 : 0);
     }
+    wsh[d] = jlo;
+    wsh[4 + d] = jhi - jlo + 1;
+    wsh[8 + d] = flags;
+  }
+  __syncthreads();
+  Win w;
+  w.R = 1;
+  const int flags = wsh[8] | wsh[9] | wsh[10] | wsh[11];
+  w.bad = (flags & 1) != 0;
+  w.empty = (flags & 2) != 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    w.lo[d] = wsh[d];
+    w.W[d] = wsh[4 + d];
+    if (d + 1 < D) w.R *= (w.W[d] > 0 ? w.W[d] : 0);
   }
   return w;
 }
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
   bool written = false;  // row k holds a partial mixture
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
-    const Win w = make_win(a, kc);
+    const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
     if (w.bad) {
       anybad = true;
       if (a.Z && threadIdx.x == 0) a.Z[kc] = __builtin_nan("");
@@ -727,7 +736,7 @@ __global__ __launch_bounds__(kThreads) void k_propagate_runs(SweepArgs a) {
   bool written = false;
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
-    const Win w = make_win(a, kc);
+    const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
     if (w.bad) {
       anybad = true;
       if (a.Z && threadIdx.x == 0) a.Z[kc] = __builtin_nan("");
@@ -782,6 +791,43 @@ __global__ __launch_bounds__(kThreads) void k_propagate_runs(SweepArgs a) {
 // ===========================================================================
 // exact-f moments: shifted FP32 strip sums, FP64 accumulation
 // ===========================================================================
+// A thread walks the rows of its strip two at a time (ping-pong buffers): the
+// loads of one row are in flight while the other row is summed.
+template <int SW>
+struct MomRow {
+  float4 f[SW / 4];
+  float go;
+};
+
+template <int SW>
+__device__ __forceinline__ void mom_load(const SweepArgs& a, const float2* rt, const float* fbase,
+                                         int r, MomRow<SW>& m) {
+  const float2 e = rt[r];
+  m.go = e.x;
+  const float4* p = reinterpret_cast<const float4*>(fbase + (unsigned)__float_as_int(e.y));
+#pragma unroll
+  for (int q = 0; q < SW / 4; ++q) m.f[q] = p[q];
+}
+
+template <int SW>
+__device__ __forceinline__ void mom_sum(const MomRow<SW>& m, const float* gl, float shift,
+                                        double& A1, double& A2) {
+  float a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+  for (int q = 0; q < SW / 4; ++q) {
+    const float fj[4] = {m.f[q].x, m.f[q].y, m.f[q].z, m.f[q].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float dv = fj[e] - shift;
+      const float t = gl[4 * q + e] * dv;
+      a1 += t;
+      a2 = fmaf(t, dv, a2);
+    }
+  }
+  A1 = fma((double)m.go, (double)a1, A1);
+  A2 = fma((double)m.go, (double)a2, A2);
+}
+
 template <int SW>
 __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, int rc,
                                          int colbase, int ns, float shift, double& A1,
@@ -797,26 +843,20 @@ __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, 
     float gl[SW];
 #pragma unroll
     for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
-    const int mcol = colbase + s * SW;
-    for (int r = ph; r < rc; r += P0) {
-      const float2 cur = rt[r];
-      const float4* fp =
-          reinterpret_cast<const float4*>(a.f32 + (long long)__float_as_int(cur.y) + mcol);
-      float a1 = 0.0f, a2 = 0.0f;
-#pragma unroll
-      for (int q = 0; q < SW / 4; ++q) {
-        const float4 fv = fp[q];
-        const float fj[4] = {fv.x, fv.y, fv.z, fv.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float dv = fj[e] - shift;
-          const float t = gl[4 * q + e] * dv;
-          a1 += t;
-          a2 = fmaf(t, dv, a2);
-        }
-      }
-      A1 += (double)cur.x * (double)a1;
-      A2 += (double)cur.x * (double)a2;
+    const float* fbase = a.f32 + colbase + s * SW;
+    int r = ph;
+    if (r >= rc) continue;
+    MomRow<SW> ma, mb;
+    mom_load<SW>(a, rt, fbase, r, ma);
+    for (;;) {
+      const int rb = r + P0;
+      if (rb < rc) mom_load<SW>(a, rt, fbase, rb, mb);
+      mom_sum<SW>(ma, gl, shift, A1, A2);
+      if (rb >= rc) break;
+      r = rb + P0;
+      if (r < rc) mom_load<SW>(a, rt, fbase, r, ma);
+      mom_sum<SW>(mb, gl, shift, A1, A2);
+      if (r >= rc) break;
     }
   }
 }
@@ -832,7 +872,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
   bool anybad = false;
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
-    const Win w = make_win(a, kc);
+    const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
     used[c] = false;
     pcs[c] = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
     if (w.bad) {
@@ -843,7 +883,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
     used[c] = true;
     int loL, WL;
     last_axis(w, D, loL, WL);
-    const int sw = choose_sw(loL, WL, w.R, kMaxSW);
+    const int sw = choose_sw(loL, WL, w.R, 8);
     const int colbase = (loL / sw) * sw;
     const int ns = (loL + WL - 1) / sw - loL / sw + 1;
     // shift: model value at the window's centre cell
@@ -863,7 +903,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
       switch (sw) {
         case 4: mom_rows<4>(a, smem, rc, colbase, ns, shift, A1, A2); break;
         case 8: mom_rows<8>(a, smem, rc, colbase, ns, shift, A1, A2); break;
-        default: mom_rows<16>(a, smem, rc, colbase, ns, shift, A1, A2); break;
+        default: mom_rows<8>(a, smem, rc, colbase, ns, shift, A1, A2); break;
       }
     }
     // normaliser: product of the per-axis factor sums (separable density)
@@ -1016,7 +1056,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   }
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
-    const Win w = make_win(a, kc);
+    const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
     const double pc = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
     if (w.bad || w.empty) {
       if (threadIdx.x == 0) {
@@ -1178,7 +1218,7 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   }
   off = round_up(off, 4);
   L.red_off = off;
-  off += 64;  // 16 doubles of reduction scratch + per-component scales
+  off += 96;  // 16 doubles of reduction scratch, per-component scales, window ints
   L.bytes = (size_t)off * 4;
   *out = L;
   return L.bytes <= 160 * 1024;
