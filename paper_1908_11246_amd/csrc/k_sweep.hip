@@ -952,15 +952,16 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
 // ===========================================================================
 // per-thread adjoint accumulators: sum w v, and sum w v t_d, sum w v t_d^2 for
 // the fastest axis (L) and the slower axes (o[d], d < L)
+template <int NO>  // number of slower axes
 struct BwdAcc {
   double a0, l1, l2;
-  double o1[3], o2[3];
+  double o1[NO > 0 ? NO : 1], o2[NO > 0 ? NO : 1];
 };
 
-template <int SW>
+template <int SW, int NO>
 __device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, int rc,
                                          int colbase, int ns, double muL, double sgL,
-                                         BwdAcc& acc) {
+                                         BwdAcc<NO>& acc) {
   const int D = a.g.ndim;
   const int L = D - 1;
   const int cols = ns < kThreads ? ns : kThreads;
@@ -974,18 +975,18 @@ __device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, 
   const float* tabL = smem + a.L.tab_off[L];
   for (int s = col; s < ns; s += cols) {
     float gl[SW], g1[SW], g2[SW];
+    const float* tab1 = smem + a.L.g_off;
+    const float* tab2 = tab1 + a.L.cap[L];
 #pragma unroll
     for (int j = 0; j < SW; ++j) {
       gl[j] = tabL[s * SW + j];
-      const int jj = colbase + s * SW + j;
-      const double t = (cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], jj) - muL) / sgL;
-      g1[j] = (float)((double)gl[j] * t);
-      g2[j] = (float)((double)gl[j] * t * t);
+      g1[j] = tab1[s * SW + j];
+      g2[j] = tab2[s * SW + j];
     }
-    const int mcol = colbase + s * SW;
-    for (int r = ph; r < rc; r += P0) {
-      const float2 cur = rt[r];
-      const MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.y) + mcol);
+    const uint16_t* mbase = a.binmap + colbase + s * SW;
+    // one row: the sums of the strip's cells weighted by the bin's v, then the
+    // row factor (and the slower axes' t) applied in FP64
+    auto row_sum = [&](int r, const MapVec<SW>& mv) {
       float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
 #pragma unroll
       for (int j = 0; j < SW; ++j) {
@@ -994,25 +995,43 @@ __device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, 
         a1 = fmaf(g1[j], vb, a1);
         a2 = fmaf(g2[j], vb, a2);
       }
-      const double go = (double)cur.x;
+      const double go = (double)rt[r].x;
       const double c0 = go * (double)a0;
       acc.a0 += c0;
       acc.l1 += go * (double)a1;
       acc.l2 += go * (double)a2;
-      if (L > 0) {
+      if constexpr (NO > 0) {
         const float4 tv = tt[r];
         const float tr[3] = {tv.x, tv.y, tv.z};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
+        for (int d = 0; d < NO; ++d) {
           const double td = (double)tr[d];
           acc.o1[d] += c0 * td;
           acc.o2[d] += c0 * td * td;
         }
       }
+    };
+    // rows two at a time in ping-pong buffers: one row's bin codes are in
+    // flight while the other row is summed
+    int r = ph;
+    if (r >= rc) continue;
+    MapVec<SW> ma = load_map<SW>(mbase + (unsigned)__float_as_int(rt[r].y)), mb;
+    for (;;) {
+      const int rb = r + P0;
+      if (rb < rc) mb = load_map<SW>(mbase + (unsigned)__float_as_int(rt[rb].y));
+      row_sum(r, ma);
+      if (rb >= rc) break;
+      r = rb + P0;
+      if (r < rc) ma = load_map<SW>(mbase + (unsigned)__float_as_int(rt[r].y));
+      row_sum(rb, mb);
+      if (r >= rc) break;
     }
   }
 }
 
+// NO = ndim - 1 slower axes (a compile-time count keeps the accumulators of
+// absent axes out of the registers)
+template <int NO>
 __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
   extern __shared__ float smem[];
   const long long k = block_k(a);
@@ -1072,15 +1091,26 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     const int L = D - 1;
     int loL, WL;
     last_axis(w, D, loL, WL);
-    const int sw = choose_sw(loL, WL, w.R, 16);
+    const int sw = choose_sw(loL, WL, w.R, 8);
     const int colbase = (loL / sw) * sw;
     const int ns = (loL + WL - 1) / sw - loL / sw + 1;
     __syncthreads();
     build_tables(a, smem, w, kc, sw, colbase, ns);
-    BwdAcc acc;
+    {
+      float* tab1 = smem + a.L.g_off;
+      float* tab2 = tab1 + a.L.cap[L];
+      const double muL = a.d.mu[kc * D + L], rsg = 1.0 / a.d.sigma[kc * D + L];
+      for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+        const double t = (cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], colbase + jj) - muL) * rsg;
+        const double g = (double)smem[a.L.tab_off[L] + jj];
+        tab1[jj] = (float)(g * t);
+        tab2[jj] = (float)(g * t * t);
+      }
+    }
+    BwdAcc<NO> acc;
     acc.a0 = acc.l1 = acc.l2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) acc.o1[i] = acc.o2[i] = 0.0;
+    for (int i = 0; i < (NO > 0 ? NO : 1); ++i) acc.o1[i] = acc.o2[i] = 0.0;
     const double muL = a.d.mu[kc * D + L];
     const double sgL = a.d.sigma[kc * D + L];
     for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
@@ -1089,9 +1119,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
       build_rows(a, smem, w, r0, rc, kc, true);
       __syncthreads();
       switch (sw) {
-        case 4: bwd_rows<4>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
-        case 8: bwd_rows<8>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
-        default: bwd_rows<16>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
+        case 4: bwd_rows<4, NO>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
+        default: bwd_rows<8, NO>(a, smem, rc, colbase, ns, muL, sgL, acc); break;
       }
     }
     // per-axis normalisers and score means from the factor tables (FP64)
@@ -1121,8 +1150,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     double t1[4], t2[4];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      t1[d] = block_sum(acc.o1[d], red) / Z;
-      t2[d] = block_sum(acc.o2[d], red) / Z;
+      t1[d] = d < NO ? block_sum(acc.o1[d < NO ? d : 0], red) / Z : 0.0;
+      t2[d] = d < NO ? block_sum(acc.o2[d < NO ? d : 0], red) / Z : 0.0;
     }
     t1[3] = 0.0;
     t2[3] = 0.0;
@@ -1215,6 +1244,9 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     off += 3 * stride;
   } else if (kind == kSweepBackward) {
     off += round_up(B + 1, 4);
+    // fastest-axis factor times t and times t^2 (t = (x - mu)/sigma)
+    L.g_off = off;
+    off += 2 * L.cap[D - 1];
   }
   off = round_up(off, 4);
   L.red_off = off;
@@ -1357,9 +1389,20 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
   a.g_mu = g_mu;
   a.g_sigma = g_sigma;
   a.g_weight = g_weight;
-  const hipError_t e = allow_lds(k_backward, a.L.bytes);
+  hipError_t e = hipSuccess;
+  switch (mm.grid.ndim) {
+    case 1: e = allow_lds(k_backward<0>, a.L.bytes); break;
+    case 2: e = allow_lds(k_backward<1>, a.L.bytes); break;
+    case 3: e = allow_lds(k_backward<2>, a.L.bytes); break;
+    default: e = allow_lds(k_backward<3>, a.L.bytes); break;
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_backward, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a);
+  switch (mm.grid.ndim) {
+    case 1: hipLaunchKernelGGL(k_backward<0>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
+    case 2: hipLaunchKernelGGL(k_backward<1>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
+    case 3: hipLaunchKernelGGL(k_backward<2>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
+    default: hipLaunchKernelGGL(k_backward<3>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
+  }
   return hipGetLastError();
 }
 
