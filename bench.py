@@ -15,8 +15,16 @@ exact number of (cell, distribution) pairs inside the truncation windows.
 Also reported (same workload, same run): propagation alone at each density
 precision, and forward + backward (propagate + IPSA + adjoint sweep), each
 with its error against the FP64 oracle on a seeded sample of distributions;
-the roofline of the dominant kernel (propagation) from HIP events; and the
-CPU oracle's own throughput on a bounded sample.
+the roofline of the longest sweep kernel of the step (and of the other one)
+from HIP events; and the CPU oracle's own throughput on a bounded sample.
+
+Profiling helpers (rocprofv3 wraps the program; see profiles/):
+  --kernels-once              one propagation and one moments launch on the
+                              workload, then a plain 256 MiB copy (the
+                              calibration dispatch for the byte counters)
+  --summarize-traffic F W     FETCH_SIZE / WRITE_SIZE counter CSVs of two
+                              --kernels-once runs -> profiles/traffic_grid1024.*
+  --summarize-stats CSV OUT   rocprofv3 kernel_stats.csv -> markdown table
 """
 import argparse
 import json
@@ -31,12 +39,127 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 64 FP32 lanes per clock x 2.4 GHz, non-packed VALU issue.
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# algorithmic VALU work per update of the propagation: one multiply (density
-# = row factor x fastest-axis factor) and one add into the bin
-OPS_PER_UPDATE = 2
+# algorithmic arithmetic per cell-distribution update, from the definitions:
+#   propagation: density (row factor x fastest-axis factor) and its add into
+#   the bin: 2 operations;
+#   exact-f moments: density, f - s, p (f - s), the add into S1 and the
+#   multiply-add into S2: 6 operations.
+OPS_PER_UPDATE = {"propagate": 2, "moments": 6}
+KERNELS = {"propagate": "k_propagate_runs (run form) / k_propagate<FP32> (cell form)",
+           "moments": "k_moments"}
+
+
+def traffic_bytes(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy of
+    known size), or None when that summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_grid1024.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    entry = rec.get("kernels", {}).get(kernel)
+    if entry is None or entry.get("source_sha256") != source_sha256():
+        return None
+    return entry["hbm_bytes_per_launch"]
+
+
+def source_sha256():
+    """Digest of the kernel sources the counters depend on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1908_11246_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernels_once():
+    import torch
+    import paper_1908_11246_amd as vup
+    import workloads
+    wl = workloads.grid1024()
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    mu = torch.from_numpy(wl.mu).cuda()
+    sigma = torch.from_numpy(wl.sigma).cuda()
+    f = vup.eval_grid(g, wl.model, wl.theta)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
+    vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
+    vup.moments(mm, mu, sigma)
+    torch.cuda.synchronize()
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)  # last dispatch: the calibration copy
+    torch.cuda.synchronize()
+    print("kernels-once done", flush=True)
+
+
+CALIB_BYTES = 256 << 20
+# kernel-name fragments of the sweep kernels in rocprofv3 output
+TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments"}
+
+
+def _counter_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the sweep kernels, scaled
+    by the ratio of the known byte count of the calibration copy (the last
+    dispatch) to what the same counter reports for it."""
+    out = {"workload": "grid1024", "calibration_bytes": CALIB_BYTES,
+           "source_sha256": source_sha256(), "kernels": {}}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _counter_rows(path) if r["Counter_Name"] == counter]
+        by_dispatch = {}
+        for r in rows:
+            d = int(r["Dispatch_Id"])
+            by_dispatch.setdefault(d, [r["Kernel_Name"], 0.0])
+            by_dispatch[d][1] += float(r["Counter_Value"])
+        last = max(by_dispatch)
+        calib_kib = by_dispatch[last][1]
+        scale = CALIB_BYTES / (calib_kib * 1024.0)
+        out[f"{counter.lower()}_calibration"] = {"kernel": by_dispatch[last][0][:120],
+                                                 "counter_kib": calib_kib, "scale": scale}
+        for key, frag in TRACE_NAMES.items():
+            vals = [v for name, v in by_dispatch.values() if frag in name]
+            if vals:
+                per.setdefault(key, {})[counter] = vals[0] * 1024.0 * scale
+    for key, v in per.items():
+        if "FETCH_SIZE" in v and "WRITE_SIZE" in v:
+            out["kernels"][key] = {"fetch_bytes": v["FETCH_SIZE"], "write_bytes": v["WRITE_SIZE"],
+                                   "hbm_bytes_per_launch": v["FETCH_SIZE"] + v["WRITE_SIZE"],
+                                   "source_sha256": out["source_sha256"]}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "traffic_grid1024.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def summarize_stats(csv_path, out_path):
+    rows = _counter_rows(csv_path)
+    lines = ["| kernel | calls | avg (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"][5:] if r["Name"].startswith("void ") else r["Name"]
+        lines.append(f"| `{name[:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f}% |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--kernels-once":
+        return kernels_once()
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
+        return summarize_traffic(sys.argv[2], sys.argv[3])
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
+        return summarize_stats(sys.argv[2], sys.argv[3])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -69,35 +192,45 @@ def main():
     log(f"[bench] U = {U:.4e} cell-distribution updates per step")
 
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    prop_ms = []
+    parts = ["eval_grid", "edges", "model_matrix", "propagate", "moments", "ipsa"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(parts) + 1)]
 
-    def step(time_prop=False):
+    # The FP32 sweep form is a property of the model matrix, identical in every
+    # step: resolve it once (one stream sync, outside the timed steps) and set
+    # it on each rebuilt matrix without a sync.
+    f0 = vup.eval_grid(g, wl.model, wl.theta)
+    form = vup.build_model_matrix(g, f0, vup.uniform_edges(f0, wl.B), want_bin=False).sweep
+    log(f"[bench] FP32 sweep form: {form}")
+
+    def step(timed=False):
+        mark = (lambda i: ev[i].record(stream)) if timed else (lambda i: None)
+        mark(0)
         f = vup.eval_grid(g, wl.model, wl.theta)
+        mark(1)
         e = vup.uniform_edges(f, wl.B)
-        mm = vup.build_model_matrix(g, f, e, want_bin=False)
-        if time_prop:
-            ev[0].record(stream)
+        mark(2)
+        mm = vup.build_model_matrix(g, f, e, want_bin=False, resolve_sweep=False)
+        mm.set_sweep_mode(form)
+        mark(3)
         P, _ = vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
-        if time_prop:
-            ev[1].record(stream)
+        mark(4)
         mean, var, _ = vup.moments(mm, mu, sigma)
+        mark(5)
         mh, vh, ent = vup.ipsa(mm, P)
+        mark(6)
         return mm, P
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    part_ms = {k: [] for k in parts}
     for _ in range(args.steps):
-        step(time_prop=True)
-        # event pair of the last step is read after the loop; collect per step
-        ev[1].synchronize()
-        prop_ms.append(ev[0].elapsed_time(ev[1]))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # the per-step event read adds a host sync per step; time the steps again
-    # back to back without it for the headline number
+        step(timed=True)
+        ev[-1].synchronize()
+        for i, k in enumerate(parts):
+            part_ms[k].append(ev[i].elapsed_time(ev[i + 1]))
+    part_ms = {k: float(np.mean(v)) for k, v in part_ms.items()}
+    # headline: steps back to back, no per-step host sync
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(args.steps):
@@ -106,10 +239,18 @@ def main():
     t3 = time.perf_counter()
     ms_step = (t3 - t2) * 1e3 / args.steps
     value = U / (ms_step * 1e-3)
-    t_prop = float(np.mean(prop_ms)) * 1e-3
-    achieved = OPS_PER_UPDATE * U / t_prop
-    log(f"[bench] step {ms_step:.3f} ms (synced-per-step {1e3 * (t1 - t0) / args.steps:.3f} ms), "
-        f"propagate {1e3 * t_prop:.3f} ms")
+    log(f"[bench] step {ms_step:.3f} ms; parts (HIP events) " +
+        ", ".join(f"{k} {v:.3f}" for k, v in part_ms.items()))
+    # roofline of the longest sweep kernel of the step, and of the other one
+    rooflines = {}
+    for k in ("propagate", "moments"):
+        t = part_ms[k] * 1e-3
+        ach = OPS_PER_UPDATE[k] * U / t
+        rooflines[k] = {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                        "unit": "TOP/s", "frac": ach / VALU_PEAK_OPS,
+                        "traffic": traffic_bytes(k), "kernel": KERNELS[k],
+                        "kernel_ms": part_ms[k], "ops_per_update": OPS_PER_UPDATE[k]}
+    dominant = max(("propagate", "moments"), key=lambda k: part_ms[k])
 
     result = {
         "metric": "cell-distribution updates/sec (FP32 densities, full VUP+IPSA step)",
@@ -127,14 +268,14 @@ def main():
         "config": {"workload": "grid1024: 2-D 1024x1024, sincos model, B=256, K=65536 "
                                "Gaussians, sigma~U[0.05,0.5], 4-sigma truncation",
                    "grid": list(wl.n), "B": wl.B, "K": wl.K, "updates_per_step": U},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "k_propagate<FP32>", "kernel_ms": 1e3 * t_prop,
-                     "ops_per_update": OPS_PER_UPDATE},
+        "roofline": rooflines[dominant],
+        "rooflines": rooflines,
+        "step_parts_ms": part_ms,
+        "sweep_form": form,
     }
 
     # ---- variants on the same workload -------------------------------------
+    ev = ev[:2]
     if not args.no_variants:
         mm, _ = step()
         torch.cuda.synchronize()

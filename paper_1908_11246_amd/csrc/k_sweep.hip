@@ -61,6 +61,13 @@ struct SweepArgs {
   double* g_weight;
 };
 
+// element i < 4 of a small array of the kernel arguments, by selects rather
+// than an indexed load (a runtime index would copy the array to private memory)
+template <typename T>
+__device__ __forceinline__ T pick4(const T (&v)[4], int i) {
+  return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+}
+
 // per-component window state, identical in every thread of the workgroup
 struct Win {
   int lo[4];
@@ -160,13 +167,13 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
   const int L = D - 1;
   int loL, WL;
   last_axis(w, D, loL, WL);
-  float* tab = smem + a.L.tab_off[L];
+  float* tab = smem + pick4(a.L.tab_off, L);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
   for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
     const int j = colbase + jj;
     float v = 0.0f;
     if (j >= loL && j < loL + WL) {
-      const double x = cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], j);
+      const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j);
       v = gauss_factor_r(x, mu, rsig);
     }
     tab[jj] = v;
@@ -305,7 +312,7 @@ template <int PREC>
 __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
                                             int sw, double* red, PropScales* ps) {
   const int D = a.g.ndim;
-  const float* tabL = smem + a.L.tab_off[D - 1];
+  const float* tabL = smem + pick4(a.L.tab_off, D - 1);
   // column classes: by the largest factor of each strip
   double cm[3] = {0.0, 0.0, 0.0};
   for (int st = threadIdx.x; st < ns; st += kThreads) {
@@ -386,7 +393,7 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
   // byte offset between row classes (3 column classes x cpc copies each)
   const int rcstep = 3 * cpc * strideb;
   char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off) + (ph & (cpc - 1)) * strideb;
-  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  const float* tabL = smem + pick4(a.L.tab_off, a.g.ndim - 1);
   for (int s = col; s < ns; s += cols) {
     float gl[SW];
     float gmax = 0.0f;
@@ -574,7 +581,7 @@ __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* sme
                                                   int loL, int WL, double* red) {
   const int D = a.g.ndim;
   const int L = D - 1;
-  const int nL = a.g.n[L];
+  const int nL = pick4(a.g.n, L);
   double* G = reinterpret_cast<double*>(smem + a.L.g_off);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
   const int per = (WL + kThreads - 1) / kThreads;
@@ -583,7 +590,7 @@ __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* sme
   double* Gw = G + loL;  // Gw[j + 1] = sum over window columns loL .. loL + j
   double sum = 0.0;
   for (int j = j0; j < j1; ++j) {
-    const double x = cell_centre(a.g.lo[L], a.g.hi[L], nL, loL + j);
+    const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), nL, loL + j);
     const double g = (double)gauss_factor_r(x, mu, rsig);
     Gw[j + 1] = g;
     sum += g;
@@ -838,7 +845,7 @@ __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, 
   const int ph = threadIdx.x / cols;
   if (ph >= P0) return;
   const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
-  const float* tabL = smem + a.L.tab_off[a.g.ndim - 1];
+  const float* tabL = smem + pick4(a.L.tab_off, a.g.ndim - 1);
   for (int s = col; s < ns; s += cols) {
     float gl[SW];
 #pragma unroll
@@ -972,11 +979,11 @@ __device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, 
   const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
   const float4* tt = reinterpret_cast<const float4*>(smem + a.L.trow_off);
   const char* vt = reinterpret_cast<const char*>(smem + a.L.hist_off);
-  const float* tabL = smem + a.L.tab_off[L];
+  const float* tabL = smem + pick4(a.L.tab_off, L);
   for (int s = col; s < ns; s += cols) {
     float gl[SW], g1[SW], g2[SW];
     const float* tab1 = smem + a.L.g_off;
-    const float* tab2 = tab1 + a.L.cap[L];
+    const float* tab2 = tab1 + pick4(a.L.cap, L);
 #pragma unroll
     for (int j = 0; j < SW; ++j) {
       gl[j] = tabL[s * SW + j];
@@ -1098,11 +1105,11 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     build_tables(a, smem, w, kc, sw, colbase, ns);
     {
       float* tab1 = smem + a.L.g_off;
-      float* tab2 = tab1 + a.L.cap[L];
+      float* tab2 = tab1 + pick4(a.L.cap, L);
       const double muL = a.d.mu[kc * D + L], rsg = 1.0 / a.d.sigma[kc * D + L];
       for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
-        const double t = (cell_centre(a.g.lo[L], a.g.hi[L], a.g.n[L], colbase + jj) - muL) * rsg;
-        const double g = (double)smem[a.L.tab_off[L] + jj];
+        const double t = (cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), colbase + jj) - muL) * rsg;
+        const double g = (double)smem[pick4(a.L.tab_off, L) + jj];
         tab1[jj] = (float)(g * t);
         tab2[jj] = (float)(g * t * t);
       }
