@@ -5,7 +5,8 @@
 //   k_bin           indicator of eq. (4) as a bin index; padded bin map
 //                   (4*bin, LDS byte offsets for the sweep kernels), padded
 //                   FP32 copy of f, per-chunk bin counts
-//   k_scan_counts   exclusive scan of the counts in (bin, chunk) order
+//   k_tile_sums, k_scan_tile_sums, k_tile_scan  exclusive scan of the counts in
+//                   (bin, chunk) order; k_csr_offsets  CSR row starts and counts
 //   k_scatter       stable scatter of cell indices into compressed-by-bin
 //                   order (the sparse one-hot model matrix of eq. (5))
 // plus the per-distribution window listing and the IPSA column statistics.
@@ -141,6 +142,7 @@ struct BinArgs {
   int pitch;
   long long rows;
   long long nblk;
+  int chunk;          // padded positions per chunk
 };
 
 // bin index of y: largest b < B with e[b] <= y, when e[0] <= y <= e[B]
@@ -174,10 +176,10 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     for (int b = threadIdx.x; b <= a.B; b += 256) a.edges_ws[b] = e[b];
     if (threadIdx.x == 0 && bad) atomicAdd(a.counters + kCntBadEdges, 1ull);
   }
-  const long long base = (long long)blockIdx.x * kBinChunk;
+  const long long base = (long long)blockIdx.x * a.chunk;
   const long long total = a.rows * a.pitch;
   int outside = 0;
-  for (int q = threadIdx.x; q < kBinChunk; q += 256) {
+  for (int q = threadIdx.x; q < a.chunk; q += 256) {
     const long long p = base + q;
     if (p >= total) break;
     const long long row = p / a.pitch;
@@ -207,41 +209,112 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   for (int b = threadIdx.x; b <= a.B; b += 256) a.chunk_counts[(long long)b * a.nblk + blockIdx.x] = cnt[b];
 }
 
-// exclusive scan of chunk_counts in (bin, chunk) order by one workgroup;
-// also per-bin totals and CSR row starts
-__global__ __launch_bounds__(1024) void k_scan_counts(int* cc, long long len, long long nblk, int B,
-                                                      long long N, long long* counts,
-                                                      long long* offsets) {
-  __shared__ long long part[1024];
-  const long long per = (len + 1023) / 1024;
-  const long long s0 = threadIdx.x * per < len ? threadIdx.x * per : len;
-  const long long s1 = s0 + per < len ? s0 + per : len;
+// ---------------------------------------------------------------------------
+// exclusive prefix sum of n ints in place (values and sums below 2^31), by
+// tiles of kScanTile: tile totals, one workgroup scanning the totals, then
+// each tile scanned from its offset. `tsum` holds ceil(n / kScanTile) int64.
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 16;                 // elements per thread
+constexpr int kScanTile = 256 * kScanPer;    // elements per workgroup
+
+__global__ __launch_bounds__(256) void k_tile_sums(const int* __restrict__ v, long long n,
+                                                   long long* __restrict__ tsum) {
+  __shared__ long long red[4];
+  const long long base = (long long)blockIdx.x * kScanTile;
   long long sum = 0;
-  for (long long i = s0; i < s1; ++i) sum += cc[i];
-  part[threadIdx.x] = sum;
+  for (int i = threadIdx.x; i < kScanTile; i += 256) {
+    const long long p = base + i;
+    if (p < n) sum += v[p];
+  }
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    long long run = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const long long v = part[t];
-      part[t] = run;
-      run += v;
-    }
+  if (threadIdx.x == 0) tsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// inclusive scan of one value per thread across a 1024-thread (or smaller)
+// workgroup; `wsum` is LDS for one value per wave
+__device__ __forceinline__ long long block_incl_scan(long long x, long long* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  long long off = 0;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  __syncthreads();
+  return x + off;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(long long* tsum, long long ntiles,
+                                                         int* total) {
+  __shared__ long long wsum[16];
+  __shared__ long long last;
+  long long carry = 0;
+  for (long long b0 = 0; b0 < ntiles; b0 += 1024) {
+    const long long i = b0 + threadIdx.x;
+    const long long x = i < ntiles ? tsum[i] : 0;
+    const long long incl = block_incl_scan(x, wsum);
+    if (i < ntiles) tsum[i] = carry + incl - x;
+    if (threadIdx.x == 1023) last = incl;
+    __syncthreads();
+    carry += last;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = (int)carry;
+}
+
+__global__ __launch_bounds__(256) void k_tile_scan(int* __restrict__ v, long long n,
+                                                   const long long* __restrict__ tsum) {
+  __shared__ int tile[kScanTile];
+  __shared__ long long wsum[4];
+  const long long base = (long long)blockIdx.x * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += 256) {
+    const long long p = base + i;
+    tile[i] = p < n ? v[p] : 0;
   }
   __syncthreads();
-  long long run = part[threadIdx.x];
-  for (long long i = s0; i < s1; ++i) {
-    const long long v = cc[i];
-    cc[i] = (int)run;  // exclusive position (< N)
-    run += v;
+  long long s = 0;
+  for (int j = 0; j < kScanPer; ++j) s += tile[threadIdx.x * kScanPer + j];
+  const long long excl = block_incl_scan(s, wsum) - s + tsum[blockIdx.x];
+  long long run = excl;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int x = tile[threadIdx.x * kScanPer + j];
+    tile[threadIdx.x * kScanPer + j] = (int)run;
+    run += x;
   }
   __syncthreads();
-  // bin b occupies [b*nblk, (b+1)*nblk); its first position is the CSR start.
-  // Slot B collects the cells without a bin, after all binned cells.
-  for (int b = threadIdx.x; b <= B; b += 1024) offsets[b] = cc[(long long)b * nblk];
-  __syncthreads();
-  for (int b = threadIdx.x; b <= B; b += 1024)
-    counts[b] = ((b < B) ? offsets[b + 1] : N) - offsets[b];
+  for (int i = threadIdx.x; i < kScanTile; i += 256) {
+    const long long p = base + i;
+    if (p < n) v[p] = tile[i];
+  }
+}
+
+long long scan_tiles(long long n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_scan_excl(int* v, long long n, long long* tsum, int* total, hipStream_t s) {
+  const long long nt = scan_tiles(n);
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)nt), dim3(256), 0, s, v, n, tsum);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(1024), 0, s, tsum, nt, total);
+  hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)nt), dim3(256), 0, s, v, n, tsum);
+  return hipGetLastError();
+}
+
+// CSR of the model matrix from the scanned chunk counts: bin b occupies
+// [b*nblk, (b+1)*nblk) in (bin, chunk) order, so its first position is the
+// row start; slot B collects the cells without a bin, after all binned cells.
+__global__ __launch_bounds__(256) void k_csr_offsets(const int* __restrict__ cc, long long nblk,
+                                                     int B, long long N, long long* counts,
+                                                     long long* offsets) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b > B) return;
+  const long long start = cc[(long long)b * nblk];
+  const long long next = b < B ? (long long)cc[(long long)(b + 1) * nblk] : N;
+  offsets[b] = start;
+  counts[b] = next - start;
 }
 
 // one wave per chunk: cells in increasing order, stable within each bin
@@ -250,10 +323,10 @@ __global__ __launch_bounds__(64) void k_scatter(BinArgs a, const int* __restrict
   extern __shared__ int pos[];  // [B+1] running positions of this chunk
   for (int b = threadIdx.x; b <= a.B; b += 64) pos[b] = cc[(long long)b * a.nblk + blockIdx.x];
   __syncthreads();
-  const long long base = (long long)blockIdx.x * kBinChunk;
+  const long long base = (long long)blockIdx.x * a.chunk;
   const long long total = a.rows * a.pitch;
   const int lane = threadIdx.x;
-  for (int q0 = 0; q0 < kBinChunk; q0 += 64) {
+  for (int q0 = 0; q0 < a.chunk; q0 += 64) {
     const long long p = base + q0 + lane;
     int b = -2;
     long long cell = -1;
@@ -305,12 +378,17 @@ hipError_t launch_bin(const vup_mm& mm, const double* f, const double* edges, in
   a.pitch = mm.pitch;
   a.rows = mm.rows;
   a.nblk = L.nblk;
+  a.chunk = L.chunk;
   const size_t lds = (size_t)(mm.B + 1) * 8 + (size_t)(mm.B + 1) * 4;
   hipLaunchKernelGGL(k_bin, dim3((unsigned)L.nblk), dim3(256), lds, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.chunk_counts,
-                     (long long)(mm.B + 1) * L.nblk, L.nblk, mm.B, (long long)mm.N,
+  const long long nc = (long long)(mm.B + 1) * L.nblk;
+  err = launch_scan_excl(a.chunk_counts, nc, reinterpret_cast<long long*>(ws + L.off_tsum), nullptr,
+                         s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_csr_offsets, dim3((unsigned)((mm.B + 1 + 255) / 256)), dim3(256), 0, s,
+                     a.chunk_counts, L.nblk, mm.B, (long long)mm.N,
                      reinterpret_cast<long long*>(ws + mm.off_counts),
                      reinterpret_cast<long long*>(ws + mm.off_offsets));
   err = hipGetLastError();
@@ -415,7 +493,12 @@ bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
   for (int d = 0; d + 1 < g.ndim; ++d) L.rows *= g.n[d];
   const long long N = L.rows * nL;
   const long long padded = L.rows * L.pitch;
-  L.nblk = (padded + kBinChunk - 1) / kBinChunk;
+  // chunks of the bin sort: small for parallelism, larger when the (bin,
+  // chunk) count table would grow past 2^24 entries
+  L.chunk = 1024;
+  while ((long long)(B + 1) * ((padded + L.chunk - 1) / L.chunk) > (1ll << 24) && L.chunk < 65536)
+    L.chunk *= 2;
+  L.nblk = (padded + L.chunk - 1) / L.chunk;
   const long long rowblocks = L.rows * (L.pitch / 32);
   size_t o = 0;
   L.off_edges = o;
@@ -433,7 +516,10 @@ bool ws_layout(const vup_grid& g, int B, WsLayout* out) {
   L.off_scratch = o;
   const size_t sort_scratch = (size_t)(B + 1) * (size_t)L.nblk * 4;
   const size_t run_scratch = (size_t)rowblocks * 4;
-  o = align256(o + (sort_scratch > run_scratch ? sort_scratch : run_scratch));
+  const size_t scratch = sort_scratch > run_scratch ? sort_scratch : run_scratch;
+  o = align256(o + scratch);
+  L.off_tsum = o;  // tile sums of the prefix scans
+  o = align256(o + (size_t)(scan_tiles((long long)(scratch / 4)) + 1) * 8);
   L.off_counters = o;
   o = align256(o + 8 * 8);
   L.off_runs = o;
@@ -483,34 +569,6 @@ __global__ __launch_bounds__(256) void k_runs_count(RunArgs a) {
   }
   for (int o = 32; o > 0; o >>= 1) real += __shfl_xor(real, o, 64);
   if ((threadIdx.x & 63) == 0 && real) atomicAdd(a.counters + kCntRuns, real);
-}
-
-// exclusive prefix sum of n ints in place, one workgroup
-__global__ __launch_bounds__(1024) void k_scan_excl(int* v, long long n, int* total) {
-  __shared__ long long part[1024];
-  const long long per = (n + 1023) / 1024;
-  const long long s0 = threadIdx.x * per < n ? threadIdx.x * per : n;
-  const long long s1 = s0 + per < n ? s0 + per : n;
-  long long sum = 0;
-  for (long long i = s0; i < s1; ++i) sum += v[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long run = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const long long x = part[t];
-      part[t] = run;
-      run += x;
-    }
-    *total = (int)run;
-  }
-  __syncthreads();
-  long long run = part[threadIdx.x];
-  for (long long i = s0; i < s1; ++i) {
-    const long long x = v[i];
-    v[i] = (int)run;
-    run += x;
-  }
 }
 
 __global__ __launch_bounds__(256) void k_runs_fill(RunArgs a) {
@@ -576,8 +634,12 @@ hipError_t launch_runs(const vup_mm& mm, hipStream_t s) {
   const long long n = a.rows * a.nb;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_runs_count, dim3(blocks), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, a.blockcnt, n,
-                     reinterpret_cast<int*>(a.counters + kCntScratch));
+  WsLayout L;
+  ws_layout(mm.grid, mm.B, &L);
+  const hipError_t err =
+      launch_scan_excl(a.blockcnt, n, reinterpret_cast<long long*>(ws + L.off_tsum),
+                       reinterpret_cast<int*>(a.counters + kCntScratch), s);
+  if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_runs_fill, dim3(blocks), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_rowptr_end, dim3(1), dim3(64), 0, s, a.rowptr, a.rows,
                      reinterpret_cast<const int*>(a.counters + kCntScratch));

@@ -12,9 +12,6 @@ namespace vup {
 
 constexpr uint64_t kMagic = 0x5655504d4d763031ull;  // "VUPMMv01"
 
-// sort / bin kernels work on chunks of this many padded positions
-constexpr int kBinChunk = 4096;
-
 // LDS layout of a sweep kernel (offsets in floats from the start of dynamic LDS)
 struct SweepLayout {
   int tab_off[4];
@@ -64,10 +61,15 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
 struct WsLayout {
   int pitch;
   int64_t rows;
-  int64_t nblk;  // chunks of kBinChunk padded positions
+  int64_t nblk;  // chunks of the bin sort
+  int chunk;     // padded positions per chunk
   size_t off_edges, off_binmap, off_f32, off_counts, off_offsets, off_perm, off_scratch,
-      off_counters, off_runs, off_rowptr, off_runidx, bytes;
+      off_counters, off_runs, off_rowptr, off_runidx, off_tsum, bytes;
 };
 bool ws_layout(const vup_grid& g, int B, WsLayout* out);
+// exclusive prefix sum of n ints in place; tsum: scan_tiles(n) int64 scratch;
+// total (device int) may be null
+long long scan_tiles(long long n);
+hipError_t launch_scan_excl(int* v, long long n, long long* tsum, int* total, hipStream_t s);
 
 }  // namespace vup
