@@ -96,15 +96,16 @@ __device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* w
     wsh[8 + d] = flags;
   }
   __syncthreads();
+  // the values are uniform: keep them in scalar registers
   Win w;
   w.R = 1;
-  const int flags = wsh[8] | wsh[9] | wsh[10] | wsh[11];
+  const int flags = __builtin_amdgcn_readfirstlane(wsh[8] | wsh[9] | wsh[10] | wsh[11]);
   w.bad = (flags & 1) != 0;
   w.empty = (flags & 2) != 0;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    w.lo[d] = wsh[d];
-    w.W[d] = wsh[4 + d];
+    w.lo[d] = __builtin_amdgcn_readfirstlane(wsh[d]);
+    w.W[d] = __builtin_amdgcn_readfirstlane(wsh[4 + d]);
     if (d + 1 < D) w.R *= (w.W[d] > 0 ? w.W[d] : 0);
   }
   return w;
