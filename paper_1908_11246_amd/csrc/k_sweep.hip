@@ -452,28 +452,36 @@ __device__ __forceinline__ void finish_component(const SweepArgs& a, const uint3
                                                  long long kc, float* Pk, bool written) {
   const int B = a.B;
   const int stride = a.L.hist_stride;
-  double zpart = 0.0;
-  for (int b = threadIdx.x; b <= B; b += kThreads) {
+  auto slot = [&](int b) {
     double v = 0.0;
     for (int cl = 0; cl < ncls; ++cl) {
       uint64_t cnt = 0;
       for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * stride + b];
       v += (double)cnt * unscale[cl];
     }
-    zpart += v;
+    return v;
+  };
+  const double wk = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
+  if (B + 1 <= 2 * kThreads) {
+    // at most two slots per thread: keep them in registers
+    const int b0 = threadIdx.x, b1 = threadIdx.x + kThreads;
+    const double v0 = b0 <= B ? slot(b0) : 0.0;
+    const double v1 = b1 <= B ? slot(b1) : 0.0;
+    const double Zc = block_sum(v0 + v1, red);
+    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+    const double f = wk / Zc;
+    if (b0 < B) Pk[b0] = (float)((written ? (double)Pk[b0] : 0.0) + v0 * f);
+    if (b1 < B) Pk[b1] = (float)((written ? (double)Pk[b1] : 0.0) + v1 * f);
+    return;
   }
+  double zpart = 0.0;
+  for (int b = threadIdx.x; b <= B; b += kThreads) zpart += slot(b);
   const double Zc = block_sum(zpart, red);
   if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
-  const double f = ((a.d.C > 1) ? a.d.weight[kc] : 1.0) / Zc;
+  const double f = wk / Zc;
   for (int b = threadIdx.x; b < B; b += kThreads) {
-    double v = 0.0;
-    for (int cl = 0; cl < ncls; ++cl) {
-      uint64_t cnt = 0;
-      for (int cp = 0; cp < cpc; ++cp) cnt += hist[(cl * cpc + cp) * stride + b];
-      v += (double)cnt * unscale[cl];
-    }
     const double prev = written ? (double)Pk[b] : 0.0;
-    Pk[b] = (float)(prev + v * f);
+    Pk[b] = (float)(prev + slot(b) * f);
   }
 }
 
@@ -598,12 +606,7 @@ __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* sme
   }
   // inclusive scan of the slice sums within the wave, then across waves
   const int lane = threadIdx.x & 63;
-  double incl = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double t = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += t;
-  }
+  const double incl = wave_scan(sum);
   if (lane == 63) red[threadIdx.x >> 6] = incl;
   __syncthreads();
   double run = incl - sum;

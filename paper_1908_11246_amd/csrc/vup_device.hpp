@@ -184,9 +184,46 @@ __device__ __forceinline__ float quantize(float w) {
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// DPP moves of an FP64 value (both halves with the same pattern); lanes whose
+// source falls outside their 16-lane row read 0
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFF), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// value of one lane (uniform result)
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFF), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// inclusive prefix sum within each 16-lane row (row_shr 1, 2, 4, 8)
+__device__ __forceinline__ double row_scan(double v) {
+  v += dpp_f64<0x111>(v);
+  v += dpp_f64<0x112>(v);
+  v += dpp_f64<0x114>(v);
+  v += dpp_f64<0x118>(v);
   return v;
+}
+
+// sum over the 64 lanes (all lanes active), in a fixed order; uniform result
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_scan(v);
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+
+// inclusive prefix sum over the 64 lanes (all lanes active)
+__device__ __forceinline__ double wave_scan(double v) {
+  v = row_scan(v);
+  const int row = (threadIdx.x & 63) >> 4;
+  const double r0 = lane_value(v, 15), r1 = lane_value(v, 31), r2 = lane_value(v, 47);
+  const double before = row == 0 ? 0.0 : (row == 1 ? r0 : (row == 2 ? r0 + r1 : (r0 + r1) + r2));
+  return v + before;
 }
 
 // deterministic block sum of one double per thread; `red` is LDS scratch of
