@@ -822,7 +822,7 @@ __device__ __forceinline__ void mom_load(const SweepArgs& a, const float2* rt, c
 
 template <int SW>
 __device__ __forceinline__ void mom_sum(const MomRow<SW>& m, const float* gl, float shift,
-                                        double& A1, double& A2) {
+                                        float& B1, float& B2) {
   float a1 = 0.0f, a2 = 0.0f;
 #pragma unroll
   for (int q = 0; q < SW / 4; ++q) {
@@ -835,8 +835,8 @@ __device__ __forceinline__ void mom_sum(const MomRow<SW>& m, const float* gl, fl
       a2 = fmaf(t, dv, a2);
     }
   }
-  A1 = fma((double)m.go, (double)a1, A1);
-  A2 = fma((double)m.go, (double)a2, A2);
+  B1 = fmaf(m.go, a1, B1);
+  B2 = fmaf(m.go, a2, B2);
 }
 
 template <int SW>
@@ -859,16 +859,28 @@ __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, 
     if (r >= rc) continue;
     MomRow<SW> ma, mb;
     mom_load<SW>(a, rt, fbase, r, ma);
+    // row sums times the row factor gather in FP32 over at most eight rows,
+    // then in FP64
+    float B1 = 0.0f, B2 = 0.0f;
+    int pairs = 0;
     for (;;) {
       const int rb = r + P0;
       if (rb < rc) mom_load<SW>(a, rt, fbase, rb, mb);
-      mom_sum<SW>(ma, gl, shift, A1, A2);
+      mom_sum<SW>(ma, gl, shift, B1, B2);
       if (rb >= rc) break;
       r = rb + P0;
       if (r < rc) mom_load<SW>(a, rt, fbase, r, ma);
-      mom_sum<SW>(mb, gl, shift, A1, A2);
+      mom_sum<SW>(mb, gl, shift, B1, B2);
       if (r >= rc) break;
+      if (++pairs == 4) {
+        A1 += (double)B1;
+        A2 += (double)B2;
+        B1 = B2 = 0.0f;
+        pairs = 0;
+      }
     }
+    A1 += (double)B1;
+    A2 += (double)B2;
   }
 }
 
@@ -1040,23 +1052,19 @@ __device__ __forceinline__ void bwd_rows(const SweepArgs& a, const float* smem, 
   }
 }
 
-// NO = ndim - 1 slower axes (a compile-time count keeps the accumulators of
-// absent axes out of the registers)
-template <int NO>
-__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
-  extern __shared__ float smem[];
-  const long long k = block_k(a);
-  if (k >= a.d.K) return;
-  const int D = a.g.ndim;
+// LDS table of the adjoint weights of distribution k's bins (the table is FP32,
+// so ln P_b is taken in FP32; P_b itself is FP32):
+// S = sum_b P_b (c_b - E); v_b = gv((c_b - E)^2 - 2 c_b S) - ge(ln P_b + 1);
+// vref = sum_b P_b v_b is subtracted from the table (covariances are shift
+// invariant) and returned, to be added back for the weight gradient. Cells
+// without a bin do not enter Var or H: their slot B holds -vref (v = 0).
+__device__ __forceinline__ double build_vtable(const SweepArgs& a, float* vt, long long k,
+                                               double* red) {
   const int B = a.B;
-  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
   const float* Pk = a.Pin + k * (long long)B;
   const double gv = a.g_var ? a.g_var[k] : 0.0;
   const double ge = a.g_ent ? a.g_ent[k] : 0.0;
   const double E = a.mean_hist[k];
-  // S = sum_b P_b (c_b - E); v_b = gv((c_b - E)^2 - 2 c_b S) - ge(ln P_b + 1);
-  // vref = sum_b P_b v_b is subtracted from the table (covariances are
-  // shift invariant) and added back for the weight gradient.
   double sp = 0.0;
   for (int b = threadIdx.x; b < B; b += kThreads) {
     const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
@@ -1068,22 +1076,59 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
     const double pb = (double)Pk[b];
     double v = gv * ((cb - E) * (cb - E) - 2.0 * cb * S);
-    if (pb > 0.0) v -= ge * (log(pb) + 1.0);
+    if (pb > 0.0) v -= ge * ((double)logf((float)pb) + 1.0);
     vp += pb * v;
   }
   const double vref = block_sum(vp, red);
-  float* vt = smem + a.L.hist_off;
   for (int b = threadIdx.x; b <= B; b += kThreads) {
     double v = 0.0;
     if (b < B) {
       const double cb = 0.5 * (a.edges[b] + a.edges[b + 1]);
       const double pb = (double)Pk[b];
       v = gv * ((cb - E) * (cb - E) - 2.0 * cb * S);
-      if (pb > 0.0) v -= ge * (log(pb) + 1.0);
+      if (pb > 0.0) v -= ge * ((double)logf((float)pb) + 1.0);
     }
-    // cells without a bin do not enter Var or H: their v is 0
     vt[b] = (float)(v - vref);
   }
+  return vref;
+}
+
+// Gradients of component kc from the normalised sweep sums: A0 = E[v],
+// l1, l2 = E[v t], E[v t^2] along the fastest axis, t1[d], t2[d] the same for
+// the slower axes, m1[d], m2[d] = E[t], E[t^2] per axis (covariances, since
+// the weight table is centred), scaled by the mixture weight pc.
+__device__ __forceinline__ void write_grads(const SweepArgs& a, long long kc, double pc,
+                                            double A0, double l1, double l2, const double* t1,
+                                            const double* t2, const double* m1,
+                                            const double* m2, double vref) {
+  if (threadIdx.x != 0) return;
+  const int D = a.g.ndim;
+  const int L = D - 1;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (d < D) {
+      const double sg = a.d.sigma[kc * D + d];
+      const double s1 = (d == L) ? l1 : t1[d < 3 ? d : 0];
+      const double s2 = (d == L) ? l2 : t2[d < 3 ? d : 0];
+      a.g_mu[kc * D + d] = pc * (s1 - m1[d] * A0) / sg;
+      a.g_sigma[kc * D + d] = pc * (s2 - m2[d] * A0) / sg;
+    }
+  }
+  if (a.g_weight) a.g_weight[kc] = A0 + vref;
+}
+
+// NO = ndim - 1 slower axes (a compile-time count keeps the accumulators of
+// absent axes out of the registers)
+template <int NO>
+__global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
+  extern __shared__ float smem[];
+  if (runs_chosen(a)) return;  // k_backward_runs does the work
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  float* vt = smem + a.L.hist_off;
+  const double vref = build_vtable(a, vt, k, red);
   for (int c = 0; c < a.d.C; ++c) {
     const long long kc = k * a.d.C + c;
     const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
@@ -1168,19 +1213,315 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     t2[3] = 0.0;
     const double l1 = block_sum(acc.l1, red) / Z;
     const double l2 = block_sum(acc.l2, red) / Z;
-    if (threadIdx.x == 0) {
+    write_grads(a, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep, run form. With the run form of the model matrix and the
+// separable density, the three fastest-axis sums the adjoint needs over a run
+// [s, e) are differences of prefix sums over the axis: G0 of g, G1 of g t and
+// G2 of g t^2 (t = (x - mu)/sigma), summed in FP64 and held in LDS as FP32
+// (flat outside the window) at offset 0, one 16-byte entry per column. A run
+// costs two 16-byte LDS reads, the bin's weight and three FMAs; there are no
+// atomics: each lane keeps its own sums, applied per row with the row factor
+// (and the slower axes' t). Rows, lanes and the DPP hand-over of run ends are
+// as in the run-form propagation.
+// ---------------------------------------------------------------------------
+struct BwdRunRow {
+  float go;    // row factor
+  float t[3];  // standardised coordinates of the slower axes
+  int ra;      // first run of the row's window segment
+  int cnt;     // runs in the segment
+  int pad[2];
+};
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(3))) f32x4v lds_f4;
+__device__ __forceinline__ f32x4v lds_load_f4(uint32_t byte_addr) {
+  return *(lds_f4*)(size_t)byte_addr;
+}
+
+// (x & 0xFFFF) * 16 in one VALU op
+__device__ __forceinline__ uint32_t lo16_times16(uint32_t x) {
+  uint32_t r;
+  asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+      "src1_sel:WORD_0"
+      : "=v"(r)
+      : "v"(x));
+  return r;
+}
+
+// G3[c] = (G0, G1, G2, -) for c = 0 .. n (sums over the window columns below
+// c); the FP64 window totals go to tot[0..2].
+__device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem, long long kc,
+                                                 int loL, int WL, double* red, double* tot) {
+  const int D = a.g.ndim;
+  const int L = D - 1;
+  const int nL = pick4(a.g.n, L);
+  const double lo = pick4(a.g.lo, L), hi = pick4(a.g.hi, L);
+  float4* G3 = reinterpret_cast<float4*>(smem);
+  const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
+  const int per = (WL + kThreads - 1) / kThreads;
+  const int j0 = min((int)threadIdx.x * per, WL);
+  const int j1 = min(j0 + per, WL);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
+    const float gf = gauss_factor_r(cell_centre(lo, hi, nL, loL + j), mu, rsig);
+    const double g = (double)gf;
+    s0 += g;
+    s1 += g * t;
+    s2 += g * t * t;
+    G3[loL + j + 1].w = gf;  // the factor, until the sums overwrite the entry
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double i0 = wave_scan(s0), i1 = wave_scan(s1), i2 = wave_scan(s2);
+  if (lane == 63) {
+    red[wv] = i0;
+    red[4 + wv] = i1;
+    red[8 + wv] = i2;
+  }
+  __syncthreads();
+  double r0 = i0 - s0, r1 = i1 - s1, r2 = i2 - s2;
+  for (int w = 0; w < wv; ++w) {
+    r0 += red[w];
+    r1 += red[4 + w];
+    r2 += red[8 + w];
+  }
+  for (int j = j0; j < j1; ++j) {
+    const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
+    const double g = (double)G3[loL + j + 1].w;
+    r0 += g;
+    r1 += g * t;
+    r2 += g * t * t;
+    G3[loL + j + 1] = make_float4((float)r0, (float)r1, (float)r2, 0.0f);
+  }
+  const double T0 = (red[0] + red[1]) + (red[2] + red[3]);
+  const double T1 = (red[4] + red[5]) + (red[6] + red[7]);
+  const double T2 = (red[8] + red[9]) + (red[10] + red[11]);
+  for (int c = threadIdx.x; c <= loL; c += kThreads) G3[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int c = loL + WL + 1 + threadIdx.x; c <= nL; c += kThreads)
+    G3[c] = make_float4((float)T0, (float)T1, (float)T2, 0.0f);
+  if (threadIdx.x == 0) {
+    tot[0] = T0;
+    tot[1] = T1;
+    tot[2] = T2;
+  }
+  __syncthreads();
+}
+
+// row table of the adjoint run form for rows [r0, r0 + rc) of the window
+__device__ __forceinline__ void build_rows_bwd_runs(const SweepArgs& a, float* smem, const Win& w,
+                                                    long long r0, int rc, long long kc, int loL,
+                                                    int hiL) {
+  const int D = a.g.ndim;
+  BwdRunRow* rt = reinterpret_cast<BwdRunRow*>(smem + a.L.row_off);
+  double rsig[3];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        if (d < D) {
-          const double sg = a.d.sigma[kc * D + d];
-          const double s1 = (d == L) ? l1 : t1[d < 3 ? d : 0];
-          const double s2 = (d == L) ? l2 : t2[d < 3 ? d : 0];
-          a.g_mu[kc * D + d] = pc * (s1 - m1[d] * A0) / sg;
-          a.g_sigma[kc * D + d] = pc * (s2 - m2[d] * A0) / sg;
-        }
+  for (int d = 0; d < 3; ++d) rsig[d] = d + 1 < D ? 1.0 / a.d.sigma[kc * D + d] : 0.0;
+  for (int r = threadIdx.x; r < rc; r += kThreads) {
+    int t = (int)r0 + r;
+    float go = 1.0f;
+    float tv[3] = {0.0f, 0.0f, 0.0f};
+    int gr = 0, mul = 1;
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+      if (d <= D - 2) {
+        const int i = d == 0 ? t : t % w.W[d];
+        if (d > 0) t /= w.W[d];
+        go *= smem[a.L.tab_off[d] + i];
+        gr += (w.lo[d] + i) * mul;
+        mul *= a.g.n[d];
+        const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
+        tv[d] = (float)((x - a.d.mu[kc * D + d]) * rsig[d]);
       }
-      if (a.g_weight) a.g_weight[kc] = A0 + vref;
     }
+    const int off = gr * a.g.pitch;
+    const int base = a.rowptr[gr];
+    BwdRunRow e;
+    e.go = go;
+    e.t[0] = tv[0];
+    e.t[1] = tv[1];
+    e.t[2] = tv[2];
+    e.ra = base + (int)a.runidx[off + loL];
+    e.cnt = base + (int)a.runidx[off + hiL] + 1 - e.ra;
+    e.pad[0] = e.pad[1] = 0;
+    rt[r] = e;
+  }
+}
+
+template <int NO>
+__device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc,
+                                         BwdAcc<NO>& acc) {
+  const int l = threadIdx.x & (kRunGroup - 1);
+  const int gi = (threadIdx.x >> 4) & 3;
+  const int wv = threadIdx.x >> 6;
+  const BwdRunRow* rt = reinterpret_cast<const BwdRunRow*>(smem + a.L.row_off);
+  const char* vt = reinterpret_cast<const char*>(smem + a.L.hist_off);
+  const int bl = (rc + 3) >> 2;
+  const int rend = min((gi + 1) * bl, rc);
+  struct {
+    float a0, l1, l2, o1[NO > 0 ? NO : 1], o2[NO > 0 ? NO : 1];
+  } b = {};
+  int nrow = 0;
+  auto flush = [&]() {
+    acc.a0 += (double)b.a0;
+    acc.l1 += (double)b.l1;
+    acc.l2 += (double)b.l2;
+#pragma unroll
+    for (int d = 0; d < NO; ++d) {
+      acc.o1[d] += (double)b.o1[d];
+      acc.o2[d] += (double)b.o2[d];
+    }
+    b = {};
+  };
+  for (int r = gi * bl + wv; r < rend; r += kWaves) {
+    const BwdRunRow row = rt[r];
+    const int cnt = row.cnt;
+    const uint32_t* rp = a.runs + row.ra;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    auto step = [&](uint32_t c, uint32_t dc, uint32_t dn, int left) {
+      const uint32_t nx = (l == kRunGroup - 1) ? dn : dc;
+      if (left > 0) {
+        const f32x4v gs = lds_load_f4(lo16_times16(c));
+        const f32x4v ge = lds_load_f4(lo16_times16(nx));
+        const float vb = *reinterpret_cast<const float*>(vt + (c >> 16));
+        a0 = fmaf(vb, ge.x - gs.x, a0);
+        a1 = fmaf(vb, ge.y - gs.y, a1);
+        a2 = fmaf(vb, ge.z - gs.z, a2);
+      }
+    };
+    uint32_t cur = rp[l];
+    uint32_t dcur = next_lane(cur);
+    for (int q0 = l; q0 - l < cnt; q0 += 4 * kRunGroup) {
+      const uint32_t* p = rp + q0;
+      const uint32_t r1 = p[kRunGroup];
+      const uint32_t r2 = p[2 * kRunGroup];
+      const uint32_t r3 = p[3 * kRunGroup];
+      const uint32_t r4 = p[4 * kRunGroup];
+      const uint32_t d1 = next_lane(r1), d2 = next_lane(r2);
+      const uint32_t d3 = next_lane(r3), d4 = next_lane(r4);
+      const int left = cnt - q0;
+      step(cur, dcur, d1, left);
+      step(r1, d1, d2, left - kRunGroup);
+      step(r2, d2, d3, left - 2 * kRunGroup);
+      step(r3, d3, d4, left - 3 * kRunGroup);
+      cur = r4;
+      dcur = d4;
+    }
+    // per-row sums times the row factor (and the slower axes' t), gathered
+    // in FP32 over at most eight rows, then in FP64
+    const float c0 = row.go * a0;
+    b.a0 += c0;
+    b.l1 = fmaf(row.go, a1, b.l1);
+    b.l2 = fmaf(row.go, a2, b.l2);
+    if constexpr (NO > 0) {
+#pragma unroll
+      for (int d = 0; d < NO; ++d) {
+        const float ct = c0 * row.t[d];
+        b.o1[d] += ct;
+        b.o2[d] = fmaf(ct, row.t[d], b.o2[d]);
+      }
+    }
+    if (++nrow == 8) {
+      flush();
+      nrow = 0;
+    }
+  }
+  flush();
+}
+
+template <int NO>
+__global__ __launch_bounds__(kThreads) void k_backward_runs(SweepArgs a) {
+  extern __shared__ float smem[];
+  if (!runs_chosen(a)) return;  // k_backward does the work
+  const long long k = block_k(a);
+  if (k >= a.d.K) return;
+  const int D = a.g.ndim;
+  const int L = D - 1;
+  double* red = reinterpret_cast<double*>(smem + a.L.red_off);
+  double* tot = red + 16;  // FP64 window totals of G0, G1, G2
+  float* vt = smem + a.L.hist_off;
+  const double vref = build_vtable(a, vt, k, red);
+  for (int c = 0; c < a.d.C; ++c) {
+    const long long kc = k * a.d.C + c;
+    const Win w = make_win(a, kc, reinterpret_cast<int*>(smem + a.L.red_off + 80));
+    const double pc = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
+    if (w.bad || w.empty) {
+      if (threadIdx.x == 0) {
+        const double val = w.bad ? __builtin_nan("") : 0.0;
+        for (int d = 0; d < D; ++d) {
+          a.g_mu[kc * D + d] = val;
+          a.g_sigma[kc * D + d] = val;
+        }
+        if (a.g_weight) a.g_weight[kc] = val;
+      }
+      continue;
+    }
+    int loL, WL;
+    last_axis(w, D, loL, WL);
+    __syncthreads();  // LDS reuse across components
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d + 1 < D) {
+        float* tab = smem + a.L.tab_off[d];
+        const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                  rsig);
+      }
+    }
+    build_prefix_bwd(a, smem, kc, loL, WL, red, tot);
+    BwdAcc<NO> acc;
+    acc.a0 = acc.l1 = acc.l2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < (NO > 0 ? NO : 1); ++i) acc.o1[i] = acc.o2[i] = 0.0;
+    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
+      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+      __syncthreads();
+      build_rows_bwd_runs(a, smem, w, r0, rc, kc, loL, loL + WL - 1);
+      __syncthreads();
+      bwd_runs<NO>(a, smem, rc, acc);
+    }
+    // per-axis normalisers and score means: the fastest axis from the FP64
+    // totals, the slower axes from their factor tables
+    const double T0 = tot[0], T1 = tot[1], T2 = tot[2];
+    double Z = T0, m1[4], m2[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      m1[d] = m2[d] = 0.0;
+      if (d + 1 < D) {
+        const double mu = a.d.mu[kc * D + d], rsg = 1.0 / a.d.sigma[kc * D + d];
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
+          const double g = (double)smem[a.L.tab_off[d] + i];
+          const double t = (cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i) - mu) * rsg;
+          z0 += g;
+          z1 += g * t;
+          z2 += g * t * t;
+        }
+        const double Zd = block_sum(z0, red);
+        m1[d] = block_sum(z1, red) / Zd;
+        m2[d] = block_sum(z2, red) / Zd;
+        Z *= Zd;
+      } else if (d == L) {
+        m1[d] = T1 / T0;
+        m2[d] = T2 / T0;
+      }
+    }
+    const double A0 = block_sum(acc.a0, red) / Z;
+    double t1[4], t2[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      t1[d] = d < NO ? block_sum(acc.o1[d < NO ? d : 0], red) / Z : 0.0;
+      t2[d] = d < NO ? block_sum(acc.o2[d < NO ? d : 0], red) / Z : 0.0;
+    }
+    t1[3] = 0.0;
+    t2[3] = 0.0;
+    const double l1 = block_sum(acc.l1, red) / Z;
+    const double l2 = block_sum(acc.l2, red) / Z;
+    write_grads(a, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
   }
 }
 
@@ -1203,10 +1544,15 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   if (kind == kSweepRuns) {
     L.g_off = 0;
     off = round_up(2 * (g.n[D - 1] + 1), 4);
+  } else if (kind == kSweepBwdRuns) {
+    // (G0, G1, G2, -) FP32 per column, 16 bytes
+    L.g_off = 0;
+    off = 4 * (g.n[D - 1] + 1);
   }
-  // factor tables: every axis for the cell sweeps; the run form keeps the
+  const bool runform = kind == kSweepRuns || kind == kSweepBwdRuns;
+  // factor tables: every axis for the cell sweeps; the run forms keep the
   // slower axes only
-  const int ntab = kind == kSweepRuns ? D - 1 : D;
+  const int ntab = runform ? D - 1 : D;
   for (int d = 0; d < ntab; ++d) {
     const int cap = (d + 1 < D) ? g.n[d] : g.n[d] + 64;
     L.cap[d] = round_up(cap, 4);
@@ -1215,7 +1561,8 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   }
   off = round_up(off, 4);
   L.row_off = off;
-  off += (kind == kSweepPropagate || kind == kSweepRuns ? 4 : 2) * kRowChunk;
+  off += (kind == kSweepBwdRuns ? 8 : (kind == kSweepPropagate || kind == kSweepRuns ? 4 : 2)) *
+         kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;
@@ -1253,6 +1600,8 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
     L.ncls = 3;
     L.cpw = 1;
     off += 3 * stride;
+  } else if (kind == kSweepBwdRuns) {
+    off += round_up(B + 1, 4);  // weight table
   } else if (kind == kSweepBackward) {
     off += round_up(B + 1, 4);
     // fastest-axis factor times t and times t^2 (t = (x - mu)/sigma)
@@ -1400,15 +1749,32 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
   a.g_mu = g_mu;
   a.g_sigma = g_sigma;
   a.g_weight = g_weight;
+  const int D = mm.grid.ndim;
   hipError_t e = hipSuccess;
-  switch (mm.grid.ndim) {
+  // the run form, when the model matrix uses it and its LDS fits in 64 KiB
+  SweepArgs ar = a;
+  a.allow_runs = a.allow_runs && sweep_layout(mm.grid, mm.B, kSweepBwdRuns, &ar.L) &&
+                 ar.L.bytes <= 64 * 1024;
+  ar.allow_runs = a.allow_runs;
+  if (a.allow_runs && mm.sweep != VUP_SWEEP_CELLS) {
+    const dim3 grid = sweep_grid(d), block(kThreads);
+    switch (D) {
+      case 1: hipLaunchKernelGGL(k_backward_runs<0>, grid, block, ar.L.bytes, s, ar); break;
+      case 2: hipLaunchKernelGGL(k_backward_runs<1>, grid, block, ar.L.bytes, s, ar); break;
+      case 3: hipLaunchKernelGGL(k_backward_runs<2>, grid, block, ar.L.bytes, s, ar); break;
+      default: hipLaunchKernelGGL(k_backward_runs<3>, grid, block, ar.L.bytes, s, ar); break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess || mm.sweep == VUP_SWEEP_RUNS) return e;
+  }
+  switch (D) {
     case 1: e = allow_lds(k_backward<0>, a.L.bytes); break;
     case 2: e = allow_lds(k_backward<1>, a.L.bytes); break;
     case 3: e = allow_lds(k_backward<2>, a.L.bytes); break;
     default: e = allow_lds(k_backward<3>, a.L.bytes); break;
   }
   if (e != hipSuccess) return e;
-  switch (mm.grid.ndim) {
+  switch (D) {
     case 1: hipLaunchKernelGGL(k_backward<0>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
     case 2: hipLaunchKernelGGL(k_backward<1>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;
     case 3: hipLaunchKernelGGL(k_backward<2>, sweep_grid(d), dim3(kThreads), a.L.bytes, s, a); break;

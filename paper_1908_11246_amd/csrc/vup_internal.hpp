@@ -27,7 +27,13 @@ struct SweepLayout {
   size_t bytes;
 };
 
-enum SweepKind { kSweepPropagate = 0, kSweepMoments = 1, kSweepBackward = 2, kSweepRuns = 3 };
+enum SweepKind {
+  kSweepPropagate = 0,
+  kSweepMoments = 1,
+  kSweepBackward = 2,
+  kSweepRuns = 3,
+  kSweepBwdRuns = 4
+};
 
 bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out);
 GridDev make_grid_dev(const vup_mm& mm);

@@ -330,11 +330,13 @@ def test_grid48_4d_sampled(vup, orc, precision):
 # ---------------------------------------------------------------------------
 # backward: adjoint kernel vs FP64 analytic gradient (and the oracle's FD)
 # ---------------------------------------------------------------------------
-def _grad_case(vup, orc, wl, ks, seed):
+def _grad_case(vup, orc, wl, ks, seed, form=None):
     rng = np.random.default_rng(seed)
     g_var = rng.uniform(0.5, 1.5, size=wl.K)
     g_ent = rng.uniform(0.5, 1.5, size=wl.K)
     gp = _gpu_pipeline(vup, wl, moments=False)
+    if form is not None:
+        gp["mm"].set_sweep_mode(form)
     gm, gs, gw = vup.ipsa_backward(gp["mm"], wl.mu, wl.sigma, wl.weight, gp["P"],
                                    gp["mean_hist"], torch.from_numpy(g_var).to(DEV),
                                    torch.from_numpy(g_ent).to(DEV))
@@ -382,6 +384,20 @@ def test_backward_ragged(vup, orc):
         wl = workloads.random_workload(name, n, lo, hi, model, B, 40, C, sr, seed=7, theta=theta)
         _say(f"[backward ragged {name}]")
         _grad_case(vup, orc, wl, np.arange(wl.K), 43)
+
+
+@pytest.mark.parametrize("form", ["cells", "runs"])
+def test_backward_both_forms(vup, orc, form):
+    # the per-cell adjoint sweep and the run-form one, each against the FP64
+    # analytic gradient, on 2-D and 3-D grids with long and short runs
+    cases = [workloads.grid64(),
+             workloads.random_workload("bwd2d", (57, 300), (-3, -3), (3, 3), "sincos2", 40, 60, 2,
+                                       (0.05, 0.9), seed=35),
+             workloads.random_workload("bwd3d", (20, 17, 90), (-2, -2, -2), (2, 2, 2), "damped3",
+                                       30, 40, 1, (0.1, 0.8), seed=36)]
+    for wl in cases:
+        _say(f"[backward {form} form: {wl.name}]")
+        _grad_case(vup, orc, wl, np.arange(wl.K), 44, form=form)
 
 
 def test_autograd_function_matches_adjoint(vup):
