@@ -406,22 +406,20 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
     const int cc = a.L.ncls > 1 ? mag_class(gmax) : 0;
     const float scol = ps->scol[cc];
     char* lh = hbase + cc * cpc * strideb;
-    const int mcol = colbase + s * SW;
-    int r = ph;
-    if (r >= rc) continue;
-    float4 cur = rt[r];
-    MapVec<SW> mv = load_map<SW>(a.binmap + (long long)__float_as_int(cur.z) + mcol);
-    for (; r < rc; r += P0) {
-      const int rn = r + P0;
-      float4 nxt = cur;
-      MapVec<SW> mn = mv;
-      if (rn < rc) {
-        nxt = rt[rn];
-        mn = load_map<SW>(a.binmap + (long long)__float_as_int(nxt.z) + mcol);
-      }
-      const int rcl = a.L.ncls > 1 ? __float_as_int(cur.w) : 0;
+    const uint16_t* mbase = a.binmap + colbase + s * SW;
+    // one row of the strip: the row entry and the strip's bin codes
+    struct Row {
+      float4 e;
+      MapVec<SW> mv;
+    };
+    auto load = [&](int r, Row& x) {
+      x.e = rt[r];
+      x.mv = load_map<SW>(mbase + (unsigned)__float_as_int(x.e.z));
+    };
+    auto accumulate = [&](const Row& x) {
+      const int rcl = a.L.ncls > 1 ? __float_as_int(x.e.w) : 0;
       char* lr = lh + rcl * rcstep;
-      const float gos = cur.y * scol;
+      const float gos = x.e.y * scol;
       float qs = 0.0f;
       if constexpr (PREC != VUP_FP32) {
         qs = ps->srow[rcl] * scol * (PREC == VUP_FP8E4M3 ? (1.0f / 448.0f) : 1.0f);
@@ -433,13 +431,27 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
         if constexpr (PREC == VUP_FP32) {
           v = fmaf(gos, gl[j], u);
         } else {
-          v = fmaf(quantize<PREC>(cur.x * gl[j]), qs, u);
+          v = fmaf(quantize<PREC>(x.e.x * gl[j]), qs, u);
         }
-        uint32_t* slot = reinterpret_cast<uint32_t*>(lr + map_at<SW>(mv, j));
+        uint32_t* slot = reinterpret_cast<uint32_t*>(lr + map_at<SW>(x.mv, j));
         __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      cur = nxt;
-      mv = mn;
+    };
+    // rows two at a time in ping-pong buffers: one row's bin codes are in
+    // flight while the other row is accumulated
+    int r = ph;
+    if (r >= rc) continue;
+    Row ra, rb;
+    load(r, ra);
+    for (;;) {
+      const int r2 = r + P0;
+      if (r2 < rc) load(r2, rb);
+      accumulate(ra);
+      if (r2 >= rc) break;
+      r = r2 + P0;
+      if (r < rc) load(r, ra);
+      accumulate(rb);
+      if (r >= rc) break;
     }
   }
 }
