@@ -1371,8 +1371,6 @@ __device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc
   const int wv = threadIdx.x >> 6;
   const BwdRunRow* rt = reinterpret_cast<const BwdRunRow*>(smem + a.L.row_off);
   const char* vt = reinterpret_cast<const char*>(smem + a.L.hist_off);
-  const int bl = (rc + 3) >> 2;
-  const int rend = min((gi + 1) * bl, rc);
   struct {
     float a0, l1, l2, o1[NO > 0 ? NO : 1], o2[NO > 0 ? NO : 1];
   } b = {};
@@ -1388,7 +1386,9 @@ __device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc
     }
     b = {};
   };
-  for (int r = gi * bl + wv; r < rend; r += kWaves) {
+  // the four groups of a wave take adjacent rows (similar run counts; there
+  // are no atomics to spread over banks here)
+  for (int r = 4 * wv + gi; r < rc; r += 4 * kWaves) {
     const BwdRunRow row = rt[r];
     const int cnt = row.cnt;
     const uint32_t* rp = a.runs + row.ra;
