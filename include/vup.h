@@ -194,7 +194,10 @@ int vup_windows(const vup_grid* g, const vup_dists* d, int32_t* win, void* strea
  *      N_y x L output matrix stored column-major);
  *   Z: dev FP64 [K][ncomp] or NULL: sum of the (precision-rounded) weights of
  *      each component over its window, including cells with no bin.
- * precision: VUP_FP32 / VUP_BF16 / VUP_BF16X2 / VUP_FP8E4M3.
+ * precision: VUP_FP32 / VUP_BF16 / VUP_BF16X2 / VUP_FP8E4M3. FP32 densities
+ * are accumulated per run of equal bin along the fastest axis (prefix sums of
+ * the fastest-axis factors) or per cell, as vup_set_sweep_mode selects; the
+ * reduced precisions round every cell's density and always go per cell.
  * Invalid parameters -> NaN row (counter bad_param); every window empty ->
  * zero row (counter empty). Column sums are 1 up to FP32 rounding unless some
  * cells of the window have bin -1.
@@ -279,6 +282,8 @@ int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, dou
  *   P: dev FP32 [K][B] from vup_propagate (VUP_FP32); mean_hist: dev FP64 [K]
  *   from vup_ipsa; g_var, g_ent: dev FP64 [K] or NULL (= 0);
  *   g_mu, g_sigma: dev FP64 [K][ncomp][ndim]; g_weight: dev FP64 [K][ncomp] or NULL.
+ * The sweep goes per run of equal bin (prefix sums of g, g t, g t^2 along the
+ * fastest axis) or per cell, with the form vup_set_sweep_mode selects.
  * Invalid parameters give NaN gradients.
  * ------------------------------------------------------------------------ */
 int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
