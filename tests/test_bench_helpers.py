@@ -1,0 +1,61 @@
+"""Host-side checks of bench.py's contract helpers (no GPU): the multi-GPU
+refusal, the calibrated byte counts of the traffic summary, and that a traffic
+figure is reported only for the kernel sources it was measured on."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for d, name, value in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
+    # the copy (last dispatch) moves CALIB_BYTES; FETCH_SIZE reports half of it
+    calib_kib = bench.CALIB_BYTES / 1024
+    fetch = tmp_path / "fetch.csv"
+    write = tmp_path / "write.csv"
+    # counters are summed over the instances of one dispatch
+    _counter_csv(fetch, "FETCH_SIZE", [(1, "vup::k_propagate_runs(vup::SweepArgs)", 1000.0),
+                                       (1, "vup::k_propagate_runs(vup::SweepArgs)", 1000.0),
+                                       (2, "vup::k_moments(vup::SweepArgs)", 500.0),
+                                       (3, "__amd_rocclr_copyBuffer", calib_kib / 2)])
+    _counter_csv(write, "WRITE_SIZE", [(1, "vup::k_propagate_runs(vup::SweepArgs)", 300.0),
+                                       (2, "vup::k_moments(vup::SweepArgs)", 7.0),
+                                       (3, "__amd_rocclr_copyBuffer", calib_kib)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "paper_1908_11246_amd" / "csrc")
+    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"):
+        (tmp_path / "paper_1908_11246_amd" / "csrc" / name).write_text("// " + name)
+    bench.summarize_traffic(str(fetch), str(write))
+    rec = json.loads((tmp_path / "profiles" / "traffic_grid1024.json").read_text())
+    assert rec["fetch_size_calibration"]["scale"] == pytest.approx(2.0)
+    assert rec["write_size_calibration"]["scale"] == pytest.approx(1.0)
+    p = rec["kernels"]["propagate"]
+    assert p["fetch_bytes"] == pytest.approx(2000.0 * 1024 * 2.0)
+    assert p["write_bytes"] == pytest.approx(300.0 * 1024)
+    assert bench.traffic_bytes("moments") == pytest.approx(500.0 * 1024 * 2.0 + 7.0 * 1024)
+    # a change of the kernel sources voids the figure
+    (tmp_path / "paper_1908_11246_amd" / "csrc" / "k_sweep.hip").write_text("// changed")
+    assert bench.traffic_bytes("moments") is None
