@@ -4,20 +4,23 @@
 // One workgroup (256 threads, 4 waves) handles one distribution k and loops
 // over its mixture components. For each component:
 //   1. the truncation window is computed per axis (FP64, exact op order) and
-//      the per-axis Gaussian factors g_d(j) are tabulated in LDS (FP32). The
-//      fastest-axis table is zero-padded to whole strips;
-//   2. the window is swept as rows (all axes but the fastest) x strips of SW
-//      consecutive cells of the fastest axis, aligned to SW in the padded bin
-//      map. A thread keeps its strip's factors in registers and walks rows; the
-//      row factor (product of the slower axes' factors) and the row's bin-map
-//      offset come from a row table in LDS;
-//   3. per cell the density is one FP32 multiply (row factor x fastest-axis
-//      factor); it is accumulated into the bin's LDS slot as a 32-bit
-//      fixed-point integer (LDS float atomics are two orders of magnitude
-//      slower than integer ones on gfx950). Cells are split into magnitude
-//      classes with one histogram and one scale each, so tail cells keep a
-//      fine quantum (see the fixed-point notes below). Integer sums are exact,
-//      so results do not depend on scheduling.
+//      the per-axis Gaussian factors g_d(j) are tabulated in LDS (FP32);
+//   2. cell form: the window is swept as rows (all axes but the fastest) x
+//      strips of SW consecutive cells of the fastest axis, aligned to SW in
+//      the padded bin map. A thread keeps its strip's factors in registers and
+//      walks rows; the row factor (product of the slower axes' factors) and
+//      the row's bin-map offset come from a row table in LDS. Per cell the
+//      density is one FP32 multiply;
+//      run form (FP32 propagation and the adjoint): each row of the window is
+//      a sequence of runs of equal bin, and the density is separable, so a
+//      run's sums are differences of prefix sums of the fastest-axis factors;
+//   3. propagation accumulates into the bins' LDS slots as 32-bit fixed-point
+//      integers (LDS float atomics are two orders of magnitude slower than
+//      integer ones on gfx950), split into magnitude classes with one
+//      histogram and one scale each so that tail cells keep a fine quantum
+//      (see the fixed-point notes below). Integer sums are exact, so results
+//      do not depend on scheduling. Moments and the adjoint keep per-thread
+//      sums reduced in a fixed order.
 // The input probability matrix is never materialised.
 #include <hip/hip_runtime.h>
 
