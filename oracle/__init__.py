@@ -16,6 +16,10 @@ Function -> paper passage it follows:
   moments          exact-f mean/variance of the propagated output; eq. IPSAvar
   ipsa             coarse-grained per-column variance and entropy (Sec. 5.2)
   ipsa_grad        derivative of those quantities w.r.t. the pdf parameters
+
+The IPSA probability matrix (Sec. 5.2, eq. IPSA and the per-column
+translation), its field lines and the marginal over locations are plain numpy
+in ``fields.py``.
 """
 from __future__ import annotations
 
