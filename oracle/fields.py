@@ -14,7 +14,9 @@ Readings (the paper leaves these open):
     d_j = d_lo + j*h (j = 0..J) reads each bin's mass as spread evenly over the
     bin: the part of bin b that lands in [d_j, d_{j+1}) is
     P_b * |[e_b - y_k, e_{b+1} - y_k) n [d_j, d_{j+1})| / (e_{b+1} - e_b).
-    Mass that lands outside [d_0, d_J) is reported as ``lost``.
+    Mass that lands outside [d_0, d_J) is reported as ``lost``. A column
+    holding a non-finite value gives NaN throughout; a non-finite y(l) moves
+    the whole column out of range (Q = 0, lost = its mass).
   * Quantiles use the same reading: the CDF is piecewise linear through
     (e_b, C_b), C_b = sum_{b' < b} P_b', and the alpha quantile is the smallest
     y with CDF(y) >= alpha * T, T = C_B (levels are fractions of the column's
@@ -51,6 +53,13 @@ def ipsa_matrix(P, edges, y_ref, dy_lo: float, dy_width: float, n_dy: int):
     lost = np.zeros(K)
     for k in range(K):
         y = y_ref[k]
+        if not all(math.isfinite(v) for v in P[k]):
+            Q[k, :] = np.nan
+            lost[k] = np.nan
+            continue
+        if not math.isfinite(y):
+            lost[k] = P[k].sum()
+            continue
         for b in range(B):
             p = P[k, b]
             if p == 0.0:

@@ -118,6 +118,16 @@ def test_matrix_tracks_the_per_cell_distribution_of_delta_y():
         assert np.all(np.abs(cumQ - (G - G[0])) <= slack)
 
 
+def test_matrix_degenerate_columns():
+    e = np.arange(5.0)
+    P = np.array([[0.1, 0.2, 0.3, 0.4], [0.1, np.nan, 0.3, 0.4], [0.1, 0.2, 0.3, 0.4]])
+    y = np.array([np.inf, 0.0, np.nan])
+    Q, lost = fields.ipsa_matrix(P, e, y, -2.0, 0.5, 8)
+    assert np.all(Q[0] == 0.0) and abs(lost[0] - 1.0) < 1e-15
+    assert np.all(np.isnan(Q[1])) and math.isnan(lost[1])
+    assert np.all(Q[2] == 0.0) and abs(lost[2] - 1.0) < 1e-15
+
+
 def test_matrix_wrong_direction_would_fail():
     """A shift by +y instead of -y moves mass the other way: pins the sign."""
     h = 1.0
