@@ -72,6 +72,9 @@ extern "C" {
 #define VUP_MAX_BINS 4096     /* B; the per-workgroup histograms live in LDS     */
 #define VUP_MAX_COMP 2        /* mixture components per distribution            */
 #define VUP_MAX_AXIS 65536    /* n[d]                                            */
+#define VUP_MAX_DY (1 << 24)  /* n_dy of vup_ipsa_matrix                         */
+#define VUP_MAX_LEVELS 16     /* quantile levels of vup_ipsa_fields              */
+#define VUP_MAX_MARGINAL_COLS (1 << 24)  /* row length n of vup_marginalize      */
 
 typedef struct vup_grid {
   int32_t ndim;      /* 1..4                                                   */
@@ -289,6 +292,78 @@ int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, dou
 int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,
                       const double* mean_hist, const double* g_var, const double* g_ent,
                       double* g_mu, double* g_sigma, double* g_weight, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_eval_points - the model at arbitrary points: y[i] = M(x_i), FP64, with
+ * x_i = x[i*ldx .. i*ldx + ndim). Gives the reference outputs y(l) of Sec. 5.3
+ * (the model at the maximum of each input pdf, e.g. x = mu with ldx =
+ * ncomp*ndim for component 0).
+ *   m: host; x: dev FP64 [n][ldx], ldx >= ndim; y: dev FP64 [n].
+ * EINVAL: unknown model, model/ndim mismatch, n < 0, ldx < ndim, NULL arrays.
+ * ------------------------------------------------------------------------ */
+int vup_eval_points(const vup_model* m, int32_t ndim, int64_t n, const double* x, int64_t ldx,
+                    double* y, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_ipsa_matrix - the IPSA probability matrix (Sec. 5.2, eq. IPSA and the
+ * per-column translation y -> Delta y = y - y(l)). Column k of P is read as a
+ * histogram whose mass is spread evenly over each bin [e_b, e_{b+1}); it is
+ * moved by y_ref[k] and integrated over the uniform grid
+ * d_j = dy_lo + j*dy_width, j = 0..n_dy:
+ *   Q[k][j] = sum_b P[k][b] |[e_b - y_k, e_{b+1} - y_k) n [d_j, d_{j+1})| / (e_{b+1} - e_b)
+ *   lost[k] = mass that falls outside [d_0, d_{n_dy}).
+ * Computed as differences of the column's piecewise-linear FP64 CDF at
+ * d_j + y_k; Q is rounded to FP32 once.
+ *   P: dev FP32 [K][B] (vup_propagate's layout); y_ref: dev FP64 [K];
+ *   Q: dev FP32 [K][n_dy]; lost: dev FP64 [K] or NULL. Edges and B come
+ *   from the model matrix.
+ * A column holding a non-finite value gives NaN in Q and lost; a non-finite
+ * y_ref[k] gives Q = 0 and lost = the column's mass.
+ * EINVAL: K < 0, n_dy not in [1, VUP_MAX_DY], dy_lo or dy_width not finite,
+ * dy_width <= 0, NULL arrays.
+ * ------------------------------------------------------------------------ */
+int vup_ipsa_matrix(const vup_mm* mm, int64_t K, const float* P, const double* y_ref, double dy_lo,
+                    double dy_width, int32_t n_dy, float* Q, double* lost, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_ipsa_fields - coarse-grained field lines of each column of P (Sec. 5.2:
+ * the most probable output, confidence intervals, the expected deviation from
+ * y(l) and the binned form of eq. IPSAvar). With c_b = (e_b + e_{b+1})/2,
+ * C_b = sum_{b'<b} P[k][b'] (FP64) and T = C_B:
+ *   p_max[k]  = max_b P[k][b];   y_mode[k] = c_b of the first bin attaining it
+ *   quant[k][q] = smallest y with F(y) >= levels[q] * T, F the piecewise-linear
+ *               CDF through (e_b, C_b) (levels in (0, 1], fractions of T)
+ *   dev[k]    = sum_b P[k][b] (c_b - y_ref[k])
+ *   delta2[k] = 1/2 sum_b P[k][b] (c_b - y_ref[k])^2
+ *   P: dev FP32 [K][B]; y_ref: dev FP64 [K] (needed for dev and delta2);
+ *   levels: host FP64 [n_levels], n_levels <= VUP_MAX_LEVELS;
+ *   y_mode, p_max, dev, delta2: dev FP64 [K] or NULL; quant: dev FP64
+ *   [K][n_levels] or NULL.
+ * A column holding a non-finite value gives NaN everywhere; a column of zeros
+ * gives p_max = dev = delta2 = 0 and NaN for y_mode and the quantiles.
+ * EINVAL: K < 0, bad n_levels or a level outside (0, 1], dev/delta2 without
+ * y_ref, NULL P.
+ * ------------------------------------------------------------------------ */
+int vup_ipsa_fields(const vup_mm* mm, int64_t K, const float* P, const double* y_ref,
+                    int32_t n_levels, const double* levels, double* y_mode, double* p_max,
+                    double* quant, double* dev, double* delta2, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_marginalize - global values over locations (Sec. 5.2: marginalising
+ * the per-location matrices with the measurement-location probability rho):
+ *   out[j] = sum_k rho[k] A[k][j]       (rho NULL: rho_k = 1/K),
+ * FP64, in a fixed order (repeatable bit for bit). A is any [K][n] FP32
+ * matrix: P from vup_propagate (n = B) or Q from vup_ipsa_matrix (n = n_dy).
+ *   A: dev FP32 [K][n]; rho: dev FP64 [K] or NULL; out: dev FP64 [n];
+ *   ws: dev scratch of vup_marginal_workspace_bytes(K, n) bytes (may be
+ *   NULL when that is 0), owned by the caller and reusable after the call's
+ *   work on `stream` has finished.
+ * EINVAL: K < 0, n not in [1, VUP_MAX_MARGINAL_COLS], NULL A or out;
+ * EWORKSPACE: workspace too small.
+ * ------------------------------------------------------------------------ */
+size_t vup_marginal_workspace_bytes(int64_t K, int32_t n);
+int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, void* ws,
+                    size_t ws_bytes, double* out, void* stream);
 
 /* --------------------------------------------------------------------------
  * vup_counters - reads and clears the device-side event counters of a model

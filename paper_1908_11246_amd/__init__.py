@@ -11,6 +11,10 @@ fallback.
     mean, var, _ = moments(mm, mu, sigma)          # exact-f output moments
     mean_h, var_h, ent = ipsa(mm, P)               # IPSA coarse-grained quantities
     var_h, ent = IPSA.apply(mu, sigma, None, mm)   # differentiable wrt mu, sigma
+    y_l = eval_points("ipsa2", mu[:, 0, :])        # y(l): the model at each pdf's maximum
+    Q, lost = ipsa_matrix(mm, P, y_l, -3.0, 0.01, 600)   # IPSA probability matrix
+    fl = ipsa_fields(mm, P, y_l, (0.025, 0.975))   # mode, intervals, deviation per l
+    g = marginalize(Q)                             # global marginal over locations
 """
 from __future__ import annotations
 
@@ -105,6 +109,16 @@ def _load():
     lib.vup_separable_workspace_bytes.argtypes = [_P(VupMM), ctypes.c_int32, ctypes.c_int32]
     lib.vup_propagate_separable.argtypes = [_P(VupMM), _P(VupSepDists), _vp, ctypes.c_size_t, _vp,
                                             _vp, _vp]
+    lib.vup_eval_points.argtypes = [_P(VupModel), ctypes.c_int32, ctypes.c_int64, _vp,
+                                    ctypes.c_int64, _vp, _vp]
+    lib.vup_ipsa_matrix.argtypes = [_P(VupMM), ctypes.c_int64, _vp, _vp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]
+    lib.vup_ipsa_fields.argtypes = [_P(VupMM), ctypes.c_int64, _vp, _vp, ctypes.c_int32,
+                                    _P(ctypes.c_double), _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.vup_marginal_workspace_bytes.restype = ctypes.c_size_t
+    lib.vup_marginal_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.vup_marginalize.argtypes = [ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t,
+                                    _vp, _vp]
     _lib = lib
     return lib
 
@@ -369,6 +383,78 @@ def ipsa(mm: ModelMatrix, P: torch.Tensor):
     _check(_load().vup_ipsa(ctypes.byref(mm.mm), K, _ptr(P), _ptr(m), _ptr(v), _ptr(h),
                             _vp(_stream())))
     return m, v, h
+
+
+def eval_points(model: str, x, theta: Sequence[float] = (), ndim: Optional[int] = None,
+                device="cuda") -> torch.Tensor:
+    """y_i = M(x_i) at the rows of x ([n][ldx]; the first ``ndim`` entries of
+    each row are the point, default all of them). ``x`` may be a strided view
+    such as mu[:, 0, :] of a [K][C][d] parameter tensor."""
+    x = torch.as_tensor(x)
+    if x.device.type != "cuda" or x.dtype != torch.float64:
+        x = x.to(device=device, dtype=torch.float64)
+    if x.dim() != 2 or x.stride(1) != 1:
+        x = x.contiguous()
+    n = x.shape[0]
+    nd = x.shape[1] if ndim is None else int(ndim)
+    ldx = x.stride(0) if n > 1 else x.shape[1]
+    y = torch.empty(n, dtype=torch.float64, device=x.device)
+    m = make_model(model, theta)
+    _check(_load().vup_eval_points(ctypes.byref(m), nd, n, _ptr(x) if n else None, max(ldx, nd),
+                                   _ptr(y), _vp(_stream())))
+    return y
+
+
+def ipsa_matrix(mm: ModelMatrix, P: torch.Tensor, y_ref: torch.Tensor, dy_lo: float,
+                dy_width: float, n_dy: int):
+    """IPSA probability matrix Q[K][n_dy] (FP32) and lost mass[K] (FP64):
+    each column of P translated by y_ref and re-binned on d_j = dy_lo + j*dy_width."""
+    K = P.shape[0]
+    y = _dev_f64(y_ref, P.device)
+    Q = torch.empty((K, int(n_dy)), dtype=torch.float32, device=P.device)
+    lost = torch.empty(K, dtype=torch.float64, device=P.device)
+    _check(_load().vup_ipsa_matrix(ctypes.byref(mm.mm), K, _ptr(P), _ptr(y), float(dy_lo),
+                                   float(dy_width), int(n_dy), _ptr(Q), _ptr(lost),
+                                   _vp(_stream())))
+    return Q, lost
+
+
+def ipsa_fields(mm: ModelMatrix, P: torch.Tensor, y_ref: Optional[torch.Tensor] = None,
+                levels: Sequence[float] = ()):
+    """Field lines of each column: y_mode, p_max, quant[K][len(levels)] and,
+    with y_ref, dev and delta2 (all FP64)."""
+    K = P.shape[0]
+    dev_ = P.device
+    f64 = dict(dtype=torch.float64, device=dev_)
+    y = None if y_ref is None else _dev_f64(y_ref, dev_)
+    out = dict(y_mode=torch.empty(K, **f64), p_max=torch.empty(K, **f64),
+               quant=torch.empty((K, len(levels)), **f64) if len(levels) else None,
+               dev=torch.empty(K, **f64) if y is not None else None,
+               delta2=torch.empty(K, **f64) if y is not None else None)
+    lv = (ctypes.c_double * max(len(levels), 1))(*[float(a) for a in levels])
+    _check(_load().vup_ipsa_fields(ctypes.byref(mm.mm), K, _ptr(P), _ptr(y), len(levels), lv,
+                                   _ptr(out["y_mode"]), _ptr(out["p_max"]), _ptr(out["quant"]),
+                                   _ptr(out["dev"]), _ptr(out["delta2"]), _vp(_stream())))
+    return out
+
+
+def marginal_workspace_bytes(K: int, n: int) -> int:
+    return int(_load().vup_marginal_workspace_bytes(int(K), int(n)))
+
+
+def marginalize(A: torch.Tensor, rho: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[j] = sum_k rho_k A[k][j] (FP64; rho None: 1/K). ``ws`` may be a
+    reusable uint8 device tensor of at least marginal_workspace_bytes(K, n)."""
+    K, n = A.shape
+    r = None if rho is None else _dev_f64(rho, A.device)
+    need = marginal_workspace_bytes(K, n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    out = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(_load().vup_marginalize(K, n, _ptr(A), _ptr(r), _ptr(ws), ws.numel(), _ptr(out),
+                                   _vp(_stream())))
+    return out
 
 
 def ipsa_backward(mm: ModelMatrix, mu, sigma, weight, P, mean_hist, g_var=None, g_ent=None,

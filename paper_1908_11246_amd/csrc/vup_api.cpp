@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "../../include/vup.h"
+#include "vup_fields.hpp"
 #include "vup_internal.hpp"
 
 namespace {
@@ -92,6 +93,19 @@ int check_sweep(const vup_mm* mm, vup::SweepKind kind) {
   return VUP_OK;
 }
 
+int check_model(const vup_model* m, int ndim) {
+  if (!m) return fail(VUP_EINVAL, "model is NULL");
+  const int need[] = {0, 2, 3, 4, 2, 2};
+  if (m->kind < 0 || m->kind > VUP_MODEL_IPSA2) return fail(VUP_EINVAL, "unknown model %d", m->kind);
+  if (m->kind == VUP_MODEL_LINEAR) {
+    for (int d = 0; d <= ndim; ++d)
+      if (!std::isfinite(m->theta[d])) return fail(VUP_EINVAL, "theta must be finite");
+  } else if (need[m->kind] != ndim) {
+    return fail(VUP_EINVAL, "model %d needs ndim %d", m->kind, need[m->kind]);
+  }
+  return VUP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -104,14 +118,7 @@ int vup_eval_grid(const vup_grid* g, const vup_model* m, double* f, void* stream
   int r = check_grid(g);
   if (r) return r;
   if (!m || !f) return fail(VUP_EINVAL, "model or f is NULL");
-  const int need[] = {0, 2, 3, 4, 2, 2};
-  if (m->kind < 0 || m->kind > VUP_MODEL_IPSA2) return fail(VUP_EINVAL, "unknown model %d", m->kind);
-  if (m->kind == VUP_MODEL_LINEAR) {
-    for (int d = 0; d <= g->ndim; ++d)
-      if (!std::isfinite(m->theta[d])) return fail(VUP_EINVAL, "theta must be finite");
-  } else if (need[m->kind] != g->ndim) {
-    return fail(VUP_EINVAL, "model %d needs ndim %d", m->kind, need[m->kind]);
-  }
+  if ((r = check_model(m, g->ndim))) return r;
   if ((r = check_device())) return r;
   return launched(vup::launch_eval_grid(*g, *m, f, (hipStream_t)stream), "vup_eval_grid");
 }
@@ -299,6 +306,81 @@ int vup_set_sweep_mode(vup_mm* mm, int32_t mode, void* stream) {
   }
   mm->sweep = mode;
   return launched(vup::launch_set_mode(*mm, mode, s), "vup_set_sweep_mode");
+}
+
+int vup_eval_points(const vup_model* m, int32_t ndim, int64_t n, const double* x, int64_t ldx,
+                    double* y, void* stream) {
+  if (ndim < 1 || ndim > VUP_MAX_DIM) return fail(VUP_EINVAL, "ndim %d not in [1,4]", ndim);
+  int r = check_model(m, ndim);
+  if (r) return r;
+  if (n < 0) return fail(VUP_EINVAL, "n < 0");
+  if (ldx < ndim) return fail(VUP_EINVAL, "ldx %lld < ndim %d", (long long)ldx, ndim);
+  if (n > 0 && (!x || !y)) return fail(VUP_EINVAL, "x or y is NULL");
+  if (n > 0 && ldx > (int64_t)1 << 40) return fail(VUP_EUNSUPPORTED, "ldx too large");
+  if ((r = check_device())) return r;
+  return launched(vup::launch_eval_points(*m, ndim, n, x, ldx, y, (hipStream_t)stream),
+                  "vup_eval_points");
+}
+
+int vup_ipsa_matrix(const vup_mm* mm, int64_t K, const float* P, const double* y_ref, double dy_lo,
+                    double dy_width, int32_t n_dy, float* Q, double* lost, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (n_dy < 1 || n_dy > VUP_MAX_DY) return fail(VUP_EINVAL, "n_dy %d not in [1,%d]", n_dy, VUP_MAX_DY);
+  if (!std::isfinite(dy_lo) || !std::isfinite(dy_width) || !(dy_width > 0.0) ||
+      !std::isfinite(dy_lo + (double)n_dy * dy_width))
+    return fail(VUP_EINVAL, "Delta-y grid needs finite dy_lo and dy_width > 0");
+  if (K > 0 && (!P || !y_ref || !Q)) return fail(VUP_EINVAL, "P, y_ref or Q is NULL");
+  if ((r = check_device())) return r;
+  const double* edges =
+      reinterpret_cast<const double*>(static_cast<const char*>(mm->ws) + mm->off_edges);
+  return launched(vup::launch_ipsa_matrix(edges, mm->B, K, P, y_ref, dy_lo, dy_width, n_dy, Q, lost,
+                                          (hipStream_t)stream),
+                  "vup_ipsa_matrix");
+}
+
+int vup_ipsa_fields(const vup_mm* mm, int64_t K, const float* P, const double* y_ref,
+                    int32_t n_levels, const double* levels, double* y_mode, double* p_max,
+                    double* quant, double* dev, double* delta2, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if (K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (n_levels < 0 || n_levels > VUP_MAX_LEVELS)
+    return fail(VUP_EINVAL, "n_levels %d not in [0,%d]", n_levels, VUP_MAX_LEVELS);
+  if (quant && n_levels == 0) return fail(VUP_EINVAL, "quant given but n_levels == 0");
+  if (n_levels > 0 && !levels) return fail(VUP_EINVAL, "levels is NULL");
+  for (int q = 0; q < n_levels; ++q)
+    if (!(levels[q] > 0.0 && levels[q] <= 1.0))
+      return fail(VUP_EINVAL, "level %d = %g not in (0, 1]", q, levels[q]);
+  if ((dev || delta2) && !y_ref) return fail(VUP_EINVAL, "dev and delta2 need y_ref");
+  if (K > 0 && !P) return fail(VUP_EINVAL, "P is NULL");
+  if ((r = check_device())) return r;
+  const double* edges =
+      reinterpret_cast<const double*>(static_cast<const char*>(mm->ws) + mm->off_edges);
+  return launched(vup::launch_ipsa_fields(edges, mm->B, K, P, y_ref, n_levels, levels, y_mode, p_max,
+                                          quant, dev, delta2, (hipStream_t)stream),
+                  "vup_ipsa_fields");
+}
+
+size_t vup_marginal_workspace_bytes(int64_t K, int32_t n) {
+  if (K < 0 || n < 1 || n > VUP_MAX_MARGINAL_COLS) return 0;
+  return vup::marginal_workspace_bytes(K, n);
+}
+
+int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, void* ws,
+                    size_t ws_bytes, double* out, void* stream) {
+  if (K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (n < 1 || n > VUP_MAX_MARGINAL_COLS)
+    return fail(VUP_EINVAL, "n %d not in [1,%d]", n, VUP_MAX_MARGINAL_COLS);
+  if (!out || (K > 0 && !A)) return fail(VUP_EINVAL, "A or out is NULL");
+  const size_t need = vup::marginal_workspace_bytes(K, n);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(VUP_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int r = check_device();
+  if (r) return r;
+  return launched(vup::launch_marginalize(K, n, A, rho, ws, out, (hipStream_t)stream),
+                  "vup_marginalize");
 }
 
 int vup_counters(const vup_mm* mm, void* stream, int64_t* out) {

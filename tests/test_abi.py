@@ -172,3 +172,56 @@ def test_no_device_is_reported(lib):
     assert lib.vup_eval_grid(ctypes.byref(g), ctypes.byref(m), ctypes.c_void_p(0x1000),
                              None) == ENODEV
     assert b"device" in lib.vup_last_error()
+
+
+def test_field_line_arguments(lib):
+    """Argument checks of the IPSA matrix / field lines / marginal / point
+    evaluation entry points (all fail before any launch)."""
+    mm = _fake_mm(lib)
+    dummy = ctypes.c_void_p(0x1000)
+    m = vup.make_model("ipsa2")
+    # eval_points: ndim mismatch, ldx < ndim, negative n, NULL arrays
+    assert lib.vup_eval_points(ctypes.byref(m), 3, 4, dummy, 3, dummy, None) == EINVAL
+    assert lib.vup_eval_points(ctypes.byref(m), 2, 4, dummy, 1, dummy, None) == EINVAL
+    assert lib.vup_eval_points(ctypes.byref(m), 2, -1, dummy, 2, dummy, None) == EINVAL
+    assert lib.vup_eval_points(ctypes.byref(m), 2, 4, None, 2, dummy, None) == EINVAL
+    assert lib.vup_eval_points(None, 2, 4, dummy, 2, dummy, None) == EINVAL
+    # ipsa_matrix: bad target grid, NULL arrays, K < 0, bad descriptor
+    mat = lib.vup_ipsa_matrix
+    assert mat(ctypes.byref(mm), 4, dummy, dummy, 0.0, 0.1, 0, dummy, None, None) == EINVAL
+    assert mat(ctypes.byref(mm), 4, dummy, dummy, 0.0, 0.0, 8, dummy, None, None) == EINVAL
+    assert mat(ctypes.byref(mm), 4, dummy, dummy, float("nan"), 0.1, 8, dummy, None,
+               None) == EINVAL
+    assert mat(ctypes.byref(mm), 4, dummy, dummy, 0.0, float("inf"), 8, dummy, None,
+               None) == EINVAL
+    assert mat(ctypes.byref(mm), 4, dummy, None, 0.0, 0.1, 8, dummy, None, None) == EINVAL
+    assert mat(ctypes.byref(mm), -1, dummy, dummy, 0.0, 0.1, 8, dummy, None, None) == EINVAL
+    assert mat(ctypes.byref(vup.VupMM()), 4, dummy, dummy, 0.0, 0.1, 8, dummy, None,
+               None) == EWORKSPACE
+    # ipsa_fields: levels outside (0, 1], too many, dev without y_ref, quant without levels
+    fl = lib.vup_ipsa_fields
+    lv = (ctypes.c_double * 17)(*([0.5] * 17))
+    bad = (ctypes.c_double * 2)(0.5, 0.0)
+    over = (ctypes.c_double * 1)(1.5)
+    assert fl(ctypes.byref(mm), 4, dummy, dummy, 2, bad, None, None, dummy, None, None,
+              None) == EINVAL
+    assert fl(ctypes.byref(mm), 4, dummy, dummy, 1, over, None, None, dummy, None, None,
+              None) == EINVAL
+    assert fl(ctypes.byref(mm), 4, dummy, dummy, 17, lv, None, None, dummy, None, None,
+              None) == EINVAL
+    assert fl(ctypes.byref(mm), 4, dummy, None, 1, lv, None, None, None, dummy, None,
+              None) == EINVAL
+    assert fl(ctypes.byref(mm), 4, dummy, dummy, 0, None, None, None, dummy, None, None,
+              None) == EINVAL
+    assert fl(ctypes.byref(mm), 4, None, dummy, 1, lv, dummy, None, None, None, None,
+              None) == EINVAL
+    # marginal: workspace size rule and checks
+    assert lib.vup_marginal_workspace_bytes(65536, 256) == 2048 * 256 * 8
+    assert lib.vup_marginal_workspace_bytes(0, 256) == 0
+    assert lib.vup_marginal_workspace_bytes(10, 0) == 0
+    assert lib.vup_marginalize(10, 0, dummy, None, dummy, 1 << 20, dummy, None) == EINVAL
+    assert lib.vup_marginalize(-1, 4, dummy, None, dummy, 1 << 20, dummy, None) == EINVAL
+    assert lib.vup_marginalize(10, 4, None, None, dummy, 1 << 20, dummy, None) == EINVAL
+    need = lib.vup_marginal_workspace_bytes(100, 9)
+    assert lib.vup_marginalize(100, 9, dummy, None, dummy, need - 1, dummy, None) == EWORKSPACE
+    assert lib.vup_marginalize(100, 9, dummy, None, None, need, dummy, None) == EWORKSPACE

@@ -23,6 +23,16 @@ also use analytic models on uniform grids, so no dataset is involved):
                mixtures, weights Dirichlet(1,1), mu ~ U[-1.5,1.5]^4,
                isotropic sigma per component ~ U[0.05, 0.25] (seed 11246005).
 
+* ``ipsa_example(sigma_l)`` the IPSA example of Sec. 5.3: 2-D 1000 x 1000
+               grid over (x, alpha) in [-5,5] x [-1,1] (N = 10^6), model
+               x^2 + 5 sin 3x + alpha, B = 1000, K = 1000 measurement
+               locations l on the 1000-cell midpoints of [-5,5], pdf centred
+               at (l, 0) with sigma = (sigma_l, 0.25), truncated at the domain
+               boundary (8-sigma windows, so the boundary is the only cut that
+               matters). The paper runs sigma_l in {0.05, 0.25, 0.5, 1, 3}; it
+               does not state the domain, which is a reading (x spans the
+               locations, alpha spans 4 sigma_alpha).
+
 Means "on an M x M subgrid" are the subgrid cell midpoints
 lo + (m + 1/2)(hi - lo)/M on each axis, with k = m0 * M + m1.
 """
@@ -160,6 +170,21 @@ def random_workload(name: str, n, lo, hi, model: str, B: int, K: int, C: int,
                     tuple(float(x) for x in hi), model, tuple(theta), B,
                     np.ascontiguousarray(mu), np.ascontiguousarray(sigma),
                     None if weight is None else np.ascontiguousarray(weight))
+
+
+IPSA_EXAMPLE_SIGMAS = (0.05, 0.25, 0.5, 1.0, 3.0)
+
+
+def ipsa_example(sigma_l: float = 0.25) -> Workload:
+    K = 1000
+    l = subgrid_midpoints(-5.0, 5.0, K)
+    mu = np.zeros((K, 1, 2), dtype=np.float64)
+    mu[:, 0, 0] = l
+    sigma = np.empty((K, 1, 2), dtype=np.float64)
+    sigma[:, 0, 0] = sigma_l
+    sigma[:, 0, 1] = 0.25
+    return Workload(f"ipsa_example[sigma_l={sigma_l}]", 2, (1000, 1000), (-5.0, -1.0),
+                    (5.0, 1.0), "ipsa2", (), 1000, mu, sigma, None, n_sigma=8.0)
 
 
 CONFIGS = {
