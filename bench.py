@@ -15,6 +15,9 @@ exact number of (cell, distribution) pairs inside the truncation windows.
 Also reported (same workload, same run): propagation alone at each density
 precision, and forward + backward (propagate + IPSA + adjoint sweep), each
 with its error against the FP64 oracle on a seeded sample of distributions;
+the IPSA probability matrix, field lines and marginal over locations on the
+step's P with their HBM rooflines; the IPSA example of Sec. 5.3 at its five
+measurement uncertainties;
 the roofline of the longest sweep kernel of the step (and of the other one)
 from HIP events; and the CPU oracle's own throughput on a bounded sample.
 
@@ -27,6 +30,7 @@ Profiling helpers (rocprofv3 wraps the program; see profiles/):
   --summarize-stats CSV OUT   rocprofv3 kernel_stats.csv -> markdown table
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -96,6 +100,120 @@ def kernels_once():
 
 
 CALIB_BYTES = 256 << 20
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def _time_on(stream, fn, reps, batch=1):
+    """Mean ms per fn() call, HIP events on the launch stream around `batch`
+    back-to-back calls (so that short kernels are not timed with host gaps),
+    averaged over reps."""
+    import torch
+    fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record(stream)
+        for _ in range(batch):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / batch)
+    return float(np.mean(ts))
+
+
+def _c_call(vup, name, *args):
+    """A prepared C-ABI call (argument marshalling done once) that raises on error."""
+    f = getattr(vup.lib(), name)
+
+    def call():
+        rc = f(*args)
+        if rc != 0:
+            raise RuntimeError(f"{name}: {vup.lib().vup_last_error().decode()}")
+    return call
+
+
+def ipsa_views(vup, mm, P, mu, stream, reps):
+    """The IPSA probability matrix, field lines and marginal on the step's P
+    (Sec. 5.2): time and HBM roofline of each (algorithmic bytes per launch:
+    what the kernel must read and write once)."""
+    import torch
+    K, B = P.shape
+    e = mm.edges.cpu().numpy()
+    rng_f = float(e[-1] - e[0])
+    n_dy = 2 * B
+    dy_lo, dy_w = -rng_f, 2 * rng_f / n_dy
+    lv = (0.025, 0.5, 0.975)
+    y = vup.eval_points("sincos2", mu[:, 0, :])
+    Q, lost = vup.ipsa_matrix(mm, P, y, dy_lo, dy_w, n_dy)
+    fl = vup.ipsa_fields(mm, P, y, lv)
+    ws = torch.empty(max(vup.marginal_workspace_bytes(K, n_dy), 1), dtype=torch.uint8,
+                     device=P.device)
+    chunks_bytes = vup.marginal_workspace_bytes(K, n_dy)
+    g_out = torch.empty(n_dy, dtype=torch.float64, device=P.device)
+    y2 = torch.empty_like(y)
+    v = lambda t: ctypes.c_void_p(t.data_ptr())
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    mref = ctypes.byref(mm.mm)
+    model = vup.make_model("sincos2")
+    mu0 = mu[:, 0, :]
+    lvc = (ctypes.c_double * len(lv))(*lv)
+    cases = {
+        "eval_points": (_c_call(vup, "vup_eval_points", ctypes.byref(model), 2, K, v(mu0),
+                                mu0.stride(0), v(y2), sp), K * (16 + 8), "k_eval_points"),
+        "ipsa_matrix": (_c_call(vup, "vup_ipsa_matrix", mref, K, v(P), v(y), dy_lo, dy_w, n_dy,
+                                v(Q), v(lost), sp),
+                        K * B * 4 + K * 8 + K * n_dy * 4 + K * 8, "k_ipsa_matrix"),
+        "ipsa_fields": (_c_call(vup, "vup_ipsa_fields", mref, K, v(P), v(y), len(lv), lvc,
+                                v(fl["y_mode"]), v(fl["p_max"]), v(fl["quant"]), v(fl["dev"]),
+                                v(fl["delta2"]), sp),
+                        K * B * 4 + K * 8 + K * (4 + len(lv)) * 8, "k_ipsa_fields"),
+        "marginalize_Q": (_c_call(vup, "vup_marginalize", K, n_dy, v(Q), None, v(ws),
+                                  ws.numel(), v(g_out), sp),
+                          K * n_dy * 4 + 2 * chunks_bytes + n_dy * 8,
+                          "k_marg_partial + k_marg_combine"),
+    }
+    out = {"n_dy": n_dy, "levels": list(lv), "timing": "HIP events around 20 back-to-back "
+           "C-ABI calls on the launch stream, mean of reps"}
+    for name, (fn, nbytes, kern) in cases.items():
+        ms = _time_on(stream, fn, reps, batch=20)
+        ach = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "roofline": {"bound": "hbm", "achieved": ach,
+                                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                             "frac": ach / HBM_PEAK_GBS,
+                                             "algorithmic_bytes": nbytes, "kernel": kern}}
+    return out
+
+
+def ipsa_example_runs(vup, workloads, stream, reps):
+    """The IPSA example of Sec. 5.3 (N = 10^6 grid over (x, alpha), K = 1000
+    locations, B = 1000) at each measurement uncertainty: model matrix once,
+    then propagation, y(l), the IPSA matrix (2000 Delta-y cells) and the field
+    lines, timed together with HIP events."""
+    import torch
+    res = {}
+    for s_l in workloads.IPSA_EXAMPLE_SIGMAS:
+        wl = workloads.ipsa_example(s_l)
+        g = vup.make_grid(wl.n, wl.lo, wl.hi)
+        f = vup.eval_grid(g, wl.model)
+        mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
+        mu = torch.from_numpy(wl.mu).to("cuda")
+        sg = torch.from_numpy(wl.sigma).to("cuda")
+        win = vup.windows(g, mu, sg, wl.n_sigma)
+        U = int(torch.prod((win[..., 1] - win[..., 0] + 1).to(torch.int64), dim=-1).sum().item())
+        e = mm.edges.cpu().numpy()
+        rng_f = float(e[-1] - e[0])
+
+        def run():
+            P, _ = vup.propagate(mm, mu, sg, None, "fp32", wl.n_sigma, want_Z=False)
+            y = vup.eval_points("ipsa2", mu[:, 0, :])
+            vup.ipsa_matrix(mm, P, y, -rng_f, rng_f / 1000, 2000)
+            vup.ipsa_fields(mm, P, y, (0.025, 0.5, 0.975))
+
+        ms = _time_on(stream, run, reps)
+        res[str(s_l)] = {"ms": ms, "updates": U, "updates_per_s": U / (ms * 1e-3),
+                         "sweep_form": mm.sweep}
+    return res
 # kernel-name fragments of the sweep kernels in rocprofv3 output
 TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments"}
 
@@ -311,6 +429,15 @@ def main():
         variants["fwd_bwd_fp32"] = {"updates_per_s": U / t, "ms": 1e3 * t,
                                     "note": "U counted once; forward and adjoint each sweep U"}
         result["variants"] = variants
+        result["ipsa_views"] = ipsa_views(vup, mm, Ps["fp32"], mu, stream,
+                                          max(3, args.steps // 2))
+        result["ipsa_example"] = ipsa_example_runs(vup, workloads, stream,
+                                                   max(3, args.steps // 2))
+        log("[bench] IPSA views " + ", ".join(
+            f"{k} {v['ms']:.3f} ms" for k, v in result["ipsa_views"].items()
+            if isinstance(v, dict)))
+        log("[bench] Sec. 5.3 example " + ", ".join(
+            f"sigma_l={k}: {v['ms']:.3f} ms" for k, v in result["ipsa_example"].items()))
     else:
         Ps = None
 

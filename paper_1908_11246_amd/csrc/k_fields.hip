@@ -1,6 +1,7 @@
-// Sensitivity views of the propagated output matrix (Sec. 5.2) and the model
-// at the input pdfs' maxima (Sec. 5.3):
+// Kernels over the columns of the propagated output matrix (Sec. 5.2) and the
+// model at the input pdfs' maxima (Sec. 5.3):
 //   k_eval_points    y_i = M(x_i) at caller-given points, FP64
+//   k_ipsa           binned mean, two-pass variance and entropy per column
 //   k_ipsa_matrix    IPSA probability matrix: each column of P, read as a
 //                    piecewise-constant density over its bins, is translated
 //                    by y(l) and integrated over a uniform Delta-y grid; done
@@ -11,12 +12,9 @@
 //   k_marg_partial / k_marg_combine   global marginal over locations,
 //                    out[j] = sum_k rho_k A[k][j], in a fixed order
 //
-// The column kernels give one wave64 to one column at a time. Lane l owns the
-// bins [l*m, l*m + m), m = ceil(B/64): it reads them (coalesced across the
-// wave), keeps their running sum, and after an exclusive scan of the lane
-// totals writes C_b = sum_{b'<b} P_b' (FP64) into the wave's LDS slice. The
-// bin edges sit once per workgroup in LDS. All HBM traffic is one read of P
-// and one write of the outputs.
+// The column kernels give one wave64 to one column at a time (see
+// stream_columns); the bin edges sit once per workgroup in LDS. All HBM
+// traffic is one read of P and one write of the outputs.
 #include <hip/hip_runtime.h>
 
 #include "vup_device.hpp"
@@ -47,79 +45,238 @@ hipError_t launch_eval_points(const vup_model& m, int ndim, int64_t n, const dou
 }
 
 // ---------------------------------------------------------------------------
-// shared pieces of the column kernels
+// column streaming shared by the column kernels
+//
+// A column is handled by a group of LPC lanes: LPC = 16 (four columns per
+// wave, one per DPP row) when B <= 1024, else LPC = 64. Lane r of a group
+// holds, for round i, the four bins RS i + 4 r .. + 3 (RS = 4 LPC bins per
+// round) in one float4, zero beyond B, so a round is one coalesced read of
+// 16 LPC bytes per column. Each wave walks its own sequence of column slots
+// (no workgroup barrier in the loop) and loads the next slot's columns while
+// it works on the current ones. Sums within a group use DPP row operations
+// (LPC = 16) or the whole-wave reduction (LPC = 64), in a fixed order.
 // ---------------------------------------------------------------------------
-struct ColArgs {
-  const double* edges;  // [B+1]
-  const float* P;       // [K][B]
-  const double* y_ref;  // [K]
-  long long K;
-  int B;
-  int m;       // bins per lane, ceil(B/64)
-  int waves;   // columns in flight per workgroup (one per wave)
-  int c_off;   // doubles from the start of LDS to the first wave's CDF
-};
+template <int LPC, int MV, bool VEC>
+__device__ __forceinline__ void load_col(const float* __restrict__ P, long long k, long long K,
+                                         int B, float4 (&v)[MV]) {
+  const int r = threadIdx.x & (LPC - 1);
+  const float* col = P + k * (long long)B;
+  const bool live = k < K;
+#pragma unroll
+  for (int i = 0; i < MV; ++i) {
+    const int b = 4 * LPC * i + 4 * r;
+    if constexpr (VEC) {
+      v[i] = live && b < B ? *reinterpret_cast<const float4*>(col + b)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      v[i].x = live && b < B ? col[b] : 0.f;
+      v[i].y = live && b + 1 < B ? col[b + 1] : 0.f;
+      v[i].z = live && b + 2 < B ? col[b + 2] : 0.f;
+      v[i].w = live && b + 3 < B ? col[b + 3] : 0.f;
+    }
+  }
+}
 
-struct MatrixArgs {
-  ColArgs c;
-  double dy_lo, dy_width;
-  int J;       // target cells
-  int mt;      // target cells per lane, ceil(J/64)
-  float* Q;    // [K][J]
-  double* lost;
-};
+// body(k, live, v): k = this group's column, live = k < K (uniform in the
+// group); every lane of the wave calls body for every slot
+template <int LPC, int MV, bool VEC, class Body>
+__device__ __forceinline__ void stream_columns(const float* __restrict__ P, long long K, int B,
+                                               Body&& body) {
+  constexpr int G = 64 / LPC;
+  const int waves = blockDim.x >> 6;
+  const long long step = (long long)gridDim.x * waves * G;
+  const int g = (threadIdx.x & 63) / LPC;
+  long long base = ((long long)blockIdx.x * waves + (threadIdx.x >> 6)) * G;
+  float4 cur[MV];
+  if (base < K) load_col<LPC, MV, VEC>(P, base + g, K, B, cur);
+  while (base < K) {
+    const long long nb = base + step;
+    float4 nxt[MV];
+    if (nb < K) {
+      load_col<LPC, MV, VEC>(P, nb + g, K, B, nxt);
+    } else {
+#pragma unroll
+      for (int i = 0; i < MV; ++i) nxt[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    body(base + g, base + g < K, cur);
+#pragma unroll
+    for (int i = 0; i < MV; ++i) cur[i] = nxt[i];
+    base = nb;
+  }
+}
 
-struct FieldArgs {
-  ColArgs c;
-  int nq;
-  double level[kMaxLevels];
-  double* y_mode;
-  double* p_max;
-  double* quant;  // [K][nq]
-  double* dev;
-  double* delta2;
-};
-
-__device__ __forceinline__ double shfl_up1(double v) {
+__device__ __forceinline__ double shfl_f64(double v, int src) {
   const long long b = __double_as_longlong(v);
-  const int lo = __shfl_up((int)(b & 0xFFFFFFFF), 1, 64);
-  const int hi = __shfl_up((int)(b >> 32), 1, 64);
+  const int lo = __shfl((int)(b & 0xFFFFFFFF), src, 64);
+  const int hi = __shfl((int)(b >> 32), src, 64);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// copy the edges into LDS (whole workgroup)
-__device__ __forceinline__ void stage_edges(const ColArgs& a, double* E) {
-  for (int b = threadIdx.x; b <= a.B; b += blockDim.x) E[b] = a.edges[b];
+// value of the previous lane of the group (0 for the group's first lane)
+template <int LPC>
+__device__ __forceinline__ double grp_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __shfl_up((int)(b & 0xFFFFFFFF), 1, LPC);
+  const int hi = __shfl_up((int)(b >> 32), 1, LPC);
+  const double p = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  return (threadIdx.x & (LPC - 1)) == 0 ? 0.0 : p;
 }
 
-// FP64 CDF of one column into C[0..B]; returns T = C[B] (uniform). `visit`
-// sees every (bin, P value) the lane owns, in increasing bin order.
-template <class Visit>
-__device__ __forceinline__ double build_cdf(const ColArgs& a, long long k, double* C, Visit&& visit) {
-  const int lane = threadIdx.x & 63;
-  const int b0 = lane * a.m;
-  const float* col = a.P + k * (long long)a.B;
-  double run = 0.0;
-  for (int i = 0; i < a.m; ++i) {
-    const int b = b0 + i;
-    if (b < a.B) {
-      const float p = col[b];
-      C[b] = run;
-      run += (double)p;
-      visit(b, p);
+// inclusive scan within the group
+template <int LPC>
+__device__ __forceinline__ double grp_scan(double v) {
+  if constexpr (LPC == 16) return row_scan(v);
+  else return wave_scan(v);
+}
+
+// the group's last lane's value, given to every lane of the group
+template <int LPC>
+__device__ __forceinline__ double grp_last(double v) {
+  if constexpr (LPC == 16) return shfl_f64(v, (threadIdx.x & 63) | 15);
+  else return lane_value(v, 63);
+}
+
+template <int LPC>
+__device__ __forceinline__ double grp_sum(double v) {
+  if constexpr (LPC == 16) return grp_last<16>(row_scan(v));
+  else return wave_sum(v);
+}
+
+__device__ __forceinline__ float f4(const float4& v, int j) {
+  return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// LDS writes of a wave made visible to the wave's other lanes
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Column CDF in registers, one round at a time. col_scan gives each lane the
+// inclusive group scan of its four-bin sums per round and returns the column
+// total T; round_cdf then yields c[j] = C_{b+j} for the lane's bins b + j and
+// c[4] = C_{b+4}. The end value c[4] is taken from the scan itself, so it
+// equals the next lane's c[0] (and, for the column's last bins, T) bit for
+// bit: the lanes' intervals (c[0], c[4]] tile (0, T] with no gap or overlap.
+template <int LPC, int MV>
+__device__ __forceinline__ double col_scan(const float4 (&v)[MV], int B, double (&incl)[MV]) {
+  double T = 0.0;
+#pragma unroll
+  for (int i = 0; i < MV; ++i) {
+    incl[i] = 0.0;
+    if (4 * LPC * i < B) {
+      const double s = (((double)v[i].x + (double)v[i].y) + (double)v[i].z) + (double)v[i].w;
+      incl[i] = grp_scan<LPC>(s);
+      T += grp_last<LPC>(incl[i]);
     }
   }
-  const double incl = wave_scan(run);
-  double off = shfl_up1(incl);
-  if (lane == 0) off = 0.0;
-  const double T = lane_value(incl, 63);
-  for (int i = 0; i < a.m; ++i) {
-    const int b = b0 + i;
-    if (b < a.B) C[b] = off + C[b];
-  }
-  if (lane == 0) C[a.B] = T;
   return T;
 }
+
+// `base` is the mass of the earlier rounds, advanced exactly as col_scan
+// accumulated T
+template <int LPC>
+__device__ __forceinline__ void round_cdf(const float4& v, double incl, double& base,
+                                          double (&c)[5]) {
+  c[0] = base + grp_prev<LPC>(incl);
+  c[1] = c[0] + (double)v.x;
+  c[2] = c[1] + (double)v.y;
+  c[3] = c[2] + (double)v.z;
+  c[4] = base + incl;
+  base += grp_last<LPC>(incl);
+}
+
+// edges, bin centres and (for the matrix) reciprocal bin widths, once per
+// workgroup
+__device__ __forceinline__ void stage_tables(const double* __restrict__ edges, int B, double* E,
+                                             double* cen, double* invw) {
+  if (E)
+    for (int b = threadIdx.x; b <= B; b += blockDim.x) E[b] = edges[b];
+  if (cen)
+    for (int b = threadIdx.x; b < B; b += blockDim.x) cen[b] = 0.5 * (edges[b] + edges[b + 1]);
+  if (invw)
+    for (int b = threadIdx.x; b < B; b += blockDim.x) invw[b] = 1.0 / (edges[b + 1] - edges[b]);
+  __syncthreads();
+}
+
+// p ln p for one FP32 probability: FP32 base-2 logarithm of the FP32 value
+// (relative error a few 2^-24), scaled and accumulated in FP64. Values below
+// the smallest normal FP32 number contribute less than 1e-36 and are skipped.
+__device__ __forceinline__ double p_log2_p(float p) {
+  return p >= 1.17549435e-38f ? (double)p * (double)__log2f(p) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// coarse-grained statistics of vup_ipsa: binned mean, two-pass variance and
+// entropy, FP64 sums (Sec. 5.2)
+// ---------------------------------------------------------------------------
+struct StatArgs {
+  const float* P;
+  const double* edges;
+  long long K;
+  int B;
+  double* mean_hist;
+  double* var;
+  double* entropy;
+};
+
+template <int LPC, int MV, bool VEC>
+__global__ __launch_bounds__(256) void k_ipsa(StatArgs a) {
+  extern __shared__ double lds[];
+  double* cen = lds;
+  const int B = a.B;
+  const int r = threadIdx.x & (LPC - 1);
+  stage_tables(a.edges, B, nullptr, cen, nullptr);
+  stream_columns<LPC, MV, VEC>(a.P, a.K, B, [&](long long k, bool live, const float4 (&v)[MV]) {
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+      const int b = 4 * LPC * i + 4 * r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (b + j < B) m += (double)f4(v[i], j) * cen[b + j];
+    }
+    m = grp_sum<LPC>(m);
+    double var = 0.0, h = 0.0;
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+      const int b = 4 * LPC * i + 4 * r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (b + j < B) {
+          const float p = f4(v[i], j);
+          const double dc = cen[b + j] - m;
+          var += (double)p * (dc * dc);
+          h += p_log2_p(p);
+        }
+      }
+    }
+    var = grp_sum<LPC>(var);
+    h = grp_sum<LPC>(h);
+    if (live && r == 0) {
+      if (a.mean_hist) a.mean_hist[k] = m;
+      if (a.var) a.var[k] = var;
+      if (a.entropy) a.entropy[k] = -0.69314718055994530942 * h;
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// IPSA probability matrix
+// ---------------------------------------------------------------------------
+struct MatrixArgs {
+  const float* P;       // [K][B]
+  const double* edges;  // [B+1]
+  const double* y_ref;  // [K]
+  long long K;
+  int B;
+  double dy_lo, dy_width;
+  int J;       // target cells
+  int mt;      // target cells per lane, ceil(J/LPC)
+  float* Q;    // [K][J]
+  double* lost;
+};
 
 // number of edges e_0..e_B that are <= t (0 for NaN t)
 __device__ __forceinline__ int count_le(const double* E, int B, double t) {
@@ -133,12 +290,12 @@ __device__ __forceinline__ int count_le(const double* E, int B, double t) {
 }
 
 // piecewise-linear CDF at t, given cnt = count_le(t)
-__device__ __forceinline__ double cdf_at(const double* E, const double* C, int B, double T, int cnt,
-                                         double t) {
+__device__ __forceinline__ double cdf_at(const double* E, const double* invw, const double* C, int B,
+                                         double T, int cnt, double t) {
   if (cnt == 0) return 0.0;
   if (cnt > B) return T;
   const int b = cnt - 1;
-  const double frac = (t - E[b]) / (E[b + 1] - E[b]);
+  const double frac = (t - E[b]) * invw[b];
   return C[b] + (C[b + 1] - C[b]) * frac;
 }
 
@@ -148,93 +305,173 @@ __device__ __forceinline__ double target_point(double dlo, double h, int j, doub
   return __dadd_rn(__dadd_rn(dlo, __dmul_rn((double)j, h)), y);
 }
 
-// ---------------------------------------------------------------------------
-// IPSA probability matrix
-// ---------------------------------------------------------------------------
+template <int LPC, int MV, bool VEC>
 __global__ __launch_bounds__(256) void k_ipsa_matrix(MatrixArgs a) {
+  constexpr int G = 64 / LPC;
   extern __shared__ double lds[];
+  const int B = a.B;
   double* E = lds;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* C = lds + a.c.c_off + wave * (a.c.B + 1);
-  const int B = a.c.B;
-  stage_edges(a.c, E);
-  const long long per_iter = (long long)gridDim.x * a.c.waves;
-  for (long long base = (long long)blockIdx.x * a.c.waves; base < a.c.K; base += per_iter) {
-    __syncthreads();  // edges staged / previous column's CDF no longer read
-    const long long k = base + wave;
-    const bool active = wave < a.c.waves && k < a.c.K;
-    double T = 0.0;
-    if (active) T = build_cdf(a.c, k, C, [](int, float) {});
-    __syncthreads();
-    if (!active) continue;
-    const int j0 = lane * a.mt;
+  double* invw = lds + (B + 1);
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (LPC - 1);
+  const int g = lane / LPC;
+  double* C = lds + (2 * B + 1) + ((threadIdx.x >> 6) * G + g) * (B + 1);
+  stage_tables(a.edges, B, E, nullptr, invw);
+  stream_columns<LPC, MV, VEC>(a.P, a.K, B, [&](long long k, bool live, const float4 (&v)[MV]) {
+    double incl[MV];
+    const double T = col_scan<LPC, MV>(v, B, incl);
+    double base = 0.0;
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+      if (4 * LPC * i < B) {
+        double c[5];
+        round_cdf<LPC>(v[i], incl[i], base, c);
+        const int b = 4 * LPC * i + 4 * r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (b + j < B) C[b + j] = c[j];
+      }
+    }
+    if (r == 0) C[B] = T;
+    wave_lds_sync();
+    const int j0 = r * a.mt;
     const int j1 = min(a.J, j0 + a.mt);
     float* q = a.Q + k * (long long)a.J;
-    const int last = (a.J - 1) / a.mt;  // lane owning the last target cell
-    if (!isfinite(T)) {
-      for (int j = j0; j < j1; ++j) q[j] = __builtin_nanf("");
-      if (lane == 0 && a.lost) a.lost[k] = __builtin_nan("");
-      continue;
-    }
-    const double y = a.c.y_ref[k];
+    const int last = (a.J - 1) / a.mt;  // lane of the group owning the last target cell
     double F_first = 0.0, F_end = 0.0;
-    if (j0 < j1) {
+    const bool fin = isfinite(T);
+    if (live && fin && j0 < j1) {
+      const double y = a.y_ref[k];
       double t = target_point(a.dy_lo, a.dy_width, j0, y);
       int cnt = count_le(E, B, t);
-      double F = cdf_at(E, C, B, T, cnt, t);
+      double F = cdf_at(E, invw, C, B, T, cnt, t);
       F_first = F;
       for (int j = j0; j < j1; ++j) {
         t = target_point(a.dy_lo, a.dy_width, j + 1, y);
+        // two branch-free steps cover target cells up to about a bin wide;
+        // the loop catches wider ones
+#pragma unroll
+        for (int u = 0; u < 2; ++u) cnt += (cnt <= B && E[min(cnt, B)] <= t) ? 1 : 0;
         while (cnt <= B && E[cnt] <= t) ++cnt;
-        const double Fn = cdf_at(E, C, B, T, cnt, t);
+        const double Fn = cdf_at(E, invw, C, B, T, cnt, t);
         q[j] = (float)(Fn - F);
         F = Fn;
       }
       F_end = F;
+    } else if (live && !fin) {
+      for (int j = j0; j < j1; ++j) q[j] = __builtin_nanf("");
     }
-    const double lo_part = lane_value(F_first, 0);
-    const double hi_part = lane_value(F_end, last);
-    if (lane == 0 && a.lost) a.lost[k] = lo_part + (T - hi_part);
-  }
+    const double lo_part = shfl_f64(F_first, g * LPC);
+    const double hi_part = shfl_f64(F_end, g * LPC + last);
+    if (live && r == 0 && a.lost) a.lost[k] = fin ? lo_part + (T - hi_part) : __builtin_nan("");
+    wave_lds_sync();  // C is rewritten for the next columns
+  });
 }
 
 // ---------------------------------------------------------------------------
 // field lines
 // ---------------------------------------------------------------------------
+struct FieldArgs {
+  const float* P;
+  const double* edges;
+  const double* y_ref;
+  long long K;
+  int B;
+  int nq;
+  double level[kMaxLevels];
+  double* y_mode;
+  double* p_max;
+  double* quant;  // [K][nq]
+  double* dev;
+  double* delta2;
+};
+
+template <int LPC, int MV, bool VEC>
 __global__ __launch_bounds__(256) void k_ipsa_fields(FieldArgs a) {
   extern __shared__ double lds[];
+  const int B = a.B;
   double* E = lds;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* C = lds + a.c.c_off + wave * (a.c.B + 1);
-  const int B = a.c.B;
+  double* cen = lds + (B + 1);
+  double* lev = lds + (2 * B + 1);
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (LPC - 1);
+  const int g = lane / LPC;
   const double nan = __builtin_nan("");
-  stage_edges(a.c, E);
-  const long long per_iter = (long long)gridDim.x * a.c.waves;
-  for (long long base = (long long)blockIdx.x * a.c.waves; base < a.c.K; base += per_iter) {
-    __syncthreads();
-    const long long k = base + wave;
-    const bool active = wave < a.c.waves && k < a.c.K;
-    const double y = (active && a.c.y_ref) ? a.c.y_ref[k] : 0.0;
+  if (threadIdx.x < kMaxLevels) lev[threadIdx.x] = a.level[threadIdx.x];
+  stage_tables(a.edges, B, E, cen, nullptr);
+  stream_columns<LPC, MV, VEC>(a.P, a.K, B, [&](long long k, bool live, const float4 (&v)[MV]) {
+    const double y = (live && a.y_ref) ? a.y_ref[k] : 0.0;
+    double incl[MV];
+    const double T = col_scan<LPC, MV>(v, B, incl);
+    const bool finite = isfinite(T);
+    const bool positive = finite && T > 0.0;
     float vmax = -__builtin_inff();
     int imax = B;
     double s1 = 0.0, s2 = 0.0;
-    double T = 0.0;
-    if (active) {
-      T = build_cdf(a.c, k, C, [&](int b, float p) {
-        if (p > vmax) {
-          vmax = p;
-          imax = b;
+    double base = 0.0;
+    unsigned found = 0u;  // levels answered so far (uniform in the group)
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+      if (4 * LPC * i < B) {
+        const int b = 4 * LPC * i + 4 * r;
+        double c[5];
+        round_cdf<LPC>(v[i], incl[i], base, c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (b + j < B) {
+            const float p = f4(v[i], j);
+            if (p > vmax) {
+              vmax = p;
+              imax = b + j;
+            }
+            const double t = cen[b + j] - y;
+            const double pt = (double)p * t;
+            s1 += pt;
+            s2 += pt * t;
+          }
         }
-        const double t = 0.5 * (E[b] + E[b + 1]) - y;
-        const double pt = (double)p * t;
-        s1 += pt;
-        s2 += pt * t;
-      });
+        if (a.quant) {
+#pragma unroll 1
+          for (int q = 0; q < a.nq; ++q) {
+            {
+              const double target = lev[q] * T;
+              const bool want = positive && !(found & (1u << q));
+              const bool mine = want && b < B && c[0] < target && target <= c[4];
+              const unsigned long long mask = __ballot(mine);
+              // this group's bits of the ballot
+              unsigned long long gm = mask;
+              if constexpr (LPC < 64) gm = (mask >> (g * LPC)) & ((1ull << LPC) - 1);
+              if (gm != 0ull) {
+                found |= 1u << q;
+                if (live && r == __ffsll((long long)gm) - 1) {
+                  // first of the lane's bins whose upper CDF value reaches the
+                  // level (selects only: no register array indexed at run time)
+                  const int jj = c[1] >= target ? 0 : c[2] >= target ? 1 : c[3] >= target ? 2 : 3;
+                  const double cj = jj == 0 ? c[0] : jj == 1 ? c[1] : jj == 2 ? c[2] : c[3];
+                  const double pb = (double)f4(v[i], jj);
+                  double* out = a.quant + k * (long long)a.nq + q;
+                  if (pb > 0.0) {
+                    const double frac = fmin(fmax((target - cj) / pb, 0.0), 1.0);
+                    *out = E[b + jj] + frac * (E[b + jj + 1] - E[b + jj]);
+                  } else {
+                    // reached only when rounding puts the level an ulp past
+                    // the end of the last positive bin before an empty
+                    // stretch: answer that bin's right edge
+                    int jb = -1;
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2)
+                      if (t2 <= jj && f4(v[i], t2) > 0.0f) jb = t2;
+                    *out = jb >= 0 ? E[b + jb + 1] : E[b];
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
     }
-    __syncthreads();
-    if (!active) continue;
-    // first maximum over the wave: larger value wins, equal values keep the lower bin
-    for (int o = 32; o >= 1; o >>= 1) {
+    // first maximum over the group: larger value wins, equal values keep the lower bin
+    for (int o = LPC / 2; o >= 1; o >>= 1) {
       const float ov = __shfl_xor(vmax, o, 64);
       const int oi = __shfl_xor(imax, o, 64);
       if (ov > vmax || (ov == vmax && oi < imax)) {
@@ -242,61 +479,23 @@ __global__ __launch_bounds__(256) void k_ipsa_fields(FieldArgs a) {
         imax = oi;
       }
     }
-    const double S1 = wave_sum(s1);
-    const double S2 = wave_sum(s2);
-    const bool finite = isfinite(T);
-    const bool positive = finite && T > 0.0;
-    if (lane == 0) {
+    const double S1 = grp_sum<LPC>(s1);
+    const double S2 = grp_sum<LPC>(s2);
+    if (live && r == 0) {
       if (a.p_max) a.p_max[k] = finite ? (double)vmax : nan;
-      if (a.y_mode) a.y_mode[k] = positive ? 0.5 * (E[imax] + E[imax + 1]) : nan;
+      if (a.y_mode) a.y_mode[k] = positive ? cen[imax] : nan;
       if (a.dev) a.dev[k] = finite ? S1 : nan;
       if (a.delta2) a.delta2[k] = finite ? 0.5 * S2 : nan;
+      if (a.quant)
+        for (int q = 0; q < a.nq; ++q)
+          if (!(found & (1u << q))) a.quant[k * (long long)a.nq + q] = nan;
     }
-    if (!a.quant) continue;
-    const int b0 = lane * a.c.m;
-    const int b1 = min(B, b0 + a.c.m);
-    const float* col = a.c.P + k * (long long)B;
-#pragma unroll
-    for (int q = 0; q < kMaxLevels; ++q) {
-      if (q < a.nq) {
-        const double target = a.level[q] * T;
-        const bool mine = positive && b0 < b1 && C[b0] < target && target <= C[b1];
-        const unsigned long long mask = __ballot(mine);
-        double* out = a.quant + k * (long long)a.nq + q;
-        if (mask == 0ull) {
-          if (lane == 0) *out = nan;
-        } else if (lane == __ffsll((long long)mask) - 1) {
-          int b = b0;
-          while (b < b1 - 1 && C[b + 1] < target) ++b;
-          const double pb = (double)col[b];
-          if (pb > 0.0) {
-            const double frac = fmin(fmax((target - C[b]) / pb, 0.0), 1.0);
-            *out = E[b] + frac * (E[b + 1] - E[b]);
-          } else {
-            // reached only when rounding puts the level an ulp past the end
-            // of the last positive bin before an empty stretch: answer that
-            // bin's right edge
-            int bb = b;
-            while (bb > b0 && col[bb] == 0.0f) --bb;
-            *out = col[bb] > 0.0f ? E[bb + 1] : E[b0];
-          }
-        }
-      }
-    }
-  }
+  });
 }
 
-// LDS layout: edges, then one CDF per wave; as many waves as fit in 64 KiB
-// (at least one, with the limit raised above 64 KiB when B needs it)
-static void col_layout(int B, int* waves, int* c_off, size_t* bytes) {
-  const size_t per = (size_t)(B + 1) * sizeof(double);
-  int w = kWaves;
-  while (w > 1 && per * (1 + w) > 65536) --w;
-  *waves = w;
-  *c_off = B + 1;
-  *bytes = per * (1 + w);
-}
-
+// ---------------------------------------------------------------------------
+// launch configuration of the column kernels
+// ---------------------------------------------------------------------------
 template <typename F>
 static hipError_t allow_lds(F* kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -304,22 +503,70 @@ static hipError_t allow_lds(F* kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-static ColArgs col_args(const double* edges, int B, int64_t K, const float* P, const double* y_ref,
-                        size_t* bytes) {
-  ColArgs c{};
-  c.edges = edges;
-  c.P = P;
-  c.y_ref = y_ref;
-  c.K = K;
-  c.B = B;
-  c.m = (B + 63) / 64;
-  col_layout(B, &c.waves, &c.c_off, bytes);
-  return c;
+// lanes per column (the statistics and field lines; the matrix always gives a
+// column a whole wave, whose lanes then share the target cells) and rounds
+// per column, rounded up to the instantiated sizes
+static int col_lpc(int B) { return B <= 1024 ? 16 : 64; }
+static int col_rounds(int B, int lpc) {
+  const int rs = 4 * lpc;
+  const int r = (B + rs - 1) / rs;
+  return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
 }
 
-static unsigned col_blocks(const ColArgs& c) {
-  const long long need = (c.K + c.waves - 1) / c.waves;
-  return (unsigned)(need < 4096 ? need : 4096);
+// waves per workgroup: 4 unless the per-wave LDS does not fit 64 KiB
+static int col_waves(size_t fixed, size_t per_wave) {
+  int w = 4;
+  while (w > 1 && fixed + per_wave * w > 65536) --w;
+  return w;
+}
+
+static unsigned col_grid(long long K, int lpc, int waves) {
+  const long long per_block = (long long)waves * (64 / lpc);
+  const long long need = (K + per_block - 1) / per_block;
+  return (unsigned)(need < 2048 ? need : 2048);
+}
+
+#define VUP_COL_CASE(NAME, LPC, MV)                        \
+  case (LPC == 16 ? 0 : 100) + MV * 2: kern = NAME<LPC, MV, false>; break; \
+  case (LPC == 16 ? 0 : 100) + MV * 2 + 1: kern = NAME<LPC, MV, true>; break;
+
+#define VUP_COL_KERNEL_TABLE(NAME, ARGS)                                                        \
+  static hipError_t launch_##NAME(const ARGS& a, int lpc, bool vec, int waves, size_t bytes,      \
+                                  hipStream_t s) {                                                \
+    void (*kern)(ARGS) = nullptr;                                                                 \
+    switch ((lpc == 16 ? 0 : 100) + col_rounds(a.B, lpc) * 2 + (vec ? 1 : 0)) {                   \
+      VUP_COL_CASE(NAME, 16, 1)                                                                   \
+      VUP_COL_CASE(NAME, 16, 2)                                                                   \
+      VUP_COL_CASE(NAME, 16, 4)                                                                   \
+      VUP_COL_CASE(NAME, 16, 8)                                                                   \
+      VUP_COL_CASE(NAME, 16, 16)                                                                  \
+      VUP_COL_CASE(NAME, 64, 1)                                                                   \
+      VUP_COL_CASE(NAME, 64, 2)                                                                   \
+      VUP_COL_CASE(NAME, 64, 4)                                                                   \
+      VUP_COL_CASE(NAME, 64, 8)                                                                   \
+      VUP_COL_CASE(NAME, 64, 16)                                                                  \
+      default: return hipErrorInvalidValue;                                                       \
+    }                                                                                             \
+    hipError_t e = allow_lds(kern, bytes);                                                        \
+    if (e != hipSuccess) return e;                                                                \
+    hipLaunchKernelGGL(kern, dim3(col_grid(a.K, lpc, waves)), dim3(64 * waves), bytes, s, a);     \
+    return hipGetLastError();                                                                     \
+  }
+
+VUP_COL_KERNEL_TABLE(k_ipsa, StatArgs)
+VUP_COL_KERNEL_TABLE(k_ipsa_matrix, MatrixArgs)
+VUP_COL_KERNEL_TABLE(k_ipsa_fields, FieldArgs)
+#undef VUP_COL_KERNEL_TABLE
+#undef VUP_COL_CASE
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+hipError_t launch_ipsa_stats(const double* edges, int B, int64_t K, const float* P,
+                             double* mean_hist, double* var, double* entropy, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  StatArgs a{P, edges, (long long)K, B, mean_hist, var, entropy};
+  const size_t bytes = (size_t)B * sizeof(double);
+  return launch_k_ipsa(a, col_lpc(B), B % 4 == 0 && aligned16(P), 4, bytes, s);
 }
 
 hipError_t launch_ipsa_matrix(const double* edges, int B, int64_t K, const float* P,
@@ -327,18 +574,23 @@ hipError_t launch_ipsa_matrix(const double* edges, int B, int64_t K, const float
                               float* Q, double* lost, hipStream_t s) {
   if (K == 0) return hipSuccess;
   MatrixArgs a{};
-  size_t bytes = 0;
-  a.c = col_args(edges, B, K, P, y_ref, &bytes);
+  a.P = P;
+  a.edges = edges;
+  a.y_ref = y_ref;
+  a.K = K;
+  a.B = B;
   a.dy_lo = dy_lo;
   a.dy_width = dy_width;
   a.J = n_dy;
-  a.mt = (n_dy + 63) / 64;
+  const int lpc = 64;
+  a.mt = (n_dy + lpc - 1) / lpc;
   a.Q = Q;
   a.lost = lost;
-  hipError_t e = allow_lds(k_ipsa_matrix, bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ipsa_matrix, dim3(col_blocks(a.c)), dim3(kThreads), bytes, s, a);
-  return hipGetLastError();
+  const size_t fixed = (size_t)(2 * B + 1) * sizeof(double);
+  const size_t per_wave = (size_t)(64 / lpc) * (B + 1) * sizeof(double);
+  const int waves = col_waves(fixed, per_wave);
+  return launch_k_ipsa_matrix(a, lpc, B % 4 == 0 && aligned16(P), waves, fixed + per_wave * waves,
+                              s);
 }
 
 hipError_t launch_ipsa_fields(const double* edges, int B, int64_t K, const float* P,
@@ -347,8 +599,11 @@ hipError_t launch_ipsa_fields(const double* edges, int B, int64_t K, const float
                               double* delta2, hipStream_t s) {
   if (K == 0) return hipSuccess;
   FieldArgs a{};
-  size_t bytes = 0;
-  a.c = col_args(edges, B, K, P, y_ref, &bytes);
+  a.P = P;
+  a.edges = edges;
+  a.y_ref = y_ref;
+  a.K = K;
+  a.B = B;
   a.nq = quant ? n_levels : 0;
   for (int q = 0; q < n_levels && q < kMaxLevels; ++q) a.level[q] = levels[q];
   a.y_mode = y_mode;
@@ -356,10 +611,8 @@ hipError_t launch_ipsa_fields(const double* edges, int B, int64_t K, const float
   a.quant = quant;
   a.dev = dev;
   a.delta2 = delta2;
-  hipError_t e = allow_lds(k_ipsa_fields, bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ipsa_fields, dim3(col_blocks(a.c)), dim3(kThreads), bytes, s, a);
-  return hipGetLastError();
+  const size_t bytes = (size_t)(2 * B + 1 + kMaxLevels) * sizeof(double);
+  return launch_k_ipsa_fields(a, col_lpc(B), B % 4 == 0 && aligned16(P), 4, bytes, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,6 +662,7 @@ __global__ __launch_bounds__(64) void k_marg_combine(const double* __restrict__ 
                                                      int n, double* __restrict__ out) {
   const int j = blockIdx.x;
   double s = 0.0;
+#pragma unroll 8
   for (int c = threadIdx.x; c < chunks; c += 64) s += part[(long long)c * n + j];
   s = wave_sum(s);
   if (threadIdx.x == 0) out[j] = s;

@@ -9,7 +9,7 @@
 //                   (bin, chunk) order; k_csr_offsets  CSR row starts and counts
 //   k_scatter       stable scatter of cell indices into compressed-by-bin
 //                   order (the sparse one-hot model matrix of eq. (5))
-// plus the per-distribution window listing and the IPSA column statistics.
+// plus the per-distribution window listing.
 #include <hip/hip_runtime.h>
 
 #include "vup_device.hpp"
@@ -439,44 +439,6 @@ hipError_t launch_windows(const vup_grid& g, const vup_dists& d, int32_t* win, h
   }
   a.d = make_dists_dev(d);
   hipLaunchKernelGGL(k_windows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, win);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// IPSA column statistics: one wave per column, FP64 accumulation
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ipsa(const float* __restrict__ P, long long K, int B,
-                                              const double* __restrict__ e, double* mean_hist,
-                                              double* var, double* entropy) {
-  const long long k = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= K) return;
-  const int lane = threadIdx.x & 63;
-  const float* Pk = P + k * (long long)B;
-  double m = 0.0;
-  for (int b = lane; b < B; b += 64) m += (double)Pk[b] * (0.5 * (e[b] + e[b + 1]));
-  m = wave_sum(m);
-  double v = 0.0, h = 0.0;
-  for (int b = lane; b < B; b += 64) {
-    const double p = (double)Pk[b];
-    const double dc = 0.5 * (e[b] + e[b + 1]) - m;
-    v += p * (dc * dc);
-    if (p > 0.0) h -= p * log(p);
-  }
-  v = wave_sum(v);
-  h = wave_sum(h);
-  if (lane == 0) {
-    if (mean_hist) mean_hist[k] = m;
-    if (var) var[k] = v;
-    if (entropy) entropy[k] = h;
-  }
-}
-
-hipError_t launch_ipsa(const vup_mm& mm, int64_t K, const float* P, double* mean_hist, double* var,
-                       double* entropy, hipStream_t s) {
-  if (K == 0) return hipSuccess;
-  const double* e = reinterpret_cast<const double*>(static_cast<const char*>(mm.ws) + mm.off_edges);
-  hipLaunchKernelGGL(k_ipsa, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, s, P, (long long)K, mm.B, e,
-                     mean_hist, var, entropy);
   return hipGetLastError();
 }
 

@@ -267,8 +267,11 @@ int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, dou
   if (K < 0) return fail(VUP_EINVAL, "K < 0");
   if (K > 0 && !P) return fail(VUP_EINVAL, "P is NULL");
   if ((r = check_device())) return r;
-  return launched(vup::launch_ipsa(*mm, K, P, mean_hist, var, entropy, (hipStream_t)stream),
-                  "vup_ipsa");
+  const double* edges =
+      reinterpret_cast<const double*>(static_cast<const char*>(mm->ws) + mm->off_edges);
+  return launched(
+      vup::launch_ipsa_stats(edges, mm->B, K, P, mean_hist, var, entropy, (hipStream_t)stream),
+      "vup_ipsa");
 }
 
 int vup_ipsa_backward(const vup_mm* mm, const vup_dists* d, const float* P,

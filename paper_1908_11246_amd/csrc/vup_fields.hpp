@@ -1,5 +1,5 @@
-// Host-side launchers of the IPSA probability matrix, field-line, marginal and
-// point-evaluation kernels (k_fields.hip).
+// Host-side launchers of the column kernels (IPSA statistics, probability
+// matrix, field lines), the marginal and the point evaluation (k_fields.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,6 +12,9 @@ namespace vup {
 
 constexpr int kMaxLevels = VUP_MAX_LEVELS;
 
+// binned mean, variance and entropy of each column (vup_ipsa)
+hipError_t launch_ipsa_stats(const double* edges, int B, int64_t K, const float* P,
+                             double* mean_hist, double* var, double* entropy, hipStream_t s);
 hipError_t launch_eval_points(const vup_model& m, int ndim, int64_t n, const double* x,
                               int64_t ldx, double* y, hipStream_t s);
 hipError_t launch_ipsa_matrix(const double* edges, int B, int64_t K, const float* P,

@@ -49,8 +49,6 @@ hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, floa
                             hipStream_t s);
 hipError_t launch_moments(const vup_mm& mm, const vup_dists& d, const vup_model* model,
                           double* mean, double* var, double* delta2, hipStream_t s);
-hipError_t launch_ipsa(const vup_mm& mm, int64_t K, const float* P, double* mean_hist, double* var,
-                       double* entropy, hipStream_t s);
 hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            const double* mean_hist, const double* g_var, const double* g_ent,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);

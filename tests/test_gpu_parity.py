@@ -10,7 +10,9 @@ Bars (per distribution k unless noted):
   exact-f mean                               <= 1e-6 * (max f - min f)
   exact-f variance                           <= 1e-5 * Var + 1e-9 * range^2
   binned mean / variance                     same as exact-f bars
-  entropy                                    <= 1e-5 nats (FP32), 2u(1 + ln B) (BF16)
+  entropy                                    <= 1e-5 nats (FP32), 2u(1 + ln B) (BF16);
+                                             the kernel alone on the oracle's P:
+                                             2^-22 (H + 1) (FP32 logarithm per term)
   gradients (FP32 adjoint vs FP64 analytic)  rtol 2e-3 + atol 1e-5 max|g|
 The oracle always computes its own f, edges and bins; when a kernel is tested
 in isolation, the GPU is fed the oracle's inputs (never the other way round).
@@ -180,7 +182,9 @@ def test_grid64_all_outputs(vup, orc):
     m2, v2, h2 = orc.ipsa(P32.astype(np.float64), o["edges"])
     assert np.allclose(_cpu(mg), m2, rtol=0, atol=1e-13)
     assert np.allclose(_cpu(vg), v2, rtol=1e-12, atol=1e-15)
-    assert np.allclose(_cpu(hg), h2, rtol=1e-12, atol=1e-13)
+    # each entropy term takes the FP32 base-2 logarithm of the FP32 value
+    # (relative error below 2^-22), so |dH| <= 2^-22 (H + 1)
+    assert (np.abs(_cpu(hg) - h2) <= 2.0 ** -22 * (np.abs(h2) + 1.0)).all()
 
 
 RAGGED = [

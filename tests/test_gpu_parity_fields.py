@@ -224,7 +224,7 @@ def test_matrix_fields_edge_cases(vup, orc):
     assert Q0.shape == (0, 5) and l0.shape == (0,)
 
 
-@pytest.mark.parametrize("B", [1, 64, 4096])
+@pytest.mark.parametrize("B", [1, 64, 300, 2000, 4096])
 def test_matrix_fields_bin_count_extremes(vup, orc, B):
     """B = 4096 needs more than 64 KiB of LDS per workgroup (one wave)."""
     rng = np.random.Generator(np.random.PCG64(B))
