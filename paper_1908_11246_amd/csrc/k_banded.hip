@@ -9,11 +9,15 @@
 // over one axis, and the contraction over the other axis is a dense banded
 // matrix product that runs on the matrix cores (MFMA, FP32 in and out).
 //   k_axis_factors   A_d, Zd = sum_i A_d[i][m] (FP64), window bounds
-//   k_sep_scatter    T, one wave per (ix, 64 consecutive my), conflict-free
-//                    LDS accumulation (lane = my), cells in increasing iy,
-//                    same-bin runs summed in registers
-//   k_sep_mfma       one wave per (16 mx, 16 my, 16 bins): 16x16x4 FP32 MFMA
-//                    over the union of the 16 mx windows
+//   k_axis_prefix    G = prefix sums of A_y along y (FP64)
+//   k_sep_runs       T from the model matrix's runs of equal bin along y:
+//                    one G difference per run (rows up to 65534 cells)
+//   k_sep_scatter    T cell by cell (longer rows): one wave per (ix, 64 my),
+//                    conflict-free LDS accumulation (lane = my), same-bin
+//                    cells summed in registers
+//   k_sep_gemm       the banded contraction on the matrix cores, 16x16x4 FP32
+//                    MFMA, LDS-staged T blocks, one workgroup per 16 my x 4
+//                    bins x 256 mx
 #include <hip/hip_runtime.h>
 
 #include "vup_device.hpp"
@@ -34,29 +38,44 @@ struct SepArgs {
   int pitch;
   const uint16_t* binmap;
   // workspace
-  float* A[2];     // [n_d][M_d]
+  float* A[2];     // A_x: [n_x + 16][ldA0], zero past n_x and past M_x; A_y: [n_y][M_y]
+  int ldA0;        // M_x rounded up to a multiple of 256
   double* Zd[2];   // [M_d]
   int* win[2];     // [M_d][2]
   float* T;        // [n_x][B][M_y]
+  double* G;       // [n_y + 1][M_y] prefix sums of A_y along y (FP64)
+  const uint32_t* runs;  // run records of the model matrix (see vup.h)
+  const int* rowptr;
   float* P;        // [M_x*M_y][B]
   double* Z;       // [M_x*M_y] or null
+  int pvec;        // P rows can be written as float4 (B % 4 == 0, P 16-byte aligned)
 };
 
-// one block per (axis, m): column m of A_d, its sum and its window
+// one block per (axis, m): column m of A_d, its sum and its window. A_x also
+// gets its zero padding (16 rows past n_x, columns up to ldA0), so that the
+// contraction reads it without bounds checks.
 __global__ __launch_bounds__(256) void k_axis_factors(SepArgs a) {
   const int d = blockIdx.y;
   const int m = blockIdx.x;
-  if (m >= a.M[d]) return;
-  __shared__ double red[kWaves];
+  const int ld = d == 0 ? a.ldA0 : a.M[1];
   const int n = a.n[d];
+  const int rows = d == 0 ? n + 16 : n;
+  if (m >= ld) return;
+  float* col = a.A[d] + m;
+  if (m >= a.M[d]) {
+    for (int i = threadIdx.x; i < rows; i += 256) col[(long long)i * ld] = 0.0f;
+    return;
+  }
+  __shared__ double red[kWaves];
   const double mu = a.mu[d][m], sg = a.sigma[d][m];
   int jlo, jhi;
   const bool ok = axis_window(a.lo[d], a.hi[d], n, mu, sg, a.ns, jlo, jhi);
   double zp = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < rows; i += 256) {
     float v = 0.0f;
-    if (ok && i >= jlo && i <= jhi) v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg);
-    a.A[d][(long long)i * a.M[d] + m] = v;
+    if (ok && i < n && i >= jlo && i <= jhi)
+      v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg);
+    col[(long long)i * ld] = v;
     zp += (double)v;
   }
   const double Z = block_sum(zp, red);
@@ -130,21 +149,115 @@ __global__ __launch_bounds__(64) void k_sep_scatter(SepArgs a) {
   }
 }
 
-// C[mx][my] for 16 bins at once: A operand = A_x^T tile (16 mx x 4 ix),
-// B operand = T tile (4 ix x 16 my), 16x16x4 FP32 MFMA, K = the union of the
-// tile's mx windows. Lane layout of v_mfma_f32_16x16x4f32: A[i][k] from lane
-// i + 16k, B[k][j] from lane j + 16k, D[4q + r][j] in lane j + 16q, slot r.
-__global__ __launch_bounds__(64) void k_sep_mfma(SepArgs a) {
-  const int mx0 = blockIdx.x * 16;
-  const int my0 = blockIdx.y * 16;
-  const int b0 = blockIdx.z * 16;
-  const int lane = threadIdx.x;
-  const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
+// G[i][my] = sum_{iy < i} A_y[iy][my], i = 0..n_y, in FP64 from the FP32
+// factors. One workgroup per my: thread t sums a contiguous stretch of y in
+// order, an exclusive scan of the stretch totals (waves, then across waves in
+// LDS) gives each stretch its start, and the thread writes its prefix sums.
+__global__ __launch_bounds__(256) void k_axis_prefix(SepArgs a) {
+  __shared__ double wtot[kWaves];
+  const int my = blockIdx.x;
+  const int ny = a.n[1], My = a.M[1];
+  const int len = (ny + 255) / 256;
+  const int i0 = threadIdx.x * len, i1 = min(ny, i0 + len);
+  const float* Ay = a.A[1] + my;
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += (double)Ay[(long long)i * My];
+  const double incl = wave_scan(s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  double run = incl - s;
+  for (int w = 0; w < wave; ++w) run += wtot[w];
+  double* Gm = a.G + my;
+  for (int i = i0; i < i1; ++i) {
+    Gm[(long long)i * My] = run;
+    run += (double)Ay[(long long)i * My];
+  }
+  if (threadIdx.x == 255) Gm[(long long)ny * My] = run;
+}
+
+// T[ix][b][my] from the runs of equal bin along y: a run [s, e) of bin b adds
+// G[e][my] - G[s][my] (the run's factor mass, zero outside the window). One
+// workgroup per (row ix, 256 my), thread = my: the thread owns its T column,
+// zeroes it and adds the row's runs in order (deterministic, no atomics; the
+// row's T block stays in L2 between the zeroing and the adds). Runs go in
+// batches of 8 whose repeated bins are merged first (the bins are the same
+// for every thread), so the batch's reads of T are independent.
+constexpr int kRunBatch = 8;
+
+__global__ __launch_bounds__(256) void k_sep_runs(SepArgs a) {
+  const int ix = blockIdx.x;
+  const int my = blockIdx.y * 256 + threadIdx.x;
+  const int My = a.M[1], B = a.B;
+  if (my >= My) return;
+  float* Trow = a.T + (long long)ix * B * My + my;
+  for (int b = 0; b < B; ++b) Trow[(long long)b * My] = 0.0f;
+  const int r0 = a.rowptr[ix], r1 = a.rowptr[ix + 1];  // last record: terminator
+  const double* Gm = a.G + my;
+  const uint32_t none = 4u * (uint32_t)B;
+  for (int r = r0; r + 1 < r1; r += kRunBatch) {
+    uint32_t rec[kRunBatch + 1];
+    double g[kRunBatch + 1];
+#pragma unroll
+    for (int i = 0; i <= kRunBatch; ++i) {
+      const int ri = min(r + i, r1 - 1);
+      rec[i] = a.runs[ri];
+      g[i] = Gm[(long long)(rec[i] & 0xFFFFu) * My];
+    }
+    int bi[kRunBatch];
+    float d[kRunBatch];
+#pragma unroll
+    for (int i = 0; i < kRunBatch; ++i) {
+      const uint32_t code = rec[i] >> 16;
+      bi[i] = (r + i + 1 < r1 && code < none) ? (int)(code >> 2) : -1;
+      d[i] = (float)(g[i + 1] - g[i]);
+    }
+    // merge repeated bins of the batch into their first occurrence
+#pragma unroll
+    for (int i = 1; i < kRunBatch; ++i) {
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        if (bi[i] >= 0 && bi[j] == bi[i]) {
+          d[j] += d[i];
+          bi[i] = -1;
+        }
+      }
+    }
+    float t[kRunBatch];
+#pragma unroll
+    for (int i = 0; i < kRunBatch; ++i) t[i] = bi[i] >= 0 ? Trow[(long long)bi[i] * My] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < kRunBatch; ++i)
+      if (bi[i] >= 0) Trow[(long long)bi[i] * My] = t[i] + d[i];
+  }
+}
+
+// Banded contraction on the matrix cores: C_b[mx][my] = sum_ix A_x[ix][mx]
+// T[ix][b][my]. A workgroup (4 waves) owns 16 my x 4 bins and 256 mx (16 mx
+// tiles; wave w takes tiles w, w+4, w+8, w+12, so the tiles inside the band
+// of any ix chunk are spread over all four waves). The ix axis is walked in
+// chunks of 16 over the union of the tiles' windows; each chunk's T block
+// (16 ix x 4 bins x 16 my) is staged in LDS, double buffered, with a row
+// pitch of 80 floats so the 4 ix rows of one MFMA operand read hit distinct
+// banks; A_x comes from L2 straight into registers. A tile whose window misses
+// the chunk skips its MFMAs (A_x is zero there). 16x16x4 FP32 MFMA lane
+// layout: A[i][k] and B[k][j] from lane i + 16 k (resp. j + 16 k), D[4 q + r][j]
+// in lane j + 16 q, slot r.
+constexpr int kSepPitch = 80;
+
+__global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
+  __shared__ __attribute__((aligned(16))) float Ts[2][16 * kSepPitch];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  // union of the 16 mx windows
-  int lo = 0x7fffffff, hi = -1;
-  {
-    const int mx = mx0 + li;
+  const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
+  const int my0 = blockIdx.x * 16, b0 = blockIdx.y * 4, mxb = blockIdx.z * 256;
+  // windows of this wave's four tiles (uniform), and of the workgroup's 16
+  int tlo[4], thi[4];
+  int glo = 0x7fffffff, ghi = -1;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int mx = mxb + 16 * t + li;
+    int lo = 0x7fffffff, hi = -1;
     if (mx < Mx) {
       const int l = a.win[0][2 * mx], h = a.win[0][2 * mx + 1];
       if (h >= l) {
@@ -152,56 +265,132 @@ __global__ __launch_bounds__(64) void k_sep_mfma(SepArgs a) {
         hi = h;
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = 8; o > 0; o >>= 1) {
       lo = min(lo, __shfl_xor(lo, o, 64));
       hi = max(hi, __shfl_xor(hi, o, 64));
     }
-  }
-  f32x4 acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-  const int mxa = mx0 + li;  // A row handled by this lane
-  const int myb = my0 + li;  // B column handled by this lane
-  for (int k0 = lo; k0 <= hi; k0 += 4) {
-    const int ix = k0 + lk;
-    const bool inx = ix <= hi && ix < nx;
-    const float av = (inx && mxa < Mx) ? a.A[0][(long long)ix * Mx + mxa] : 0.0f;
-    const float* Tr = a.T + (long long)(inx ? ix : 0) * B * My;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int b = b0 + q;
-      const float bv = (inx && myb < My && b < B) ? Tr[(long long)b * My + myb] : 0.0f;
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    glo = min(glo, lo);
+    ghi = max(ghi, hi);
+    if ((t & 3) == w) {
+      tlo[t >> 2] = lo;
+      thi[t >> 2] = hi;
     }
   }
-  // D[4 lk + r][li] = C[mx0 + 4 lk + r][my0 + li]
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[j][q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  if (ghi >= glo) {
+    // staging map: thread -> (ix row, bin q, 4 my)
+    const int sr = threadIdx.x >> 4, sq = (threadIdx.x >> 2) & 3, sm = (threadIdx.x & 3) * 4;
+    const bool vec = (My & 3) == 0;
+    auto load_t = [&](int ix0) {
+      const int ix = ix0 + sr, b = b0 + sq, my = my0 + sm;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ix <= ghi && ix < nx && b < B) {
+        const float* src = a.T + ((long long)ix * B + b) * My + my;
+        if (vec && my + 3 < My) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (my < My) v.x = src[0];
+          if (my + 1 < My) v.y = src[1];
+          if (my + 2 < My) v.z = src[2];
+          if (my + 3 < My) v.w = src[3];
+        }
+      }
+      return v;
+    };
+    // A_x is zero-padded: rows up to n_x + 15 and columns up to ldA0 exist
+    const int ldA = a.ldA0;
+    const float* Abase = a.A[0] + mxb + 16 * w + li + (long long)lk * ldA;
+    auto load_a = [&](int ix0, float (&av)[4][4]) {
+      const float* p = Abase + (long long)ix0 * ldA;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[j][s] = p[64 * j + 4 * s * ldA];
+    };
+    const int c0 = glo >> 4, c1 = ghi >> 4;
+    float* Tst = &Ts[0][sr * kSepPitch + sq * 16 + sm];
+    *reinterpret_cast<float4*>(Tst) = load_t(16 * c0);
+    float av[4][4], an[4][4];
+    load_a(16 * c0, av);
+    __syncthreads();
+    // one chunk: MFMAs from LDS buffer `buf` and A operands `cur`, while the
+    // next chunk's T block and A operands are in flight
+    auto step = [&](int c, int buf, float (&cur)[4][4], float (&nxt)[4][4]) {
+      const int ix0 = 16 * c;
+      const bool more = c < c1;
+      float4 tv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (more) {
+        tv = load_t(ix0 + 16);
+        load_a(ix0 + 16, nxt);
+      }
+      const float* Tb = Ts[buf];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (tlo[j] <= ix0 + 15 && thi[j] >= ix0) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const float* row = Tb + (4 * s + lk) * kSepPitch + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[j][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[j][s], row[16 * q], acc[j][q],
+                                                                0, 0, 0);
+          }
+        }
+      }
+      if (more) *reinterpret_cast<float4*>(Tst + (buf ^ 1) * 16 * kSepPitch) = tv;
+      __syncthreads();
+    };
+    for (int c = c0; c <= c1; c += 2) {
+      step(c, 0, av, an);
+      if (c + 1 <= c1) step(c + 1, 1, an, av);
+    }
+  }
+  // D[4 lk + r][li] = C[tile mx + 4 lk + r][my0 + li]; normalise and store the
+  // four bins of each (mx, my)
   const int my = my0 + li;
+  if (my >= My) return;
+  const double zy = a.Zd[1][my];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int mx = mx0 + 4 * lk + r;
-    if (mx >= Mx || my >= My) continue;
-    const double zx = a.Zd[0][mx], zy = a.Zd[1][my];
-    const double z = zx * zy;
-    const long long k = (long long)mx * My + my;
+  for (int j = 0; j < 4; ++j) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int b = b0 + q;
-      if (b >= B) continue;
-      const double v = (double)acc[q][r];
-      a.P[k * B + b] = (z > 0.0) ? (float)(v / z) : (z == 0.0 ? 0.0f : __builtin_nanf(""));
+    for (int r = 0; r < 4; ++r) {
+      const int mx = mxb + 16 * (4 * j + w) + 4 * lk + r;
+      if (mx >= Mx) continue;
+      const double z = a.Zd[0][mx] * zy;
+      const long long k = (long long)mx * My + my;
+      float o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        o[q] = (z > 0.0) ? (float)((double)acc[j][q][r] / z) : (z == 0.0 ? 0.0f : __builtin_nanf(""));
+      float* dst = a.P + k * B + b0;
+      if (a.pvec) {
+        *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (b0 + q < B) dst[q] = o[q];
+      }
+      if (a.Z && blockIdx.y == 0) a.Z[k] = z;
     }
-    if (a.Z && blockIdx.z == 0) a.Z[k] = z;
   }
 }
 
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t o = 0;
-  o += al((size_t)g.n[0] * Mx * 4);
+  const size_t ld0 = ((size_t)Mx + 255) / 256 * 256;
+  o += al(((size_t)g.n[0] + 16) * ld0 * 4);
   o += al((size_t)g.n[1] * My * 4);
   o += al((size_t)Mx * 8) + al((size_t)My * 8);
   o += al((size_t)Mx * 8) + al((size_t)My * 8);
   o += al((size_t)g.n[0] * B * My * 4);
+  o += al((size_t)(g.n[1] + 1) * My * 8);
   return o;
 }
 
@@ -226,8 +415,9 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   a.pitch = mm.pitch;
   a.binmap = reinterpret_cast<const uint16_t*>(static_cast<const char*>(mm.ws) + mm.off_binmap);
   char* w = static_cast<char*>(ws);
+  a.ldA0 = (Mx + 255) / 256 * 256;
   a.A[0] = reinterpret_cast<float*>(w);
-  w += al((size_t)a.n[0] * Mx * 4);
+  w += al(((size_t)a.n[0] + 16) * a.ldA0 * 4);
   a.A[1] = reinterpret_cast<float*>(w);
   w += al((size_t)a.n[1] * My * 4);
   a.Zd[0] = reinterpret_cast<double*>(w);
@@ -239,23 +429,36 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   a.win[1] = reinterpret_cast<int*>(w);
   w += al((size_t)My * 8);
   a.T = reinterpret_cast<float*>(w);
+  w += al((size_t)a.n[0] * mm.B * My * 4);
+  a.G = reinterpret_cast<double*>(w);
+  a.runs = reinterpret_cast<const uint32_t*>(static_cast<const char*>(mm.ws) + mm.off_runs);
+  a.rowptr = reinterpret_cast<const int*>(static_cast<const char*>(mm.ws) + mm.off_rowptr);
   a.P = P;
   a.Z = Z;
-  const int Mmax = Mx > My ? Mx : My;
+  a.pvec = (mm.B % 4 == 0) && ((reinterpret_cast<uintptr_t>(P) & 15u) == 0);
+  const int Mmax = a.ldA0 > My ? a.ldA0 : My;
   hipLaunchKernelGGL(k_axis_factors, dim3(Mmax, 2), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)mm.B * 64 * 4;
-  if (lds > 65536) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sep_scatter),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (a.n[1] <= 65534) {
+    // run records hold 16-bit columns: T from the runs and the y prefix sums
+    hipLaunchKernelGGL(k_axis_prefix, dim3(My), dim3(256), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sep_runs, dim3(a.n[0], (My + 255) / 256), dim3(256), 0, s, a);
+  } else {
+    const size_t lds = (size_t)mm.B * 64 * 4;
+    if (lds > 65536) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sep_scatter),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sep_scatter, dim3(a.n[0], (My + 63) / 64), dim3(64), lds, s, a);
   }
-  hipLaunchKernelGGL(k_sep_scatter, dim3(a.n[0], (My + 63) / 64), dim3(64), lds, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sep_mfma, dim3((Mx + 15) / 16, (My + 15) / 16, (mm.B + 15) / 16), dim3(64),
-                     0, s, a);
+  hipLaunchKernelGGL(k_sep_gemm, dim3((My + 15) / 16, (mm.B + 3) / 4, (Mx + 255) / 256),
+                     dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
