@@ -17,7 +17,8 @@ precision, and forward + backward (propagate + IPSA + adjoint sweep), each
 with its error against the FP64 oracle on a seeded sample of distributions;
 the IPSA probability matrix, field lines and marginal over locations on the
 step's P with their HBM rooflines; the IPSA example of Sec. 5.3 at its five
-measurement uncertainties;
+measurement uncertainties; the banded MFMA form on a tensor-product family of
+the same grid size (shared sigma) with its MFMA roofline;
 the roofline of the longest sweep kernel of the step (and of the other one)
 from HIP events; and the CPU oracle's own throughput on a bounded sample.
 
@@ -183,6 +184,47 @@ def ipsa_views(vup, mm, P, mu, stream, reps):
                                              "frac": ach / HBM_PEAK_GBS,
                                              "algorithmic_bytes": nbytes, "kernel": kern}}
     return out
+
+
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def separable_run(vup, workloads, stream, reps):
+    """The banded MFMA form on a tensor-product family at full scale: 1024^2
+    grid on [-3,3]^2, sincos model, B = 256, 256 x 256 locations on the
+    midpoint subgrid with one shared sigma = 0.25 per axis (4-sigma windows).
+    Timed with HIP events around the whole separable call (factors, prefix
+    sums, the run scatter and the MFMA contraction); the MFMA roofline counts
+    the banded contraction's algorithmic flops 2 B M_y sum_mx |window_x(mx)|
+    against that whole time, so its fraction is a lower bound for the
+    contraction kernel."""
+    import torch
+    n, lo, hi, B, M, sg = (1024, 1024), (-3.0, -3.0), (3.0, 3.0), 256, 256, 0.25
+    g = vup.make_grid(n, lo, hi)
+    f = vup.eval_grid(g, "sincos2")
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, B), want_bin=False)
+    m = workloads.subgrid_midpoints(lo[0], hi[0], M)
+    s = np.full(M, sg)
+    P, Z, ws = vup.propagate_separable(mm, m, m, s, s, want_Z=False)
+    # windows per axis from the library, U = sum over the family of |wx| |wy|
+    mu1 = torch.zeros((M, 1, 2), dtype=torch.float64, device="cuda")
+    mu1[:, 0, 0] = torch.from_numpy(m).cuda()
+    mu1[:, 0, 1] = torch.from_numpy(m).cuda()
+    win = vup.windows(g, mu1, torch.full_like(mu1, sg))
+    wlen = (win[:, 0, :, 1] - win[:, 0, :, 0] + 1).clamp(min=0).to(torch.float64)
+    wx, wy = wlen[:, 0], wlen[:, 1]
+    U = float(wx.sum().item() * wy.sum().item())
+    flops = 2.0 * B * M * float(wx.sum().item())
+    ms = _time_on(stream, lambda: vup.propagate_separable(mm, m, m, s, s, ws=ws, want_Z=False),
+                  reps)
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"workload": "1024^2 grid on [-3,3]^2, sincos model, B=256, 256x256 locations on "
+                        "the midpoint subgrid, shared sigma=0.25, 4-sigma windows",
+            "ms": ms, "updates": U, "updates_per_s": U / (ms * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / MFMA_FP32_PEAK_TFLOPS,
+                         "algorithmic_flops": flops,
+                         "kernel": "vup_propagate_separable (k_sep_gemm + set-up, whole call)"}}
 
 
 def ipsa_example_runs(vup, workloads, stream, reps):
@@ -431,6 +473,10 @@ def main():
         result["variants"] = variants
         result["ipsa_views"] = ipsa_views(vup, mm, Ps["fp32"], mu, stream,
                                           max(3, args.steps // 2))
+        sep = separable_run(vup, workloads, stream, max(3, args.steps // 2))
+        variants["propagate_separable"] = sep
+        log(f"[bench] separable (banded MFMA) {sep['ms']:.3f} ms, "
+            f"{sep['updates_per_s']:.3e} updates/s, MFMA frac {sep['roofline']['frac']:.3f}")
         result["ipsa_example"] = ipsa_example_runs(vup, workloads, stream,
                                                    max(3, args.steps // 2))
         log("[bench] IPSA views " + ", ".join(

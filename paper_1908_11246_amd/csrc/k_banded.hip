@@ -10,8 +10,10 @@
 // matrix product that runs on the matrix cores (MFMA, FP32 in and out).
 //   k_axis_factors   A_d, Zd = sum_i A_d[i][m] (FP64), window bounds
 //   k_axis_prefix    G = prefix sums of A_y along y (FP64)
-//   k_sep_runs       T from the model matrix's runs of equal bin along y:
-//                    one G difference per run (rows up to 65534 cells)
+//   k_sep_runs_tiled T from the model matrix's runs of equal bin along y:
+//                    one G difference per run, 32-bin LDS tiles, T written
+//                    once (rows up to 4096 cells)
+//   k_sep_runs       the same with read-modify-writes of T (rows up to 65534)
 //   k_sep_scatter    T cell by cell (longer rows): one wave per (ix, 64 my),
 //                    conflict-free LDS accumulation (lane = my), same-bin
 //                    cells summed in registers
@@ -232,25 +234,149 @@ __global__ __launch_bounds__(256) void k_sep_runs(SepArgs a) {
   }
 }
 
-// Banded contraction on the matrix cores: C_b[mx][my] = sum_ix A_x[ix][mx]
-// T[ix][b][my]. A workgroup (4 waves) owns 16 my x 4 bins and 256 mx (16 mx
-// tiles; wave w takes tiles w, w+4, w+8, w+12, so the tiles inside the band
-// of any ix chunk are spread over all four waves). The ix axis is walked in
-// chunks of 16 over the union of the tiles' windows; each chunk's T block
-// (16 ix x 4 bins x 16 my) is staged in LDS, double buffered, with a row
-// pitch of 80 floats so the 4 ix rows of one MFMA operand read hit distinct
-// banks; A_x comes from L2 straight into registers. A tile whose window misses
-// the chunk skips its MFMAs (A_x is zero there). 16x16x4 FP32 MFMA lane
-// layout: A[i][k] and B[k][j] from lane i + 16 k (resp. j + 16 k), D[4 q + r][j]
-// in lane j + 16 q, slot r.
-constexpr int kSepPitch = 80;
+// T[ix][b][my] from the runs, written once: one workgroup per (row ix, 256 my),
+// thread = my. Wave 0 first sorts the row's runs by 32-bin tile into LDS
+// (stable: run order kept inside a tile, using ballots per distinct tile of
+// each 64-run chunk). Then, tile by tile, every thread accumulates its
+// column of the tile's 32 bins in LDS (slots owned by the thread, runs in row
+// order, batches of 8 runs whose G loads are issued together) and writes the
+// 32 T entries once. Used for rows of at most kRunRowMax cells.
+constexpr int kTileBins = 32;
+constexpr int kRunRowMax = 4096;
 
-__global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
-  __shared__ __attribute__((aligned(16))) float Ts[2][16 * kSepPitch];
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+}
+
+__global__ __launch_bounds__(256) void k_sep_runs_tiled(SepArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  const int B = a.B, My = a.M[1];
+  const int ntiles = (B + kTileBins - 1) / kTileBins;
+  float* acc = smem;                                          // [kTileBins][256]
+  int* start = reinterpret_cast<int*>(acc + kTileBins * 256);  // [ntiles + 1]
+  int* cur = start + (ntiles + 1);                             // [ntiles]
+  uint32_t* lse = reinterpret_cast<uint32_t*>(cur + ntiles);   // [runs] s | e << 16
+  uint16_t* lbin = reinterpret_cast<uint16_t*>(lse + (a.n[1] + 1));  // [runs]
+  const int ix = blockIdx.x, tid = threadIdx.x;
+  const int my = blockIdx.y * 256 + tid;
+  const int r0 = a.rowptr[ix], r1 = a.rowptr[ix + 1];
+  const int R = r1 - 1 - r0;  // runs of the row (the last record is the terminator)
+  const uint32_t none = 4u * (uint32_t)B;
+  for (int t = tid; t <= ntiles; t += 256) start[t] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    // pass 1: runs per tile; pass 2: stable placement
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        if (lane == 0) {
+          int run = 0;
+          for (int t = 0; t < ntiles; ++t) {
+            const int c = start[t + 1];
+            start[t] = run;
+            cur[t] = run;
+            run += c;
+          }
+          start[ntiles] = run;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      for (int c0 = 0; c0 < R; c0 += 64) {
+        const int r = c0 + lane;
+        uint32_t rec = 0, nxt = 0;
+        int tile = -1;
+        if (r < R) {
+          rec = a.runs[r0 + r];
+          nxt = a.runs[r0 + r + 1];
+          if ((rec >> 16) < none) tile = (int)((rec >> 16) >> 2) / kTileBins;
+        }
+        unsigned long long todo = __ballot(tile >= 0);
+        while (todo) {
+          const int first = __ffsll((long long)todo) - 1;
+          const int t = __shfl(tile, first, 64);
+          const unsigned long long m = __ballot(tile == t);
+          if (pass == 0) {
+            if (lane == 0) start[t + 1] += __popcll(m);
+          } else {
+            const int base = cur[t];
+            if (tile == t) {
+              const int pos = base + lanes_below(m);
+              lse[pos] = (rec & 0xFFFFu) | ((nxt & 0xFFFFu) << 16);
+              lbin[pos] = (uint16_t)((rec >> 16) >> 2);
+            }
+            if (lane == 0) cur[t] = base + __popcll(m);
+          }
+          todo &= ~m;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (my >= My) return;  // no barrier below
+  const double* Gm = a.G + my;
+  float* Tcol = a.T + (long long)ix * B * My + my;
+  float* mine = acc + tid;
+  for (int t = 0; t < ntiles; ++t) {
+    const int bt = t * kTileBins;
+#pragma unroll
+    for (int q = 0; q < kTileBins; ++q) mine[q * 256] = 0.0f;
+    const int st = start[t], en = start[t + 1];
+    for (int k = st; k < en; k += 8) {
+      double g0[8], g1[8];
+      int bb[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = min(k + i, en - 1);
+        const uint32_t se = lse[kk];
+        bb[i] = k + i < en ? (int)lbin[kk] - bt : -1;
+        g0[i] = Gm[(long long)(se & 0xFFFFu) * My];
+        g1[i] = Gm[(long long)(se >> 16) * My];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (bb[i] >= 0) mine[bb[i] * 256] += (float)(g1[i] - g0[i]);
+    }
+    const int nq = min(kTileBins, B - bt);
+    for (int q = 0; q < nq; ++q) Tcol[(long long)(bt + q) * My] = mine[q * 256];
+  }
+}
+
+static size_t runs_tiled_lds(int B, int ny) {
+  const int ntiles = (B + kTileBins - 1) / kTileBins;
+  return (size_t)kTileBins * 256 * 4 + (size_t)(2 * ntiles + 1) * 4 + (size_t)(ny + 1) * 4 +
+         (size_t)(ny + 1) * 2;
+}
+
+// Banded contraction on the matrix cores: C_b[mx][my] = sum_ix A_x[ix][mx]
+// T[ix][b][my]. A workgroup (4 waves) owns 16 my x NB bins and 256 mx (16 mx
+// tiles; wave w takes tiles w, w+4, w+8, w+12, so the tiles inside the band
+// of any ix chunk are spread over the four waves). The ix axis is walked in
+// chunks of 16 over the union of the tiles' windows; each chunk's T block
+// (16 ix x NB bins x 16 my) is staged in LDS, double buffered, with a row
+// pitch of 16 NB + 16 floats so the 4 ix rows of one MFMA operand read hit
+// distinct banks; A_x comes from L2 straight into registers, only for tiles
+// whose window meets the chunk (the others skip their MFMAs: A_x is zero
+// there). 16x16x4 FP32 MFMA lane layout: A[i][k] and B[k][j] from lane
+// i + 16 k (resp. j + 16 k), D[4 q + r][j] in lane j + 16 q, slot r.
+#ifndef VUP_SEP_BINS
+#define VUP_SEP_BINS 4
+#endif
+constexpr int kSepBins = VUP_SEP_BINS;  // bins per workgroup of the contraction
+
+template <int NB>
+__global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
+  constexpr int kPitch = 16 * NB + 16;
+  constexpr int kTile = 16 * kPitch;
+  __shared__ __attribute__((aligned(16))) float Ts[2 * kTile];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
-  const int my0 = blockIdx.x * 16, b0 = blockIdx.y * 4, mxb = blockIdx.z * 256;
+  const int my0 = blockIdx.x * 16, b0 = blockIdx.y * NB, mxb = blockIdx.z * 256;
   // windows of this wave's four tiles (uniform), and of the workgroup's 16
   int tlo[4], thi[4];
   int glo = 0x7fffffff, ghi = -1;
@@ -278,44 +404,58 @@ __global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
       thi[t >> 2] = hi;
     }
   }
-  f32x4 acc[4][4];
+  f32x4 acc[4][NB];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[j][q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int q = 0; q < NB; ++q) acc[j][q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
   if (ghi >= glo) {
-    // staging map: thread -> (ix row, bin q, 4 my)
-    const int sr = threadIdx.x >> 4, sq = (threadIdx.x >> 2) & 3, sm = (threadIdx.x & 3) * 4;
     const bool vec = (My & 3) == 0;
-    auto load_t = [&](int ix0) {
-      const int ix = ix0 + sr, b = b0 + sq, my = my0 + sm;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ix <= ghi && ix < nx && b < B) {
-        const float* src = a.T + ((long long)ix * B + b) * My + my;
-        if (vec && my + 3 < My) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else {
-          if (my < My) v.x = src[0];
-          if (my + 1 < My) v.y = src[1];
-          if (my + 2 < My) v.z = src[2];
-          if (my + 3 < My) v.w = src[3];
+    // staging: element e = threadIdx.x + 256 u -> (ix row, bin q, 4 my)
+    auto load_t = [&](int ix0, float4 (&tv)[NB / 4]) {
+#pragma unroll
+      for (int u = 0; u < NB / 4; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int ix = ix0 + e / (4 * NB), b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ix <= ghi && ix < nx && b < B) {
+          const float* src = a.T + ((long long)ix * B + b) * My + my;
+          if (vec && my + 3 < My) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else {
+            if (my < My) v.x = src[0];
+            if (my + 1 < My) v.y = src[1];
+            if (my + 2 < My) v.z = src[2];
+            if (my + 3 < My) v.w = src[3];
+          }
         }
+        tv[u] = v;
       }
-      return v;
+    };
+    auto store_t = [&](int buf, const float4 (&tv)[NB / 4]) {
+#pragma unroll
+      for (int u = 0; u < NB / 4; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        *reinterpret_cast<float4*>(&Ts[buf * kTile + (e / (4 * NB)) * kPitch +
+                                       ((e >> 2) % NB) * 16 + 4 * (e & 3)]) = tv[u];
+      }
     };
     // A_x is zero-padded: rows up to n_x + 15 and columns up to ldA0 exist
     const int ldA = a.ldA0;
     const float* Abase = a.A[0] + mxb + 16 * w + li + (long long)lk * ldA;
+    auto live = [&](int j, int ix0) { return tlo[j] <= ix0 + 15 && thi[j] >= ix0; };
     auto load_a = [&](int ix0, float (&av)[4][4]) {
       const float* p = Abase + (long long)ix0 * ldA;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
+        if (live(j, ix0))
 #pragma unroll
-        for (int s = 0; s < 4; ++s) av[j][s] = p[64 * j + 4 * s * ldA];
+          for (int s = 0; s < 4; ++s) av[j][s] = p[64 * j + 4 * s * ldA];
     };
     const int c0 = glo >> 4, c1 = ghi >> 4;
-    float* Tst = &Ts[0][sr * kSepPitch + sq * 16 + sm];
-    *reinterpret_cast<float4*>(Tst) = load_t(16 * c0);
+    float4 tv[NB / 4];
+    load_t(16 * c0, tv);
+    store_t(0, tv);
     float av[4][4], an[4][4];
     load_a(16 * c0, av);
     __syncthreads();
@@ -324,26 +464,25 @@ __global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
     auto step = [&](int c, int buf, float (&cur)[4][4], float (&nxt)[4][4]) {
       const int ix0 = 16 * c;
       const bool more = c < c1;
-      float4 tv = make_float4(0.f, 0.f, 0.f, 0.f);
       if (more) {
-        tv = load_t(ix0 + 16);
+        load_t(ix0 + 16, tv);
         load_a(ix0 + 16, nxt);
       }
-      const float* Tb = Ts[buf];
+      const float* Tb = Ts + buf * kTile;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (tlo[j] <= ix0 + 15 && thi[j] >= ix0) {
+        if (live(j, ix0)) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const float* row = Tb + (4 * s + lk) * kSepPitch + li;
+            const float* row = Tb + (4 * s + lk) * kPitch + li;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < NB; ++q)
               acc[j][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[j][s], row[16 * q], acc[j][q],
                                                                 0, 0, 0);
           }
         }
       }
-      if (more) *reinterpret_cast<float4*>(Tst + (buf ^ 1) * 16 * kSepPitch) = tv;
+      if (more) store_t(buf ^ 1, tv);
       __syncthreads();
     };
     for (int c = c0; c <= c1; c += 2) {
@@ -352,7 +491,7 @@ __global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
     }
   }
   // D[4 lk + r][li] = C[tile mx + 4 lk + r][my0 + li]; normalise and store the
-  // four bins of each (mx, my)
+  // NB bins of each (mx, my)
   const int my = my0 + li;
   if (my >= My) return;
   const double zy = a.Zd[1][my];
@@ -363,18 +502,23 @@ __global__ __launch_bounds__(256) void k_sep_gemm(SepArgs a) {
       const int mx = mxb + 16 * (4 * j + w) + 4 * lk + r;
       if (mx >= Mx) continue;
       const double z = a.Zd[0][mx] * zy;
+      const double rz = 1.0 / z;
       const long long k = (long long)mx * My + my;
-      float o[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        o[q] = (z > 0.0) ? (float)((double)acc[j][q][r] / z) : (z == 0.0 ? 0.0f : __builtin_nanf(""));
       float* dst = a.P + k * B + b0;
-      if (a.pvec) {
-        *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
-      } else {
+#pragma unroll
+      for (int q4 = 0; q4 < NB / 4; ++q4) {
+        float o[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (b0 + q < B) dst[q] = o[q];
+          o[q] = (z > 0.0) ? (float)((double)acc[j][4 * q4 + q][r] * rz)
+                           : (z == 0.0 ? 0.0f : __builtin_nanf(""));
+        if (a.pvec && b0 + 4 * q4 + 3 < B) {
+          *reinterpret_cast<float4*>(dst + 4 * q4) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (b0 + 4 * q4 + q < B) dst[4 * q4 + q] = o[q];
+        }
       }
       if (a.Z && blockIdx.y == 0) a.Z[k] = z;
     }
@@ -445,7 +589,17 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
     hipLaunchKernelGGL(k_axis_prefix, dim3(My), dim3(256), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sep_runs, dim3(a.n[0], (My + 255) / 256), dim3(256), 0, s, a);
+    if (a.n[1] <= kRunRowMax) {
+      const size_t lds = runs_tiled_lds(mm.B, a.n[1]);
+      if (lds > 65536) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sep_runs_tiled),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_sep_runs_tiled, dim3(a.n[0], (My + 255) / 256), dim3(256), lds, s, a);
+    } else {
+      hipLaunchKernelGGL(k_sep_runs, dim3(a.n[0], (My + 255) / 256), dim3(256), 0, s, a);
+    }
   } else {
     const size_t lds = (size_t)mm.B * 64 * 4;
     if (lds > 65536) {
@@ -457,7 +611,8 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sep_gemm, dim3((My + 15) / 16, (mm.B + 3) / 4, (Mx + 255) / 256),
+  constexpr int NB = kSepBins;
+  hipLaunchKernelGGL(k_sep_gemm<NB>, dim3((My + 15) / 16, (mm.B + NB - 1) / NB, (Mx + 255) / 256),
                      dim3(256), 0, s, a);
   return hipGetLastError();
 }

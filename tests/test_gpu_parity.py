@@ -459,6 +459,30 @@ def test_separable_grid64(vup, orc):
     assert d <= 2e-5
 
 
+SEP_PATHS = [
+    # (label, n, Mx, My, B): rows over 4096 cells (T by read-modify-write),
+    # rows over 65534 cells (T cell by cell), more than 256 x locations
+    ("long_rows", (6, 5000), 5, 300, 37),
+    ("very_long_rows", (2, 65536), 2, 3, 20),
+    ("wide_x", (300, 40), 300, 5, 64),
+]
+
+
+@pytest.mark.parametrize("case", SEP_PATHS, ids=[c[0] for c in SEP_PATHS])
+def test_separable_paths(vup, orc, case):
+    label, n, Mx, My, B = case
+    lo, hi = (-2.0, -3.0), (2.5, 3.0)
+    rng = np.random.default_rng(sum(n) + Mx)
+    mux = rng.uniform(lo[0], hi[0], Mx)
+    muy = rng.uniform(lo[1], hi[1], My)
+    sgx = rng.uniform(0.1, 0.8, Mx)
+    sgy = rng.uniform(0.01, 0.5, My)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "sincos2", B, mux, muy, sgx, sgy,
+                                           label)
+    _check_P(Pg, Po, 2e-5, f"P separable {label}")
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
 def test_separable_ragged_and_edge_cases(vup, orc):
     rng = np.random.default_rng(50)
     n, lo, hi = (61, 75), (-3.0, -2.0), (3.0, 2.5)
