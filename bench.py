@@ -64,16 +64,24 @@ def traffic_bytes(kernel):
     with open(path) as fh:
         rec = json.load(fh)
     entry = rec.get("kernels", {}).get(kernel)
-    if entry is None or entry.get("source_sha256") != source_sha256():
+    if entry is None or entry.get("source_sha256") != source_sha256(kernel):
         return None
     return entry["hbm_bytes_per_launch"]
 
 
-def source_sha256():
-    """Digest of the kernel sources the counters depend on."""
+# sources each measured kernel is built from (its launch and its input layout)
+KERNEL_SOURCES = {
+    "propagate": ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"),
+    "moments": ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"),
+    "ipsa": ("k_fields.hip", "vup_fields.hpp", "vup_device.hpp"),
+}
+
+
+def source_sha256(kernel="propagate"):
+    """Digest of the kernel sources a kernel's counters depend on."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1908_11246_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -89,8 +97,9 @@ def kernels_once():
     sigma = torch.from_numpy(wl.sigma).cuda()
     f = vup.eval_grid(g, wl.model, wl.theta)
     mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
-    vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
+    P, _ = vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
     vup.moments(mm, mu, sigma)
+    vup.ipsa(mm, P)
     torch.cuda.synchronize()
     src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -257,7 +266,7 @@ def ipsa_example_runs(vup, workloads, stream, reps):
                          "sweep_form": mm.sweep}
     return res
 # kernel-name fragments of the sweep kernels in rocprofv3 output
-TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments"}
+TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments", "ipsa": "k_ipsa<"}
 
 
 def _counter_rows(path):
@@ -270,8 +279,7 @@ def summarize_traffic(fetch_csv, write_csv):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the sweep kernels, scaled
     by the ratio of the known byte count of the calibration copy (the last
     dispatch) to what the same counter reports for it."""
-    out = {"workload": "grid1024", "calibration_bytes": CALIB_BYTES,
-           "source_sha256": source_sha256(), "kernels": {}}
+    out = {"workload": "grid1024", "calibration_bytes": CALIB_BYTES, "kernels": {}}
     per = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = [r for r in _counter_rows(path) if r["Counter_Name"] == counter]
@@ -293,7 +301,7 @@ def summarize_traffic(fetch_csv, write_csv):
         if "FETCH_SIZE" in v and "WRITE_SIZE" in v:
             out["kernels"][key] = {"fetch_bytes": v["FETCH_SIZE"], "write_bytes": v["WRITE_SIZE"],
                                    "hbm_bytes_per_launch": v["FETCH_SIZE"] + v["WRITE_SIZE"],
-                                   "source_sha256": out["source_sha256"]}
+                                   "source_sha256": source_sha256(key)}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", "traffic_grid1024.json"), "w") as fh:
         json.dump(out, fh, indent=1)
@@ -410,6 +418,14 @@ def main():
                         "unit": "TOP/s", "frac": ach / VALU_PEAK_OPS,
                         "traffic": traffic_bytes(k), "kernel": KERNELS[k],
                         "kernel_ms": part_ms[k], "ops_per_update": OPS_PER_UPDATE[k]}
+    # the IPSA column statistics stream P once: HBM bound, K*B*4 bytes read
+    # plus mean, variance and entropy (3*K*8 bytes) written
+    ipsa_bytes = wl.K * wl.B * 4 + 3 * wl.K * 8
+    ach = ipsa_bytes / (part_ms["ipsa"] * 1e-3) / 1e9
+    rooflines["ipsa"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic_bytes("ipsa"),
+                         "kernel": "k_ipsa", "kernel_ms": part_ms["ipsa"],
+                         "algorithmic_bytes": ipsa_bytes}
     dominant = max(("propagate", "moments"), key=lambda k: part_ms[k])
 
     result = {

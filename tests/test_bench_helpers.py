@@ -46,7 +46,8 @@ def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
                                        (3, "__amd_rocclr_copyBuffer", calib_kib)])
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "paper_1908_11246_amd" / "csrc")
-    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"):
+    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp",
+                 "k_fields.hip", "vup_fields.hpp"):
         (tmp_path / "paper_1908_11246_amd" / "csrc" / name).write_text("// " + name)
     bench.summarize_traffic(str(fetch), str(write))
     rec = json.loads((tmp_path / "profiles" / "traffic_grid1024.json").read_text())
@@ -56,6 +57,8 @@ def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     assert p["fetch_bytes"] == pytest.approx(2000.0 * 1024 * 2.0)
     assert p["write_bytes"] == pytest.approx(300.0 * 1024)
     assert bench.traffic_bytes("moments") == pytest.approx(500.0 * 1024 * 2.0 + 7.0 * 1024)
-    # a change of the kernel sources voids the figure
+    # a change of a kernel source voids the figures of the kernels built from it
+    assert bench.traffic_bytes("propagate") is not None
     (tmp_path / "paper_1908_11246_amd" / "csrc" / "k_sweep.hip").write_text("// changed")
     assert bench.traffic_bytes("moments") is None
+    assert bench.traffic_bytes("propagate") is None
