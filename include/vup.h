@@ -366,6 +366,30 @@ int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, voi
                     size_t ws_bytes, double* out, void* stream);
 
 /* --------------------------------------------------------------------------
+ * vup_posterior - Bayes inversion over the model matrix (Sec. 3, the Bayes
+ * theorem paragraph and its footnote): columns of the "inverted model matrix"
+ * for the selected distributions k = sel[t],
+ *   post[t][i] = p_k(x_i) / P[k][bin(i)]   (0 for a cell without a bin, or
+ *                                            whose bin has no mass),
+ * the posterior over input cells given that the output fell in that cell's
+ * bin, relative to the forward propagation that produced P and Z. Applied
+ * after the model matrix it returns the input pdf (the footnote's identity:
+ * sum_b post[i] P[k][b] [bin(i) = b] = p_k(x_i)), and over the cells of one
+ * bin it sums to 1. p_k is the truncated, normalised mixture the propagation
+ * uses (FP32 per-axis factors, normalised by Z in FP64).
+ * Optional per-bin posterior means E[x_d | y in b, k] = sum over the bin's
+ * cells of post x_d (FP64, summed in the compressed-by-bin order).
+ *   d: the distributions given to vup_propagate; sel: dev int64 [n_sel]
+ *   (an index outside [0, K) gives a NaN row); P: dev FP32 [K][B] and Z: dev
+ *   FP64 [K][ncomp] from vup_propagate (VUP_FP32); post: dev FP32
+ *   [n_sel][N]; mean: dev FP64 [n_sel][B][ndim] or NULL.
+ * Invalid parameters or non-finite Z or evidence give NaN.
+ * EINVAL: bad descriptor or dists, NULL arrays; EUNSUPPORTED: n_sel > 65535.
+ * ------------------------------------------------------------------------ */
+int vup_posterior(const vup_mm* mm, const vup_dists* d, int64_t n_sel, const int64_t* sel,
+                  const float* P, const double* Z, float* post, double* mean, void* stream);
+
+/* --------------------------------------------------------------------------
  * vup_counters - reads and clears the device-side event counters of a model
  * matrix's workspace. Synchronises `stream`.
  *   out (host int64[4]): [0] cells with no bin (set by vup_bin),

@@ -115,6 +115,8 @@ def _load():
                                     ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]
     lib.vup_ipsa_fields.argtypes = [_P(VupMM), ctypes.c_int64, _vp, _vp, ctypes.c_int32,
                                     _P(ctypes.c_double), _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.vup_posterior.argtypes = [_P(VupMM), _P(VupDists), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp,
+                                  _vp]
     lib.vup_marginal_workspace_bytes.restype = ctypes.c_size_t
     lib.vup_marginal_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.vup_marginalize.argtypes = [ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t,
@@ -455,6 +457,22 @@ def marginalize(A: torch.Tensor, rho: Optional[torch.Tensor] = None,
     _check(_load().vup_marginalize(K, n, _ptr(A), _ptr(r), _ptr(ws), ws.numel(), _ptr(out),
                                    _vp(_stream())))
     return out
+
+
+def posterior(mm: ModelMatrix, mu, sigma, weight, sel, P: torch.Tensor, Z: torch.Tensor,
+              n_sigma: float = 4.0, want_mean: bool = True):
+    """Bayes inversion (Sec. 3): post[t][i] = p_k(x_i) / P[k][bin(i)] for k = sel[t]
+    (FP32 [n_sel][N]) and, optionally, per-bin posterior means [n_sel][B][ndim]."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
+    s = torch.as_tensor(sel).to(device=mm.device, dtype=torch.int64).contiguous()
+    n_sel = s.numel()
+    post = torch.empty((n_sel, int(mm.mm.N)), dtype=torch.float32, device=mm.device)
+    mean = (torch.empty((n_sel, mm.B, mm.grid.ndim), dtype=torch.float64, device=mm.device)
+            if want_mean else None)
+    d = _dists(mu, sigma, w, n_sigma)
+    _check(_load().vup_posterior(ctypes.byref(mm.mm), ctypes.byref(d), n_sel, _ptr(s), _ptr(P),
+                                 _ptr(Z.contiguous()), _ptr(post), _ptr(mean), _vp(_stream())))
+    return post, mean
 
 
 def ipsa_backward(mm: ModelMatrix, mu, sigma, weight, P, mean_hist, g_var=None, g_ent=None,

@@ -10,6 +10,7 @@
 
 #include "../../include/vup.h"
 #include "vup_fields.hpp"
+#include "vup_inverse.hpp"
 #include "vup_internal.hpp"
 
 namespace {
@@ -384,6 +385,20 @@ int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, voi
   if (r) return r;
   return launched(vup::launch_marginalize(K, n, A, rho, ws, out, (hipStream_t)stream),
                   "vup_marginalize");
+}
+
+int vup_posterior(const vup_mm* mm, const vup_dists* d, int64_t n_sel, const int64_t* sel,
+                  const float* P, const double* Z, float* post, double* mean, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if ((r = check_dists(d, mm->grid.ndim))) return r;
+  if (n_sel < 0) return fail(VUP_EINVAL, "n_sel < 0");
+  if (n_sel > 65535) return fail(VUP_EUNSUPPORTED, "n_sel %lld > 65535", (long long)n_sel);
+  if (n_sel > 0 && (!sel || !P || !Z || !post))
+    return fail(VUP_EINVAL, "sel, P, Z or post is NULL");
+  if ((r = check_device())) return r;
+  return launched(vup::launch_posterior(*mm, *d, n_sel, sel, P, Z, post, mean, (hipStream_t)stream),
+                  "vup_posterior");
 }
 
 int vup_counters(const vup_mm* mm, void* stream, int64_t* out) {
