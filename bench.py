@@ -143,10 +143,11 @@ def _c_call(vup, name, *args):
     return call
 
 
-def ipsa_views(vup, mm, P, mu, stream, reps):
+def ipsa_views(vup, mm, P, mu, sigma, stream, reps):
     """The IPSA probability matrix, field lines and marginal on the step's P
-    (Sec. 5.2): time and HBM roofline of each (algorithmic bytes per launch:
-    what the kernel must read and write once)."""
+    (Sec. 5.2), and the Bayes inversion (Sec. 3) for 64 of the distributions:
+    time and HBM roofline of each (algorithmic bytes per launch: what the
+    kernel must read and write once)."""
     import torch
     K, B = P.shape
     e = mm.edges.cpu().numpy()
@@ -168,6 +169,8 @@ def ipsa_views(vup, mm, P, mu, stream, reps):
     model = vup.make_model("sincos2")
     mu0 = mu[:, 0, :]
     lvc = (ctypes.c_double * len(lv))(*lv)
+    P2 = torch.empty_like(P)
+    dists = vup._dists(mu, sigma, None, 4.0)
     cases = {
         "eval_points": (_c_call(vup, "vup_eval_points", ctypes.byref(model), 2, K, v(mu0),
                                 mu0.stride(0), v(y2), sp), K * (16 + 8), "k_eval_points"),
@@ -183,6 +186,19 @@ def ipsa_views(vup, mm, P, mu, stream, reps):
                           K * n_dy * 4 + 2 * chunks_bytes + n_dy * 8,
                           "k_marg_partial + k_marg_combine"),
     }
+    # Bayes inversion (Sec. 3) for 64 distributions spread over K: 64 x N FP32
+    # posteriors plus per-bin posterior means
+    n_sel = 64
+    sel = torch.arange(0, K, K // n_sel, dtype=torch.int64, device=P.device)[:n_sel].contiguous()
+    N = int(mm.mm.N)
+    post = torch.empty((n_sel, N), dtype=torch.float32, device=P.device)
+    pmean = torch.empty((n_sel, B, 2), dtype=torch.float64, device=P.device)
+    Zc = torch.empty((K, 1), dtype=torch.float64, device=P.device)
+    vup.lib().vup_propagate(mref, ctypes.byref(dists), 0, v(P2), v(Zc), sp)
+    cases["posterior_64"] = (_c_call(vup, "vup_posterior", mref, ctypes.byref(dists), n_sel, v(sel),
+                                     v(P2), v(Zc), v(post), v(pmean), sp),
+                             n_sel * N * 4 + N * 2 + n_sel * B * 2 * 8,
+                             "k_posterior + k_posterior_mean")
     out = {"n_dy": n_dy, "levels": list(lv), "timing": "HIP events around 20 back-to-back "
            "C-ABI calls on the launch stream, mean of reps"}
     for name, (fn, nbytes, kern) in cases.items():
@@ -487,7 +503,7 @@ def main():
         variants["fwd_bwd_fp32"] = {"updates_per_s": U / t, "ms": 1e3 * t,
                                     "note": "U counted once; forward and adjoint each sweep U"}
         result["variants"] = variants
-        result["ipsa_views"] = ipsa_views(vup, mm, Ps["fp32"], mu, stream,
+        result["ipsa_views"] = ipsa_views(vup, mm, Ps["fp32"], mu, sigma, stream,
                                           max(3, args.steps // 2))
         sep = separable_run(vup, workloads, stream, max(3, args.steps // 2))
         variants["propagate_separable"] = sep

@@ -225,3 +225,25 @@ def test_field_line_arguments(lib):
     need = lib.vup_marginal_workspace_bytes(100, 9)
     assert lib.vup_marginalize(100, 9, dummy, None, dummy, need - 1, dummy, None) == EWORKSPACE
     assert lib.vup_marginalize(100, 9, dummy, None, None, need, dummy, None) == EWORKSPACE
+
+
+def test_posterior_arguments(lib):
+    mm = _fake_mm(lib)
+    dummy = ctypes.c_void_p(0x1000)
+    d = vup.VupDists()
+    d.K, d.ncomp, d.ndim, d.n_sigma = 4, 1, 2, 4.0
+    d.mu, d.sigma = 0x1000, 0x2000
+    post = lib.vup_posterior
+    assert post(ctypes.byref(mm), ctypes.byref(d), -1, dummy, dummy, dummy, dummy, None,
+                None) == EINVAL
+    assert post(ctypes.byref(mm), ctypes.byref(d), 70000, dummy, dummy, dummy, dummy, None,
+                None) == EUNSUPPORTED
+    for i in range(4):
+        args = [dummy, dummy, dummy, dummy]
+        args[i] = None
+        assert post(ctypes.byref(mm), ctypes.byref(d), 3, *args, None, None) == EINVAL
+    d.ndim = 3
+    assert post(ctypes.byref(mm), ctypes.byref(d), 3, dummy, dummy, dummy, dummy, None,
+                None) == EINVAL
+    assert post(ctypes.byref(vup.VupMM()), ctypes.byref(d), 3, dummy, dummy, dummy, dummy, None,
+                None) == EWORKSPACE
