@@ -17,8 +17,10 @@ precision, and forward + backward (propagate + IPSA + adjoint sweep), each
 with its error against the FP64 oracle on a seeded sample of distributions;
 the IPSA probability matrix, field lines and marginal over locations on the
 step's P with their HBM rooflines; the IPSA example of Sec. 5.3 at its five
-measurement uncertainties; the banded MFMA form on a tensor-product family of
-the same grid size (shared sigma) with its MFMA roofline;
+measurement uncertainties; the timing experiment of Sec. 4.1 (the whole
+pipeline for L = 1 ... 1000 pdfs on 10^6 cells, wall clock); the Bayes
+inversion of 64 distributions; the banded MFMA form on a tensor-product
+family of the same grid size (shared sigma) with its MFMA roofline;
 the roofline of the longest sweep kernel of the step (and of the other one)
 from HIP events; and the CPU oracle's own throughput on a bounded sample.
 
@@ -250,6 +252,43 @@ def separable_run(vup, workloads, stream, reps):
                          "unit": "TFLOP/s", "frac": ach / MFMA_FP32_PEAK_TFLOPS,
                          "algorithmic_flops": flops,
                          "kernel": "vup_propagate_separable (k_sep_gemm + set-up, whole call)"}}
+
+
+def timing_study_runs(vup, workloads, reps):
+    """The timing experiment of Sec. 4.1 as a synthetic run: for L pdfs on
+    N = 10^6 cells, the whole VUP pipeline (model evaluation, bin edges, model
+    matrix with its sweep-form choice, propagation of all L pdfs), wall clock
+    with the device synchronised on both sides, best of `reps`. The paper's
+    figures (other hardware, context only) are L = 1: 0.43 s and L = 1000:
+    4.39 s on a Quadro P4000, excluding GPU initialisation."""
+    import torch
+    res = {}
+    for L in (1, 10, 100, 1000):
+        wl = workloads.timing_study(L)
+        g = vup.make_grid(wl.n, wl.lo, wl.hi)
+        mu = torch.from_numpy(wl.mu).cuda()
+        sg = torch.from_numpy(wl.sigma).cuda()
+
+        def run():
+            f = vup.eval_grid(g, wl.model)
+            mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
+            P, _ = vup.propagate(mm, mu, sg, None, "fp32", wl.n_sigma, want_Z=False)
+            return P
+
+        run()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        U = wl.N * L
+        res[str(L)] = {"ms": best * 1e3, "updates": U, "updates_per_s": U / best}
+    res["growth_L1_to_L1000"] = res["1000"]["ms"] / res["1"]["ms"]
+    return res
 
 
 def ipsa_example_runs(vup, workloads, stream, reps):
@@ -514,6 +553,11 @@ def main():
         log("[bench] IPSA views " + ", ".join(
             f"{k} {v['ms']:.3f} ms" for k, v in result["ipsa_views"].items()
             if isinstance(v, dict)))
+        result["timing_study"] = timing_study_runs(vup, workloads, 3)
+        log("[bench] Sec. 4.1 timing study (whole pipeline, wall clock) " + ", ".join(
+            f"L={k}: {v['ms']:.3f} ms" for k, v in result["timing_study"].items()
+            if isinstance(v, dict)) +
+            f"; growth L=1 -> 1000: x{result['timing_study']['growth_L1_to_L1000']:.2f}")
         log("[bench] Sec. 5.3 example " + ", ".join(
             f"sigma_l={k}: {v['ms']:.3f} ms" for k, v in result["ipsa_example"].items()))
     else:

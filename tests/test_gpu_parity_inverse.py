@@ -156,3 +156,20 @@ def test_posterior_full_size_grid1024(vup, orc):
         # window minus the mass of cells without a bin
         dens = post[t][has].double() * P[k].double()[b[has]]
         assert abs(dens.sum().item() - P[k].double().sum().item()) <= 2e-5
+
+
+def test_timing_study_workload_small_L(vup, orc):
+    """The Sec. 4.1 timing workload (N = 10^6, untruncated pdfs over the
+    whole grid) at L = 3 against the oracle: the configuration bench.py times
+    with L up to 1000."""
+    wl = workloads.timing_study(3)
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    fo = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    eo = orc.uniform_edges(fo, wl.B)
+    mm = vup.build_model_matrix(g, torch.from_numpy(fo).to(DEV), torch.from_numpy(eo).to(DEV))
+    P, _ = vup.propagate(mm, wl.mu, wl.sigma, None, "fp32", wl.n_sigma)
+    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(fo, eo), wl.B, wl.mu, wl.sigma,
+                          n_sigma=wl.n_sigma)
+    l1 = np.abs(_cpu(P).astype(np.float64) - Po).sum(axis=1).max()
+    _say(f"[timing study L=3] max column L1 {l1:.3e}")
+    assert l1 <= 2e-5

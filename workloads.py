@@ -33,6 +33,14 @@ also use analytic models on uniform grids, so no dataset is involved):
                does not state the domain, which is a reading (x spans the
                locations, alpha spans 4 sigma_alpha).
 
+* ``timing_study(L)`` the timing experiment of Sec. 4.1: 2-D 1000 x 1000 grid
+               over (x, alpha) in [-3,3]^2 (N = 10^6), model
+               1.1 sin x + 7 sin^2 alpha, L Gaussians with sigma = (1, 1)
+               differing only in mu_x (L points on the midpoint subgrid of
+               [-2,2], mu_alpha = 0), untruncated (windows span the grid),
+               B = 1000. The paper does not state the domain, sigma or the
+               bin count; these are readings.
+
 Means "on an M x M subgrid" are the subgrid cell midpoints
 lo + (m + 1/2)(hi - lo)/M on each axis, with k = m0 * M + m1.
 """
@@ -185,6 +193,14 @@ def ipsa_example(sigma_l: float = 0.25) -> Workload:
     sigma[:, 0, 1] = 0.25
     return Workload(f"ipsa_example[sigma_l={sigma_l}]", 2, (1000, 1000), (-5.0, -1.0),
                     (5.0, 1.0), "ipsa2", (), 1000, mu, sigma, None, n_sigma=8.0)
+
+
+def timing_study(L: int) -> Workload:
+    mu = np.zeros((L, 1, 2), dtype=np.float64)
+    mu[:, 0, 0] = subgrid_midpoints(-2.0, 2.0, L)
+    sigma = np.ones((L, 1, 2), dtype=np.float64)
+    return Workload(f"timing_study[L={L}]", 2, (1000, 1000), (-3.0, -3.0), (3.0, 3.0), "timing2",
+                    (), 1000, mu, sigma, None, n_sigma=1.0e6)
 
 
 CONFIGS = {
