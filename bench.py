@@ -317,8 +317,20 @@ def ipsa_example_runs(vup, workloads, stream, reps):
             vup.ipsa_fields(mm, P, y, (0.025, 0.5, 0.975))
 
         ms = _time_on(stream, run, reps)
+        # the alpha factor is shared by all locations: the same propagation in
+        # the banded MFMA form (M_x = 1000 locations, M_y = 1), and the
+        # general propagation alone for comparison
+        mux = wl.mu[:, 0, 0].copy()
+        sgx = wl.sigma[:, 0, 0].copy()
+        _, _, ws = vup.propagate_separable(mm, mux, [0.0], sgx, [0.25], wl.n_sigma, want_Z=False)
+        ms_sep = _time_on(stream, lambda: vup.propagate_separable(mm, mux, [0.0], sgx, [0.25],
+                                                                   wl.n_sigma, ws=ws,
+                                                                   want_Z=False), reps)
+        ms_prop = _time_on(stream, lambda: vup.propagate(mm, mu, sg, None, "fp32", wl.n_sigma,
+                                                          want_Z=False), reps)
         res[str(s_l)] = {"ms": ms, "updates": U, "updates_per_s": U / (ms * 1e-3),
-                         "sweep_form": mm.sweep}
+                         "sweep_form": mm.sweep, "propagate_ms": ms_prop,
+                         "propagate_separable_ms": ms_sep}
     return res
 # kernel-name fragments of the sweep kernels in rocprofv3 output
 TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments", "ipsa": "k_ipsa<"}

@@ -222,8 +222,9 @@ typedef struct vup_sepdists {
 
 /* --------------------------------------------------------------------------
  * vup_separable_workspace_bytes - device workspace for vup_propagate_separable
- * (factor matrices, per-axis sums and the partial contraction T, whose size
- * is n[0] * B * M[1] floats). 0 for invalid arguments.
+ * (factor matrices, per-axis sums, prefix sums along y and the partial
+ * contraction T, whose size is n[0] * B * M[1] floats). 0 for invalid
+ * arguments.
  * ------------------------------------------------------------------------ */
 size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My);
 
@@ -236,7 +237,10 @@ size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My);
  * T is a scatter over one axis; the contraction over the other is a banded
  * dense product evaluated on the matrix cores (FP32 MFMA). Same outputs and
  * conventions as vup_propagate with K = M[0]*M[1], ncomp = 1 (Z[k] =
- * Zx[mx] * Zy[my], the window mass). Needs ndim == 2 and B <= 512.
+ * Zx[mx] * Zy[my], the window mass). T is built from the model matrix's runs
+ * of equal bin along y (one difference of FP64 prefix sums per run). Families
+ * with M[1] < 16 (e.g. one shared alpha factor) tile the contraction over
+ * bins instead of over my. Needs ndim == 2, and B <= 512 when n[1] > 65534.
  *   ws: dev, 256-byte aligned, ws_bytes >= vup_separable_workspace_bytes.
  * ------------------------------------------------------------------------ */
 int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, size_t ws_bytes,

@@ -368,7 +368,11 @@ static size_t runs_tiled_lds(int B, int ny) {
 #endif
 constexpr int kSepBins = VUP_SEP_BINS;  // bins per workgroup of the contraction
 
-template <int NB>
+// BT = false: a workgroup owns 16 my x NB bins (the column tile q is bin
+// b0 + q, its 16 columns the my); BT = true (families with M_y < 16, e.g. a
+// shared alpha axis, M_y = 1): one my and 16 NB bins (column tile q holds
+// bins b0 + 16 q .. + 15).
+template <int NB, bool BT>
 __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   constexpr int kPitch = 16 * NB + 16;
   constexpr int kTile = 16 * kPitch;
@@ -376,7 +380,9 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
-  const int my0 = blockIdx.x * 16, b0 = blockIdx.y * NB, mxb = blockIdx.z * 256;
+  const int my0 = BT ? blockIdx.x : blockIdx.x * 16;
+  const int b0 = BT ? blockIdx.y * 16 * NB : blockIdx.y * NB;
+  const int mxb = blockIdx.z * 256;
   // windows of this wave's four tiles (uniform), and of the workgroup's 16
   int tlo[4], thi[4];
   int glo = 0x7fffffff, ghi = -1;
@@ -416,17 +422,34 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
 #pragma unroll
       for (int u = 0; u < NB / 4; ++u) {
         const int e = threadIdx.x + 256 * u;
-        const int ix = ix0 + e / (4 * NB), b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
+        const int ix = ix0 + e / (4 * NB);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ix <= ghi && ix < nx && b < B) {
-          const float* src = a.T + ((long long)ix * B + b) * My + my;
-          if (vec && my + 3 < My) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else {
-            if (my < My) v.x = src[0];
-            if (my + 1 < My) v.y = src[1];
-            if (my + 2 < My) v.z = src[2];
-            if (my + 3 < My) v.w = src[3];
+        if constexpr (BT) {
+          // four consecutive bins of one my
+          const int b = b0 + 16 * ((e >> 2) % NB) + 4 * (e & 3);
+          if (ix <= ghi && ix < nx) {
+            const float* src = a.T + ((long long)ix * B + b) * My + my0;
+            if (My == 1 && (B & 3) == 0 && b + 3 < B) {
+              v = *reinterpret_cast<const float4*>(src);
+            } else {
+              if (b < B) v.x = src[0];
+              if (b + 1 < B) v.y = src[My];
+              if (b + 2 < B) v.z = src[2 * My];
+              if (b + 3 < B) v.w = src[3 * My];
+            }
+          }
+        } else {
+          const int b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
+          if (ix <= ghi && ix < nx && b < B) {
+            const float* src = a.T + ((long long)ix * B + b) * My + my;
+            if (vec && my + 3 < My) {
+              v = *reinterpret_cast<const float4*>(src);
+            } else {
+              if (my < My) v.x = src[0];
+              if (my + 1 < My) v.y = src[1];
+              if (my + 2 < My) v.z = src[2];
+              if (my + 3 < My) v.w = src[3];
+            }
           }
         }
         tv[u] = v;
@@ -490,8 +513,32 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
       if (c + 1 <= c1) step(c + 1, 1, an, av);
     }
   }
-  // D[4 lk + r][li] = C[tile mx + 4 lk + r][my0 + li]; normalise and store the
-  // NB bins of each (mx, my)
+  // D[4 lk + r][li] = C[tile mx + 4 lk + r][column li of tile q]; normalise and
+  // store
+  if constexpr (BT) {
+    const int my = my0;
+    const double zy = a.Zd[1][my];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mx = mxb + 16 * (4 * j + w) + 4 * lk + r;
+        if (mx >= Mx) continue;
+        const double z = a.Zd[0][mx] * zy;
+        const double rz = 1.0 / z;
+        const long long k = (long long)mx * My + my;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int b = b0 + 16 * q + li;
+          if (b < B)
+            a.P[k * B + b] = (z > 0.0) ? (float)((double)acc[j][q][r] * rz)
+                                       : (z == 0.0 ? 0.0f : __builtin_nanf(""));
+        }
+        if (a.Z && blockIdx.y == 0 && li == 0) a.Z[k] = z;
+      }
+    }
+    return;
+  }
   const int my = my0 + li;
   if (my >= My) return;
   const double zy = a.Zd[1][my];
@@ -612,8 +659,15 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int NB = kSepBins;
-  hipLaunchKernelGGL(k_sep_gemm<NB>, dim3((My + 15) / 16, (mm.B + NB - 1) / NB, (Mx + 255) / 256),
-                     dim3(256), 0, s, a);
+  if (My < 16) {
+    hipLaunchKernelGGL((k_sep_gemm<NB, true>), dim3(My, (mm.B + 16 * NB - 1) / (16 * NB),
+                                                    (Mx + 255) / 256),
+                       dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_sep_gemm<NB, false>), dim3((My + 15) / 16, (mm.B + NB - 1) / NB,
+                                                     (Mx + 255) / 256),
+                       dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

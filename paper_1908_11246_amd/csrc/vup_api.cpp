@@ -224,7 +224,8 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
   int r = check_mm(mm);
   if (r) return r;
   if (mm->grid.ndim != 2) return fail(VUP_EUNSUPPORTED, "separable form needs a 2-D grid");
-  if (mm->B > 512) return fail(VUP_EUNSUPPORTED, "separable form needs B <= 512");
+  if (mm->B > 512 && mm->grid.n[1] > 65534)
+    return fail(VUP_EUNSUPPORTED, "separable form needs B <= 512 when n[1] > 65534");
   if (!s) return fail(VUP_EINVAL, "sepdists is NULL");
   if (s->M[0] < 1 || s->M[1] < 1 || s->M[0] > 65535 || s->M[1] > 65535)
     return fail(VUP_EINVAL, "M must be in [1, 65535]");

@@ -468,6 +468,39 @@ SEP_PATHS = [
 ]
 
 
+def test_separable_shared_alpha_axis(vup, orc):
+    """A family with one shared alpha factor (M_y = 1), as in the Sec. 5.3
+    example: the bin-tiled contraction, against the oracle."""
+    n, lo, hi = (200, 150), (-5.0, -1.0), (5.0, 1.0)
+    mux = workloads.subgrid_midpoints(-5.0, 5.0, 40)
+    for s_l in (0.05, 3.0):
+        sgx = np.full(40, s_l)
+        Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "ipsa2", 100, mux,
+                                               np.array([0.0]), sgx, np.array([0.25]),
+                                               f"shared alpha, sigma_l={s_l}")
+        _check_P(Pg, Po, 2e-5, f"P separable shared alpha sigma_l={s_l}")
+        assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("s_l", [0.05, 3.0])
+def test_separable_ipsa_example_full_size(vup, orc, s_l):
+    """The Sec. 5.3 example at full size (N = 10^6, B = 1000, 1000 locations)
+    in the banded form with the shared alpha factor: sampled rows against the
+    oracle."""
+    wl = workloads.ipsa_example(s_l)
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    fo = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    eo = orc.uniform_edges(fo, wl.B)
+    mm = vup.build_model_matrix(g, torch.from_numpy(fo).to(DEV), torch.from_numpy(eo).to(DEV))
+    P, Z, _ = vup.propagate_separable(mm, wl.mu[:, 0, 0], [0.0], wl.sigma[:, 0, 0], [0.25],
+                                      wl.n_sigma)
+    ks = workloads.sample_indices(wl.K, 5, 13)
+    sub = wl.subset(ks)
+    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(fo, eo), wl.B, sub.mu, sub.sigma,
+                          n_sigma=wl.n_sigma)
+    _check_P(_cpu(P)[ks], Po, 2e-5, f"P separable Sec. 5.3 example sigma_l={s_l}")
+
+
 @pytest.mark.parametrize("case", SEP_PATHS, ids=[c[0] for c in SEP_PATHS])
 def test_separable_paths(vup, orc, case):
     label, n, Mx, My, B = case
