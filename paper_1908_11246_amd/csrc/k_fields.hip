@@ -273,7 +273,6 @@ struct MatrixArgs {
   int B;
   double dy_lo, dy_width;
   int J;       // target cells
-  int mt;      // target cells per lane, ceil(J/LPC)
   float* Q;    // [K][J]
   double* lost;
 };
@@ -305,10 +304,30 @@ __device__ __forceinline__ double target_point(double dlo, double h, int j, doub
   return __dadd_rn(__dadd_rn(dlo, __dmul_rn((double)j, h)), y);
 }
 
+// number of edges <= t from a guess: exact whatever the guess (monotone
+// edges), a step or two when the guess comes from near-uniform edges
+__device__ __forceinline__ int count_le_from(const double* E, int B, double t, int cnt) {
+  while (cnt <= B && E[cnt] <= t) ++cnt;
+  while (cnt > 0 && !(E[cnt - 1] <= t)) --cnt;
+  return cnt;
+}
+
+// The matrix gives a column a whole wave. The J + 1 grid points d_j + y are
+// taken round-robin (lane l of round r has point 64 r + l), so the lanes of a
+// round look up adjacent bins (no LDS bank conflicts); Q_j = F(j+1) - F(j)
+// comes from the neighbouring lane. With near-uniform edges (each within half
+// an average bin width of its uniform position) a point's bin is guessed
+// arithmetically and corrected exactly; otherwise it is found by bisection.
 template <int LPC, int MV, bool VEC>
 __global__ __launch_bounds__(256) void k_ipsa_matrix(MatrixArgs a) {
-  constexpr int G = 64 / LPC;
+  // launched with LPC = 64 only (one column per wave); the launch table
+  // instantiates the other widths, which do nothing
+  if constexpr (LPC != 64) {
+    return;
+  } else {
+  constexpr int G = 1;
   extern __shared__ double lds[];
+  __shared__ int s_nonuniform;
   const int B = a.B;
   double* E = lds;
   double* invw = lds + (B + 1);
@@ -316,7 +335,15 @@ __global__ __launch_bounds__(256) void k_ipsa_matrix(MatrixArgs a) {
   const int r = lane & (LPC - 1);
   const int g = lane / LPC;
   double* C = lds + (2 * B + 1) + ((threadIdx.x >> 6) * G + g) * (B + 1);
+  if (threadIdx.x == 0) s_nonuniform = 0;
   stage_tables(a.edges, B, E, nullptr, invw);
+  // near-uniform edges?
+  const double e0 = E[0], wbar = (E[B] - E[0]) / B;
+  for (int b = threadIdx.x; b <= B; b += blockDim.x)
+    if (!(fabs(E[b] - (e0 + b * wbar)) <= 0.5 * wbar)) atomicOr(&s_nonuniform, 1);
+  __syncthreads();
+  const bool uniform = s_nonuniform == 0;
+  const double scale = 1.0 / wbar;
   stream_columns<LPC, MV, VEC>(a.P, a.K, B, [&](long long k, bool live, const float4 (&v)[MV]) {
     double incl[MV];
     const double T = col_scan<LPC, MV>(v, B, incl);
@@ -334,38 +361,41 @@ __global__ __launch_bounds__(256) void k_ipsa_matrix(MatrixArgs a) {
     }
     if (r == 0) C[B] = T;
     wave_lds_sync();
-    const int j0 = r * a.mt;
-    const int j1 = min(a.J, j0 + a.mt);
     float* q = a.Q + k * (long long)a.J;
-    const int last = (a.J - 1) / a.mt;  // lane of the group owning the last target cell
-    double F_first = 0.0, F_end = 0.0;
     const bool fin = isfinite(T);
-    if (live && fin && j0 < j1) {
+    if (live && !fin) {
+      for (int j = lane; j < a.J; j += 64) q[j] = __builtin_nanf("");
+      if (lane == 0 && a.lost) a.lost[k] = __builtin_nan("");
+    } else if (live) {
       const double y = a.y_ref[k];
-      double t = target_point(a.dy_lo, a.dy_width, j0, y);
-      int cnt = count_le(E, B, t);
-      double F = cdf_at(E, invw, C, B, T, cnt, t);
-      F_first = F;
-      for (int j = j0; j < j1; ++j) {
-        t = target_point(a.dy_lo, a.dy_width, j + 1, y);
-        // two branch-free steps cover target cells up to about a bin wide;
-        // the loop catches wider ones
-#pragma unroll
-        for (int u = 0; u < 2; ++u) cnt += (cnt <= B && E[min(cnt, B)] <= t) ? 1 : 0;
-        while (cnt <= B && E[cnt] <= t) ++cnt;
-        const double Fn = cdf_at(E, invw, C, B, T, cnt, t);
-        q[j] = (float)(Fn - F);
-        F = Fn;
+      const int J = a.J;
+      double last = 0.0, F_first = 0.0, F_end = 0.0;
+      for (int p0 = 0; p0 <= J; p0 += 64) {
+        const int p = p0 + lane;
+        double F = 0.0;
+        if (p <= J) {
+          const double t = target_point(a.dy_lo, a.dy_width, p, y);
+          int cnt;
+          if (uniform) {
+            const double gd = fmin(fmax(floor((t - e0) * scale), -1.0), (double)B);
+            cnt = count_le_from(E, B, t, (int)gd + 1);
+          } else {
+            cnt = count_le(E, B, t);
+          }
+          F = cdf_at(E, invw, C, B, T, cnt, t);
+        }
+        double Fprev = grp_prev<64>(F);
+        if (lane == 0) Fprev = last;
+        if (p >= 1 && p <= J) q[p - 1] = (float)(F - Fprev);
+        last = lane_value(F, 63);
+        if (p0 == 0) F_first = lane_value(F, 0);
+        if (p0 == (J / 64) * 64) F_end = lane_value(F, J - p0);
       }
-      F_end = F;
-    } else if (live && !fin) {
-      for (int j = j0; j < j1; ++j) q[j] = __builtin_nanf("");
+      if (lane == 0 && a.lost) a.lost[k] = F_first + (T - F_end);
     }
-    const double lo_part = shfl_f64(F_first, g * LPC);
-    const double hi_part = shfl_f64(F_end, g * LPC + last);
-    if (live && r == 0 && a.lost) a.lost[k] = fin ? lo_part + (T - hi_part) : __builtin_nan("");
-    wave_lds_sync();  // C is rewritten for the next columns
+    wave_lds_sync();  // C is rewritten for the next column
   });
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -583,7 +613,6 @@ hipError_t launch_ipsa_matrix(const double* edges, int B, int64_t K, const float
   a.dy_width = dy_width;
   a.J = n_dy;
   const int lpc = 64;
-  a.mt = (n_dy + lpc - 1) / lpc;
   a.Q = Q;
   a.lost = lost;
   const size_t fixed = (size_t)(2 * B + 1) * sizeof(double);
