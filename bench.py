@@ -406,7 +406,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the propagation shards over distributions with no "
-              "communication, and multi-GPU runs are not part of this build.", file=sys.stderr)
+              "communication, and runs on more than one GPU are not supported.", file=sys.stderr)
         sys.exit(2)
 
     import torch
