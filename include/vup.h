@@ -256,8 +256,8 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
  * computed as (var + (mean - M(mu_k))^2)/2 with M evaluated at mu_k.
  *   mean, var: dev FP64 [K]; delta2: dev FP64 [K] or NULL; model: host, used
  *   only for delta2 (may be NULL when delta2 is NULL).
- * Moments are of the f given to vup_bin (its FP32 copy, see DESIGN notes in
- * the source). NaN for invalid parameters or all-empty windows.
+ * Moments are of the f given to vup_bin (its FP32 copy, held in the model
+ * matrix). NaN for invalid parameters or all-empty windows.
  * ------------------------------------------------------------------------ */
 int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, double* mean,
                 double* var, double* delta2, void* stream);
