@@ -50,8 +50,9 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 #   propagation: density (row factor x fastest-axis factor) and its add into
 #   the bin: 2 operations;
 #   exact-f moments: density, f - s, p (f - s), the add into S1 and the
-#   multiply-add into S2: 6 operations.
-OPS_PER_UPDATE = {"propagate": 2, "moments": 6}
+#   multiply-add into S2 (one operation, as every fused multiply-add here):
+#   5 operations.
+OPS_PER_UPDATE = {"propagate": 2, "moments": 5}
 KERNELS = {"propagate": "k_propagate_runs (run form) / k_propagate<FP32> (cell form)",
            "moments": "k_moments"}
 
