@@ -497,7 +497,7 @@ def main():
     dominant = max(("propagate", "moments"), key=lambda k: part_ms[k])
 
     result = {
-        "metric": "cell-distribution updates/sec (FP32 densities, full VUP+IPSA step)",
+        "metric": "cell\u00b7distribution updates/sec (FP32 vs BF16 vs fwd+bwd) at stated error",
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -510,7 +510,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "grid1024: 2-D 1024x1024, sincos model, B=256, K=65536 "
-                               "Gaussians, sigma~U[0.05,0.5], 4-sigma truncation",
+                               "Gaussians, sigma~U[0.05,0.5], 4-sigma truncation; value = "
+                               "FP32 full VUP+IPSA step (BF16 and fwd+bwd in variants, "
+                               "errors in error_vs_fp64_oracle)",
                    "grid": list(wl.n), "B": wl.B, "K": wl.K, "updates_per_step": U},
         "roofline": rooflines[dominant],
         "rooflines": rooflines,
