@@ -118,7 +118,9 @@ typedef struct vup_mm {
   /* byte offsets inside ws */
   size_t off_edges;     /* double[B+1]      bin edges                           */
   size_t off_binmap;    /* uint16[rows*pitch] 4*bin (4*B for no bin), padded    */
-  size_t off_f32;       /* float[rows*pitch] model values in FP32, padded       */
+  size_t off_f32;       /* float[rows*pitch] model values in FP32, padded: a    */
+                        /* column c with c % 8 == 0 holds f, any other column  */
+                        /* f - f(c - c % 8) (padding columns: 0)               */
   size_t off_counts;    /* int64[B+1]       cells per bin; [B] = outside        */
   size_t off_offsets;   /* int64[B+1]       CSR row starts of the model matrix  */
   size_t off_perm;      /* int32[N]         cells sorted by bin (stable)        */

@@ -4,7 +4,9 @@
 //   k_minmax / k_edges   B uniform bins over [min f, max f]
 //   k_bin           indicator of eq. (4) as a bin index; padded bin map
 //                   (4*bin, LDS byte offsets for the sweep kernels), padded
-//                   FP32 copy of f, per-chunk bin counts
+//                   FP32 copy of f in anchored form (every eighth column
+//                   holds f, the columns after it their offset from it),
+//                   per-chunk bin counts
 //   k_tile_sums, k_scan_tile_sums, k_tile_scan  exclusive scan of the counts in
 //                   (bin, chunk) order; k_csr_offsets  CSR row starts and counts
 //   k_scatter       stable scatter of cell indices into compressed-by-bin
@@ -198,7 +200,10 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
         ++outside;
         atomicAdd(&cnt[a.B], 1);
       }
-      fv = (float)y;
+      // anchored FP32 form: columns 8m hold f, the seven after each their
+      // difference from it (taken in FP64, rounded once)
+      const int c0 = col & ~7;
+      fv = col == c0 ? (float)y : (float)(y - a.f[row * a.nL + c0]);
     }
     a.binmap[p] = code;
     a.f32[p] = fv;
