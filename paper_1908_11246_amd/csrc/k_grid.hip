@@ -344,20 +344,22 @@ __global__ __launch_bounds__(64) void k_scatter(BinArgs a, const int* __restrict
         b = (code == 4 * a.B) ? -2 : code >> 2;
       }
     }
-    unsigned long long todo = __ballot(b >= 0);
+    // lanes holding the same bin as this lane (found one distinct bin at a
+    // time with ballots), then one LDS read of the bin's position per lane;
+    // the highest lane of each bin advances it. One wave per workgroup: its
+    // LDS reads and writes take effect in program order, so no barrier.
+    unsigned long long todo = __ballot(b >= 0), same = 0ull;
     while (todo) {
       const int leader = __ffsll((long long)todo) - 1;
-      const int bl = __shfl(b, leader, 64);
+      const int bl = __builtin_amdgcn_readlane(b, leader);
       const unsigned long long m = __ballot(b == bl);
-      const int start = pos[bl];
-      if (b == bl) {
-        const int rank = __popcll(m & ((1ull << lane) - 1ull));
-        perm[start + rank] = (int32_t)cell;
-      }
-      __syncthreads();
-      if (lane == leader) pos[bl] = start + __popcll(m);
-      __syncthreads();
+      if (b == bl) same = m;
       todo &= ~m;
+    }
+    if (b >= 0) {
+      const int start = pos[b];
+      perm[start + __popcll(same & ((1ull << lane) - 1ull))] = (int32_t)cell;
+      if ((same >> lane) == 1ull) pos[b] = start + __popcll(same);
     }
   }
 }
