@@ -80,16 +80,28 @@ __global__ void k_minmax_init(unsigned long long* e, int B) {
   }
 }
 
+// Min and max of the non-NaN model values as order-preserving integer images.
+// A thread reads eight values at once (independent loads in flight), the
+// workgroup reduces in LDS, and one pair of atomics per workgroup merges.
 __global__ __launch_bounds__(256) void k_minmax(const double* __restrict__ f, long long N,
                                                 unsigned long long* e, int B) {
+  __shared__ unsigned long long smn[4], smx[4];
   unsigned long long mn = ~0ull, mx = 0ull;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N;
-       i += (long long)gridDim.x * 256) {
-    const double v = f[i];
-    if (v != v) continue;
-    const unsigned long long o = ord_of(v);
-    mn = o < mn ? o : mn;
-    mx = o > mx ? o : mx;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i0 = (long long)blockIdx.x * 256 + threadIdx.x; i0 < N; i0 += 8 * stride) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long i = i0 + u * stride;
+      v[u] = i < N ? f[i] : __builtin_nan("");
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (v[u] != v[u]) continue;
+      const unsigned long long o = ord_of(v[u]);
+      mn = o < mn ? o : mn;
+      mx = o > mx ? o : mx;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long a = __shfl_xor(mn, off, 64), b = __shfl_xor(mx, off, 64);
@@ -97,6 +109,15 @@ __global__ __launch_bounds__(256) void k_minmax(const double* __restrict__ f, lo
     mx = b > mx ? b : mx;
   }
   if ((threadIdx.x & 63) == 0) {
+    smn[threadIdx.x >> 6] = mn;
+    smx[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      mn = smn[w] < mn ? smn[w] : mn;
+      mx = smx[w] > mx ? smx[w] : mx;
+    }
     atomicMin(e, mn);
     atomicMax(e + B, mx);
   }
@@ -119,8 +140,8 @@ __global__ __launch_bounds__(256) void k_edges(double* e, int B) {
 hipError_t launch_uniform_edges(const double* f, int64_t N, int B, double* edges, hipStream_t s) {
   unsigned long long* e = reinterpret_cast<unsigned long long*>(edges);
   hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(64), 0, s, e, B);
-  long long blocks = (N + 4095) / 4096;
-  if (blocks > 2048) blocks = 2048;
+  long long blocks = (N + 2047) / 2048;  // eight values per thread
+  if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, s, f, (long long)N, e, B);
   hipLaunchKernelGGL(k_edges, dim3(1), dim3(256), 0, s, edges, B);
