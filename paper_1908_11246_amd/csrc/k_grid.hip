@@ -540,8 +540,45 @@ struct RunArgs {
   int nL, pitch, nb, none;
 };
 
-__device__ __forceinline__ bool run_start(const uint16_t* row, int c) {
-  return c == 0 || row[c] != row[c - 1];
+// the 32 bin codes of block q of a row (the row pitch is a multiple of 32
+// cells, so a block is 64 aligned bytes: four 16-byte loads) and the code of
+// the cell before it (0xFFFFFFFF for the row's first block, so cell 0 starts
+// a run)
+struct Block32 {
+  uint32_t w[16];  // two codes per word, the lower column in the low half
+  uint32_t prev;
+};
+
+__device__ __forceinline__ Block32 load_block32(const uint16_t* row, int q) {
+  Block32 b;
+  const uint4* p = reinterpret_cast<const uint4*>(row + q * 32);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint4 v = p[i];
+    b.w[4 * i] = v.x;
+    b.w[4 * i + 1] = v.y;
+    b.w[4 * i + 2] = v.z;
+    b.w[4 * i + 3] = v.w;
+  }
+  b.prev = q == 0 ? 0xFFFFFFFFu : (uint32_t)row[q * 32 - 1];
+  return b;
+}
+
+__device__ __forceinline__ uint32_t code_at(const Block32& b, int j) {
+  return (j & 1) ? (b.w[j >> 1] >> 16) : (b.w[j >> 1] & 0xFFFFu);
+}
+
+// bit j set when cell q*32 + j (a cell of the row) starts a run
+__device__ __forceinline__ uint32_t run_starts(const Block32& b, int q, int nL) {
+  uint32_t m = 0;
+  uint32_t before = b.prev;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const uint32_t c = code_at(b, j);
+    if (c != before && q * 32 + j < nL) m |= 1u << j;
+    before = c;
+  }
+  return m;
 }
 
 __global__ __launch_bounds__(256) void k_runs_count(RunArgs a) {
@@ -550,9 +587,8 @@ __global__ __launch_bounds__(256) void k_runs_count(RunArgs a) {
   if (t < a.rows * a.nb) {
     const long long r = t / a.nb;
     const int q = (int)(t - r * a.nb);
-    const uint16_t* row = a.binmap + r * a.pitch;
-    int cnt = 0;
-    for (int c = q * 32; c < q * 32 + 32 && c < a.nL; ++c) cnt += run_start(row, c) ? 1 : 0;
+    const Block32 blk = load_block32(a.binmap + r * a.pitch, q);
+    int cnt = __popc(run_starts(blk, q, a.nL));
     real = cnt;
     if (q == a.nb - 1) ++cnt;  // terminator of the row
     a.blockcnt[t] = cnt;
@@ -567,25 +603,33 @@ __global__ __launch_bounds__(256) void k_runs_fill(RunArgs a) {
   const long long r = t / a.nb;
   const int q = (int)(t - r * a.nb);
   const uint16_t* row = a.binmap + r * a.pitch;
+  const Block32 blk = load_block32(row, q);
+  const uint32_t starts = run_starts(blk, q, a.nL);
   const int rowstart = a.blockcnt[r * a.nb];
   int pos = a.blockcnt[t];
   if (q == 0) a.rowptr[r] = rowstart;
   int cur = pos - 1 - rowstart;  // run holding the cell before this block
-  for (int c = q * 32; c < q * 32 + 32; ++c) {
-    if (c < a.nL) {
-      if (run_start(row, c)) {
-        a.runs[pos] = (uint32_t)c | ((uint32_t)row[c] << 16);
-        cur = pos - rowstart;
-        ++pos;
-      }
+  uint32_t idx[16];              // run indices of the 32 cells, two per word
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int c = q * 32 + j;
+    if ((starts >> j) & 1u) {
+      a.runs[pos] = (uint32_t)c | (code_at(blk, j) << 16);
+      cur = pos - rowstart;
+      ++pos;
     } else if (c == a.nL) {
       // terminator: first column past the row, no bin
       a.runs[pos] = (uint32_t)a.nL | ((uint32_t)a.none << 16);
       cur = pos - rowstart;
       ++pos;
     }
-    a.runidx[r * a.pitch + c] = (uint16_t)cur;
+    if (j & 1) idx[j >> 1] |= (uint32_t)(uint16_t)cur << 16;
+    else idx[j >> 1] = (uint32_t)(uint16_t)cur;
   }
+  uint4* out = reinterpret_cast<uint4*>(a.runidx + r * a.pitch + q * 32);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    out[i] = make_uint4(idx[4 * i], idx[4 * i + 1], idx[4 * i + 2], idx[4 * i + 3]);
   if (q == a.nb - 1 && a.nL == a.nb * 32) {
     // row length is a multiple of 32: terminator after the last block
     a.runs[pos] = (uint32_t)a.nL | ((uint32_t)a.none << 16);
