@@ -240,18 +240,23 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
 // tiles of kScanTile: tile totals, one workgroup scanning the totals, then
 // each tile scanned from its offset. `tsum` holds ceil(n / kScanTile) int64.
 // ---------------------------------------------------------------------------
-constexpr int kScanPer = 16;                 // elements per thread
+constexpr int kScanPer = 4;                  // elements per thread (one 16-byte load)
 constexpr int kScanTile = 256 * kScanPer;    // elements per workgroup
+
+// this thread's four consecutive elements of the tile (zeros past n); the
+// array is 16-byte aligned and tiles are whole multiples of four elements
+__device__ __forceinline__ int4 scan_load4(const int* __restrict__ v, long long n, long long p) {
+  if (p + 3 < n) return *reinterpret_cast<const int4*>(v + p);
+  return make_int4(p < n ? v[p] : 0, p + 1 < n ? v[p + 1] : 0, p + 2 < n ? v[p + 2] : 0,
+                   p + 3 < n ? v[p + 3] : 0);
+}
 
 __global__ __launch_bounds__(256) void k_tile_sums(const int* __restrict__ v, long long n,
                                                    long long* __restrict__ tsum) {
   __shared__ long long red[4];
-  const long long base = (long long)blockIdx.x * kScanTile;
-  long long sum = 0;
-  for (int i = threadIdx.x; i < kScanTile; i += 256) {
-    const long long p = base + i;
-    if (p < n) sum += v[p];
-  }
+  const long long p = (long long)blockIdx.x * kScanTile + kScanPer * threadIdx.x;
+  const int4 x = scan_load4(v, n, p);
+  long long sum = (long long)x.x + x.y + x.z + x.w;
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
@@ -294,27 +299,19 @@ __global__ __launch_bounds__(1024) void k_scan_tile_sums(long long* tsum, long l
 
 __global__ __launch_bounds__(256) void k_tile_scan(int* __restrict__ v, long long n,
                                                    const long long* __restrict__ tsum) {
-  __shared__ int tile[kScanTile];
   __shared__ long long wsum[4];
-  const long long base = (long long)blockIdx.x * kScanTile;
-  for (int i = threadIdx.x; i < kScanTile; i += 256) {
-    const long long p = base + i;
-    tile[i] = p < n ? v[p] : 0;
-  }
-  __syncthreads();
-  long long s = 0;
-  for (int j = 0; j < kScanPer; ++j) s += tile[threadIdx.x * kScanPer + j];
-  const long long excl = block_incl_scan(s, wsum) - s + tsum[blockIdx.x];
-  long long run = excl;
-  for (int j = 0; j < kScanPer; ++j) {
-    const int x = tile[threadIdx.x * kScanPer + j];
-    tile[threadIdx.x * kScanPer + j] = (int)run;
-    run += x;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kScanTile; i += 256) {
-    const long long p = base + i;
-    if (p < n) v[p] = tile[i];
+  const long long p = (long long)blockIdx.x * kScanTile + kScanPer * threadIdx.x;
+  const int4 x = scan_load4(v, n, p);
+  const long long s = (long long)x.x + x.y + x.z + x.w;
+  const long long e0 = block_incl_scan(s, wsum) - s + tsum[blockIdx.x];
+  const int4 y = make_int4((int)e0, (int)(e0 + x.x), (int)(e0 + x.x + x.y),
+                           (int)(e0 + x.x + x.y + x.z));
+  if (p + 3 < n) {
+    *reinterpret_cast<int4*>(v + p) = y;
+  } else {
+    if (p < n) v[p] = y.x;
+    if (p + 1 < n) v[p + 1] = y.y;
+    if (p + 2 < n) v[p + 2] = y.z;
   }
 }
 
