@@ -158,6 +158,15 @@ def test_posterior_full_size_grid1024(vup, orc):
         assert abs(dens.sum().item() - P[k].double().sum().item()) <= 2e-5
 
 
+def test_posterior_long_fastest_axis(vup, orc):
+    """A fastest axis of 17 000 cells: the fastest-axis factor table no longer
+    fits the posterior kernel's 64 KB LDS budget and is evaluated per cell."""
+    wl = workloads.random_workload("inv_long", (4, 17000), (-2.0, -3.0), (2.0, 3.0), "sincos2", 23,
+                                   12, 1, (0.2, 0.9), seed=73)
+    _say("[posterior] long fastest axis")
+    _run(vup, orc, wl, [0, 5, 11], "long axis")
+
+
 def test_timing_study_workload_small_L(vup, orc):
     """The Sec. 4.1 timing workload (N = 10^6, untruncated pdfs over the
     whole grid) at L = 3 against the oracle: the configuration bench.py times
