@@ -602,3 +602,22 @@ def test_run_and_cell_forms_agree(vup, orc):
         assert mm_u.sweep == "auto"
         Pu, _ = vup.propagate(mm_u, wl.mu, wl.sigma, wl.weight)
         assert np.array_equal(_cpu(Pu), out[mm.sweep])
+
+
+def test_model_copy_is_anchored(vup):
+    """The FP32 model copy inside the model matrix holds, per row, f at every
+    eighth column and the FP64 difference f - f(anchor), rounded once, at the
+    seven after it; padding columns hold 0 (the layout include/vup.h states).
+    A fastest axis of 37 cells makes the last anchor block ragged."""
+    g = vup.make_grid((5, 37), (-2.0, -1.0), (2.0, 1.5))
+    f = vup.eval_grid(g, "sincos2")
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, 16))
+    torch.cuda.synchronize()
+    rows, pitch = int(mm.mm.rows), int(mm.mm.pitch)
+    f32 = mm._view(mm.mm.off_f32, torch.float32, rows * pitch).cpu().numpy().reshape(rows, pitch)
+    fh = f.cpu().numpy().reshape(5, 37)
+    want = np.zeros((rows, pitch), dtype=np.float32)
+    for c in range(37):
+        c0 = c - c % 8
+        want[:, c] = fh[:, c] if c == c0 else (fh[:, c] - fh[:, c0])
+    assert np.array_equal(f32, want)
