@@ -597,6 +597,10 @@ struct RunScales {
 };
 
 constexpr int kRunGroup = 16;  // lanes per row: one DPP row
+// rows of the run form's row table held in LDS at once: 256 keeps a
+// workgroup's LDS near 20 KB at 1024-cell rows, so eight workgroups (eight
+// waves per SIMD, with the kernel held to 64 VGPRs) fit on a CU
+constexpr int kRunRowChunk = 256;
 
 // G[c] = sum of the fastest-axis factors of the window columns below c, FP64,
 // for every column c = 0 .. n (0 up to loL, the window total from hiL + 1 on).
@@ -748,7 +752,7 @@ __device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int r
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_propagate_runs(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, 8) void k_propagate_runs(SweepArgs a) {
   extern __shared__ float smem[];
   if (!runs_chosen(a)) return;  // k_propagate does the work
   const long long k = block_k(a);
@@ -800,8 +804,8 @@ __global__ __launch_bounds__(kThreads) void k_propagate_runs(SweepArgs a) {
         ps->unscale[r] = 1.0 / ps->srow[r];
       }
     }
-    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
-      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+    for (long long r0 = 0; r0 < w.R; r0 += kRunRowChunk) {
+      const int rc = (int)((w.R - r0) < kRunRowChunk ? (w.R - r0) : kRunRowChunk);
       __syncthreads();
       build_rows_runs(a, smem, w, r0, rc, ps, loL, loL + WL - 1);
       __syncthreads();
@@ -1590,8 +1594,9 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   }
   off = round_up(off, 4);
   L.row_off = off;
-  off += (kind == kSweepBwdRuns ? 8 : (kind == kSweepPropagate || kind == kSweepRuns ? 4 : 2)) *
-         kRowChunk;
+  off += kind == kSweepRuns
+             ? 4 * kRunRowChunk
+             : (kind == kSweepBwdRuns ? 8 : (kind == kSweepPropagate ? 4 : 2)) * kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;
