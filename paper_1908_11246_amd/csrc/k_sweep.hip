@@ -601,6 +601,10 @@ constexpr int kRunGroup = 16;  // lanes per row: one DPP row
 // workgroup's LDS near 20 KB at 1024-cell rows, so eight workgroups (eight
 // waves per SIMD, with the kernel held to 64 VGPRs) fit on a CU
 constexpr int kRunRowChunk = 256;
+// the same for the adjoint's run form (32-byte rows): about 30 KB of LDS per
+// workgroup at 1024-cell rows, five workgroups per CU, matched by holding the
+// 2-D kernel to 96 VGPRs (five waves per SIMD)
+constexpr int kBwdRowChunk = 256;
 
 // G[c] = sum of the fastest-axis factors of the window columns below c, FP64,
 // for every column c = 0 .. n (0 up to loL, the window total from hiL + 1 on).
@@ -1466,7 +1470,7 @@ __device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc
 }
 
 template <int NO>
-__global__ __launch_bounds__(kThreads) void k_backward_runs(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, NO <= 1 ? 5 : 1) void k_backward_runs(SweepArgs a) {
   extern __shared__ float smem[];
   if (!runs_chosen(a)) return;  // k_backward does the work
   const long long k = block_k(a);
@@ -1510,8 +1514,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_runs(SweepArgs a) {
     acc.a0 = acc.l1 = acc.l2 = 0.0;
 #pragma unroll
     for (int i = 0; i < (NO > 0 ? NO : 1); ++i) acc.o1[i] = acc.o2[i] = 0.0;
-    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
-      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+    for (long long r0 = 0; r0 < w.R; r0 += kBwdRowChunk) {
+      const int rc = (int)((w.R - r0) < kBwdRowChunk ? (w.R - r0) : kBwdRowChunk);
       __syncthreads();
       build_rows_bwd_runs(a, smem, w, r0, rc, kc, loL, loL + WL - 1);
       __syncthreads();
@@ -1596,7 +1600,8 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   L.row_off = off;
   off += kind == kSweepRuns
              ? 4 * kRunRowChunk
-             : (kind == kSweepBwdRuns ? 8 : (kind == kSweepPropagate ? 4 : 2)) * kRowChunk;
+             : kind == kSweepBwdRuns ? 8 * kBwdRowChunk
+                                     : (kind == kSweepPropagate ? 4 : 2) * kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;

@@ -16,7 +16,7 @@ constexpr uint64_t kMagic = 0x5655504d4d763031ull;  // "VUPMMv01"
 struct SweepLayout {
   int tab_off[4];
   int cap[4];
-  int row_off;      // 16-byte entries [kRunRowChunk] (run form), [kRowChunk] (cell form) or float2[kRowChunk]
+  int row_off;      // row table: [kRunRowChunk] / [kBwdRowChunk] entries in the run forms, [kRowChunk] in the cell forms
   int trow_off;     // float4[kRowChunk] (backward only, else -1)
   int hist_off;     // histogram copies (propagate) or v table (backward)
   int hist_stride;  // floats per histogram copy
