@@ -597,10 +597,6 @@ struct RunScales {
 };
 
 constexpr int kRunGroup = 16;  // lanes per row: one DPP row
-// rows of the run form's row table held in LDS at once: 256 keeps a
-// workgroup's LDS near 20 KB at 1024-cell rows, so eight workgroups (eight
-// waves per SIMD, with the kernel held to 64 VGPRs) fit on a CU
-constexpr int kRunRowChunk = 256;
 // the same for the adjoint's run form (32-byte rows): about 30 KB of LDS per
 // workgroup at 1024-cell rows, five workgroups per CU, matched by holding the
 // 2-D kernel to 96 VGPRs (five waves per SIMD)
@@ -756,6 +752,8 @@ __device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int r
   }
 }
 
+// RR: rows per row-table pass (the layout's rrows)
+template <int RR>
 __global__ __launch_bounds__(kThreads, 8) void k_propagate_runs(SweepArgs a) {
   extern __shared__ float smem[];
   if (!runs_chosen(a)) return;  // k_propagate does the work
@@ -808,8 +806,8 @@ __global__ __launch_bounds__(kThreads, 8) void k_propagate_runs(SweepArgs a) {
         ps->unscale[r] = 1.0 / ps->srow[r];
       }
     }
-    for (long long r0 = 0; r0 < w.R; r0 += kRunRowChunk) {
-      const int rc = (int)((w.R - r0) < kRunRowChunk ? (w.R - r0) : kRunRowChunk);
+    for (long long r0 = 0; r0 < w.R; r0 += RR) {
+      const int rc = (int)((w.R - r0) < RR ? (w.R - r0) : RR);
       __syncthreads();
       build_rows_runs(a, smem, w, r0, rc, ps, loL, loL + WL - 1);
       __syncthreads();
@@ -1567,8 +1565,9 @@ __global__ __launch_bounds__(kThreads, NO <= 1 ? 5 : 1) void k_backward_runs(Swe
 // ===========================================================================
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
+bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out, int run_rows) {
   SweepLayout L{};
+  L.rrows = run_rows > 0 ? run_rows : kRunRowChunk;
   const int D = g.ndim;
   int off = 0;
   for (int d = 0; d < 4; ++d) {
@@ -1599,7 +1598,7 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out) {
   off = round_up(off, 4);
   L.row_off = off;
   off += kind == kSweepRuns
-             ? 4 * kRunRowChunk
+             ? 4 * L.rrows
              : kind == kSweepBwdRuns ? 8 * kBwdRowChunk
                                      : (kind == kSweepPropagate ? 4 : 2) * kRowChunk;
   L.trow_off = -1;
@@ -1736,8 +1735,16 @@ hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, floa
     // the run form returns at once unless the device-side mode and run
     // statistics select it; the cell form below then returns at once
     SweepArgs ar = a;
-    sweep_layout(mm.grid, mm.B, kSweepRuns, &ar.L);
-    hipLaunchKernelGGL(k_propagate_runs, grid, block, ar.L.bytes, s, ar);
+    // with fewer distributions than the GPU holds workgroups, occupancy does
+    // not matter and the larger row table saves passes
+    const long long nwg = 8 * ((d.K + 7) / 8);
+    if (nwg <= 2048 && sweep_layout(mm.grid, mm.B, kSweepRuns, &ar.L, 2 * kRunRowChunk) &&
+        ar.L.bytes <= 64 * 1024) {
+      hipLaunchKernelGGL(k_propagate_runs<2 * kRunRowChunk>, grid, block, ar.L.bytes, s, ar);
+    } else {
+      sweep_layout(mm.grid, mm.B, kSweepRuns, &ar.L);
+      hipLaunchKernelGGL(k_propagate_runs<kRunRowChunk>, grid, block, ar.L.bytes, s, ar);
+    }
     e = hipGetLastError();
     if (e != hipSuccess || mm.sweep == VUP_SWEEP_RUNS) return e;
   }

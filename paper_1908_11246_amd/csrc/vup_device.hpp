@@ -13,6 +13,11 @@ namespace vup {
 constexpr int kThreads = 256;     // threads per workgroup of the sweep kernels
 constexpr int kWaves = kThreads / 64;
 constexpr int kRowChunk = 512;    // rows of the row table held in LDS at once
+// rows per row-table pass of the run-form propagation when many distributions
+// are propagated: 256 keeps a workgroup's LDS near 20 KB at 1024-cell rows, so
+// eight workgroups (eight waves per SIMD, the kernel held to 64 VGPRs) fit on
+// a CU; with fewer distributions than resident workgroups, 512 (fewer passes)
+constexpr int kRunRowChunk = 256;
 constexpr int kMaxSW = 16;        // widest strip of the fastest axis
 constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
 

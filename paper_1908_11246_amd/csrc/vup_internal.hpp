@@ -16,7 +16,8 @@ constexpr uint64_t kMagic = 0x5655504d4d763031ull;  // "VUPMMv01"
 struct SweepLayout {
   int tab_off[4];
   int cap[4];
-  int row_off;      // row table: [kRunRowChunk] / [kBwdRowChunk] entries in the run forms, [kRowChunk] in the cell forms
+  int row_off;      // row table: [rrows] / [kBwdRowChunk] entries in the run forms, [kRowChunk] in the cell forms
+  int rrows;        // rows per row-table pass of the run-form propagation
   int trow_off;     // float4[kRowChunk] (backward only, else -1)
   int hist_off;     // histogram copies (propagate) or v table (backward)
   int hist_stride;  // floats per histogram copy
@@ -35,7 +36,9 @@ enum SweepKind {
   kSweepBwdRuns = 4
 };
 
-bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out);
+// run_rows: rows per row-table pass of the run-form propagation (0: the
+// default, kRunRowChunk)
+bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out, int run_rows = 0);
 GridDev make_grid_dev(const vup_mm& mm);
 DistsDev make_dists_dev(const vup_dists& d);
 
