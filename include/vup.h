@@ -255,9 +255,16 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
  * with FP32 per-row partial sums of shifted values and FP64 accumulation.
  * delta2 (optional, ncomp == 1 and a built-in model only): the local expected
  * squared deviation of eq. IPSAvar, 1/2 sum_i p_k(x_i)(f_i - M(mu_k))^2,
- * computed as (var + (mean - M(mu_k))^2)/2 with M evaluated at mu_k.
+ * computed as (var + (mean - M(mu_k))^2)/2 with M evaluated at mu_k. The
+ * reference value is the model at the pdf's maximum, y(l) = M(mu_k), the same
+ * reference the IPSA probability matrix is translated by (Sec. 5.3). Eq.
+ * IPSAvar keeps parameter-like axes (alpha) at the cell's own value inside the
+ * reference, M(l, alpha); both readings agree when every axis is data-like,
+ * and for a model additive in alpha with a window symmetric about mu_alpha
+ * the y(l) reading exceeds eq. IPSAvar's by half the pdf's alpha variance.
  *   mean, var: dev FP64 [K]; delta2: dev FP64 [K] or NULL; model: host, used
- *   only for delta2 (may be NULL when delta2 is NULL).
+ *   only for delta2 (may be NULL when delta2 is NULL); it must be a model of
+ *   the grid's ndim (EINVAL otherwise).
  * Moments are of the f given to vup_bin (its FP32 copy, held in the model
  * matrix). NaN for invalid parameters or all-empty windows.
  * ------------------------------------------------------------------------ */

@@ -252,8 +252,8 @@ int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, do
   if (delta2) {
     if (d->ncomp != 1) return fail(VUP_EUNSUPPORTED, "delta2 needs single-component pdfs");
     if (!model) return fail(VUP_EINVAL, "delta2 needs the built-in model");
-    if (model->kind < 0 || model->kind > VUP_MODEL_IPSA2)
-      return fail(VUP_EINVAL, "unknown model %d", model->kind);
+    // the kernel evaluates the model at mu with the grid's ndim coordinates
+    if ((r = check_model(model, mm->grid.ndim))) return r;
   }
   if ((r = check_sweep(mm, vup::kSweepMoments))) return r;
   if ((r = check_device())) return r;

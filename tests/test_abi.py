@@ -150,6 +150,16 @@ def test_dists_validation(lib):
                            None) == EUNSUPPORTED
     assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d), None, dummy, dummy, dummy,
                            None) == EINVAL
+    # ... a model of the grid's ndim (a 4-D model on a 2-D grid would read
+    # coordinates the distributions do not have)
+    m4 = vup.make_model("ring4")
+    assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d), ctypes.byref(m4), dummy, dummy,
+                           dummy, None) == EINVAL
+    assert b"ndim" in lib.vup_last_error()
+    m_bad = vup.make_model("sincos2")
+    m_bad.kind = 42
+    assert lib.vup_moments(ctypes.byref(mm), ctypes.byref(d), ctypes.byref(m_bad), dummy, dummy,
+                           dummy, None) == EINVAL
     assert lib.vup_ipsa_backward(ctypes.byref(mm), ctypes.byref(d), None, dummy, None, None,
                                  dummy, dummy, None, None) == EINVAL
 

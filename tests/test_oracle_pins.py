@@ -491,6 +491,34 @@ def test_ipsa_gradient_vs_central_fd(orc, C):
                            atol=1e-8 * np.abs(gw).max())
 
 
+def test_ipsa_gradient_vs_central_fd_grid1024_subset(orc):
+    """P11 at the full 1024^2 size: the 64 seeded locations of the gradient
+    subset of the 1024^2 configuration (sigma ~ U[0.05, 0.5], B = 256), all
+    four parameters each (mu and sigma per axis), FP64 central differences
+    with h = 1e-4 on frozen windows against the analytic gradient. The central
+    difference's truncation error is about (h/sigma)^2/6 <= 7e-7 of the
+    derivative, so rtol 1e-5 holds with margin."""
+    wl = workloads.grid1024()
+    ks = workloads.fd_subset(wl.K, 64)
+    sub = wl.subset(ks)
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    e = orc.uniform_edges(f, wl.B)
+    b = orc.bins(f, e)
+    win, _, _ = orc.windows(wl.n, wl.lo, wl.hi, sub.mu, sub.sigma)
+    rng = np.random.default_rng(41)
+    gv = rng.uniform(0.5, 1.5, size=sub.K)
+    ge = rng.uniform(0.5, 1.5, size=sub.K)
+    P, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, win=win)
+    gm, gs, _ = orc.ipsa_grad(wl.n, wl.lo, wl.hi, b, e, sub.mu, sub.sigma, None, win, P, gv, ge)
+    fm, fs = _fd_grad(orc, wl.n, wl.lo, wl.hi, b, e, sub.mu, sub.sigma, None, win, gv, ge)
+    scale = max(np.abs(gm).max(), np.abs(gs).max())
+    assert np.allclose(gm, fm, rtol=1e-5, atol=1e-9 * scale)
+    assert np.allclose(gs, fs, rtol=1e-5, atol=1e-9 * scale)
+    # the isotropic pdf's two sigma partials are not equal at a generic
+    # location (the test would not notice an axis swap otherwise)
+    assert np.abs(gs[:, 0, 0] - gs[:, 0, 1]).max() > 1e-3 * scale
+
+
 def test_ipsa_gradient_with_mass_outside_the_bins(orc):
     """P11 with edges that leave part of the output range uncovered, so columns
     sum to less than one and the variance derivative keeps its -2 c_b S term."""
@@ -581,3 +609,19 @@ def test_workload_generators_shapes():
     w1 = workloads.grid64()
     # subgrid midpoints: 16 per axis, spacing 6/16
     assert np.allclose(np.unique(w1.mu[:, 0, 0]), -3 + (np.arange(16) + 0.5) * 0.375)
+
+
+def test_oracle_clean_under_address_and_ub_sanitizers():
+    """The oracle's C code, with a driver calling every exported function on
+    1- to 4-D grids, mixtures, every density precision, frozen windows and the
+    degenerate inputs it defines outputs for, built under AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only): any out-of-bounds access, use
+    after free, leak or undefined arithmetic fails the run."""
+    import subprocess
+    from oracle import build as oracle_build
+    exe = oracle_build.build_sanitized()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0 and "san_check ok" in r.stdout, r.stderr[-4000:]
+
