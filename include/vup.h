@@ -20,8 +20,11 @@
  *    Sec. 3); flat cell index row major, axis 0 slowest.
  *  - Memory: the caller owns all memory. Pointers marked "dev" are device
  *    (HBM) pointers of the current HIP device; "host" pointers are ordinary
- *    host memory. No call allocates device memory; the only buffer the
- *    library needs is the workspace the caller passes to vup_bin.
+ *    host memory. No call allocates device memory; the buffers the library
+ *    needs are workspaces the caller passes (vup_bin, the separable form,
+ *    the marginal). The one exception to caller-owned memory is the fixed
+ *    device array behind vup_marginalize_noalloc (VUP_NOALLOC_SCRATCH_BYTES
+ *    per GPU, part of the loaded code object, never allocated by a call).
  *  - Streams: every kernel is enqueued on `stream` (a hipStream_t; NULL = the
  *    default stream). No call synchronises except vup_counters.
  *  - Errors: every call returns VUP_OK (0) or a negative status. Arguments
@@ -377,6 +380,25 @@ int vup_ipsa_fields(const vup_mm* mm, int64_t K, const float* P, const double* y
 size_t vup_marginal_workspace_bytes(int64_t K, int32_t n);
 int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, void* ws,
                     size_t ws_bytes, double* out, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_marginalize_noalloc - vup_marginalize for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same result, bit for bit, with the partial sums
+ * held in a device array the library owns (VUP_NOALLOC_SCRATCH_BYTES per GPU,
+ * kept until the process ends) instead of a caller workspace. The call makes
+ * no allocation of any kind; the caller still passes A, rho and out.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller. Nothing in the array needs clearing between calls.
+ *   Arguments and errors as vup_marginalize, plus EUNSUPPORTED when
+ *   vup_marginal_workspace_bytes(K, n) > VUP_NOALLOC_SCRATCH_BYTES, which
+ *   happens exactly when n > 1048576 (any K), checked before anything is
+ *   enqueued.
+ * ------------------------------------------------------------------------ */
+#define VUP_NOALLOC_SCRATCH_BYTES (8 << 20)
+int vup_marginalize_noalloc(int64_t K, int32_t n, const float* A, const double* rho,
+                            double* out, void* stream);
 
 /* --------------------------------------------------------------------------
  * vup_posterior - Bayes inversion over the model matrix (Sec. 3, the Bayes

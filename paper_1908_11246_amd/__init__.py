@@ -121,6 +121,7 @@ def _load():
     lib.vup_marginal_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.vup_marginalize.argtypes = [ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t,
                                     _vp, _vp]
+    lib.vup_marginalize_noalloc.argtypes = [ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp]
     _lib = lib
     return lib
 
@@ -456,6 +457,18 @@ def marginalize(A: torch.Tensor, rho: Optional[torch.Tensor] = None,
     out = torch.empty(n, dtype=torch.float64, device=A.device)
     _check(_load().vup_marginalize(K, n, _ptr(A), _ptr(r), _ptr(ws), ws.numel(), _ptr(out),
                                    _vp(_stream())))
+    return out
+
+
+def marginalize_noalloc(A: torch.Tensor, rho: Optional[torch.Tensor] = None,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """marginalize() with the partial sums in the library's own device array
+    (no workspace); ``out`` may be a preallocated FP64 tensor of n elements."""
+    K, n = A.shape
+    r = None if rho is None else _dev_f64(rho, A.device)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(_load().vup_marginalize_noalloc(K, n, _ptr(A), _ptr(r), _ptr(out), _vp(_stream())))
     return out
 
 

@@ -17,6 +17,8 @@
 // traffic is one read of P and one write of the outputs.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "vup_device.hpp"
 #include "vup_fields.hpp"
 
@@ -712,6 +714,51 @@ hipError_t launch_marginalize(int64_t K, int n, const float* A, const double* rh
   }
   hipLaunchKernelGGL(k_marg_combine, dim3((unsigned)n), dim3(64), 0, s, part, chunks, n, out);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// marginal without a caller workspace: the partial sums live in a file-scope
+// device array of kStaticMarginalBytes, one copy per GPU for the life of the
+// process. Host code never passes the array's name to a kernel (on the host
+// it is a stand-in, not a device address); it passes the address
+// hipGetSymbolAddress returns for the current device, looked up on the first
+// call on that device and kept. Every partial sum is written before it is
+// read, so nothing needs clearing between calls; calls that overlap on one
+// GPU share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double g_marginal_scratch[kStaticMarginalBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static hipError_t marginal_scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_marginal_scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_marginalize_static(int64_t K, int n, const float* A, const double* rho,
+                                     double* out, hipStream_t s) {
+  if (marginal_workspace_bytes(K, n) > kStaticMarginalBytes) return hipErrorInvalidValue;
+  void* part = nullptr;
+  const hipError_t e = marginal_scratch_for_current_device(&part);
+  if (e != hipSuccess) return e;
+  return launch_marginalize(K, n, A, rho, part, out, s);
 }
 
 }  // namespace vup

@@ -13,6 +13,9 @@
 #include "vup_inverse.hpp"
 #include "vup_internal.hpp"
 
+static_assert(vup::kStaticMarginalBytes == (size_t)VUP_NOALLOC_SCRATCH_BYTES,
+              "the header states the scratch array's size");
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -386,6 +389,24 @@ int vup_marginalize(int64_t K, int32_t n, const float* A, const double* rho, voi
   if (r) return r;
   return launched(vup::launch_marginalize(K, n, A, rho, ws, out, (hipStream_t)stream),
                   "vup_marginalize");
+}
+
+int vup_marginalize_noalloc(int64_t K, int32_t n, const float* A, const double* rho,
+                            double* out, void* stream) {
+  if (K < 0) return fail(VUP_EINVAL, "K < 0");
+  if (n < 1 || n > VUP_MAX_MARGINAL_COLS)
+    return fail(VUP_EINVAL, "n %d not in [1,%d]", n, VUP_MAX_MARGINAL_COLS);
+  if (!out || (K > 0 && !A)) return fail(VUP_EINVAL, "A or out is NULL");
+  const size_t need = vup::marginal_workspace_bytes(K, n);
+  if (need > VUP_NOALLOC_SCRATCH_BYTES)
+    return fail(VUP_EUNSUPPORTED,
+                "partial sums of %zu bytes exceed the library's %d-byte scratch array "
+                "(use vup_marginalize with a workspace)",
+                need, VUP_NOALLOC_SCRATCH_BYTES);
+  int r = check_device();
+  if (r) return r;
+  return launched(vup::launch_marginalize_static(K, n, A, rho, out, (hipStream_t)stream),
+                  "vup_marginalize_noalloc");
 }
 
 int vup_posterior(const vup_mm* mm, const vup_dists* d, int64_t n_sel, const int64_t* sel,

@@ -29,5 +29,10 @@ int marginal_chunks(int64_t K, int n);
 size_t marginal_workspace_bytes(int64_t K, int n);
 hipError_t launch_marginalize(int64_t K, int n, const float* A, const double* rho, void* ws,
                               double* out, hipStream_t s);
+// the same with the partial sums in the library's own device array (no
+// caller workspace); needs marginal_workspace_bytes(K, n) <= kStaticMarginalBytes
+constexpr size_t kStaticMarginalBytes = (size_t)8 << 20;
+hipError_t launch_marginalize_static(int64_t K, int n, const float* A, const double* rho,
+                                     double* out, hipStream_t s);
 
 }  // namespace vup

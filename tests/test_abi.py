@@ -235,6 +235,16 @@ def test_field_line_arguments(lib):
     need = lib.vup_marginal_workspace_bytes(100, 9)
     assert lib.vup_marginalize(100, 9, dummy, None, dummy, need - 1, dummy, None) == EWORKSPACE
     assert lib.vup_marginalize(100, 9, dummy, None, None, need, dummy, None) == EWORKSPACE
+    # the allocation-free marginal: same argument checks, and sizes whose
+    # partial sums exceed its 8 MiB array are refused before any launch
+    noalloc = lib.vup_marginalize_noalloc
+    assert noalloc(-1, 4, dummy, None, dummy, None) == EINVAL
+    assert noalloc(10, 0, dummy, None, dummy, None) == EINVAL
+    assert noalloc(10, 4, None, None, dummy, None) == EINVAL
+    assert noalloc(10, 4, dummy, None, None, None) == EINVAL
+    assert noalloc(10, (1 << 20) + 1, dummy, None, dummy, None) == EUNSUPPORTED
+    assert b"scratch" in lib.vup_last_error()
+    assert lib.vup_marginal_workspace_bytes(1 << 30, 1 << 20) <= 8 << 20
 
 
 def test_posterior_arguments(lib):
