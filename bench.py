@@ -90,26 +90,48 @@ def source_sha256(kernel="propagate"):
     return h.hexdigest()
 
 
-def kernels_once():
+def kernels_once(name="grid1024"):
+    """One launch of each sweep kernel on a workload (propagation at every
+    density precision the workload is measured at, moments, IPSA, adjoint),
+    then a plain 256 MiB copy: the calibration dispatch of the byte counters."""
     import torch
     import paper_1908_11246_amd as vup
     import workloads
-    wl = workloads.grid1024()
+    wl = workloads.CONFIGS[name]()
     g = vup.make_grid(wl.n, wl.lo, wl.hi)
     mu = torch.from_numpy(wl.mu).cuda()
     sigma = torch.from_numpy(wl.sigma).cuda()
+    w = None if wl.weight is None else torch.from_numpy(wl.weight).cuda()
     f = vup.eval_grid(g, wl.model, wl.theta)
     mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
-    P, _ = vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
-    vup.moments(mm, mu, sigma)
-    vup.ipsa(mm, P)
+    P, _ = vup.propagate(mm, mu, sigma, w, "fp32", want_Z=False)
+    vup.moments(mm, mu, sigma, w)
+    mh, _, _ = vup.ipsa(mm, P)
+    if name != "grid1024":
+        for prec in PRECISIONS[name][1:]:
+            vup.propagate(mm, mu, sigma, w, prec, want_Z=False)
+        one = torch.ones(wl.K, dtype=torch.float64, device="cuda")
+        vup.ipsa_backward(mm, mu, sigma, w, P, mh, one, one)
+    else:
+        # the banded form on the tensor-product family of the same grid
+        # (256 x 256 locations, shared sigma = 0.25)
+        m = workloads.subgrid_midpoints(wl.lo[0], wl.hi[0], 256)
+        s = np.full(256, 0.25)
+        vup.propagate_separable(mm, m, m, s, s, want_Z=False)
     torch.cuda.synchronize()
     src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)  # last dispatch: the calibration copy
     torch.cuda.synchronize()
-    print("kernels-once done", flush=True)
+    print(f"kernels-once {name} done", flush=True)
+
+
+# density precisions each configuration is measured at (the first is FP32,
+# the reference the others are compared with)
+PRECISIONS = {"grid1024": ("fp32", "bf16", "bf16x2", "fp8e4m3"),
+              "grid128_3d": ("fp32", "bf16", "bf16x2"),
+              "grid48_4d": ("fp32", "fp8e4m3")}
 
 
 CALIB_BYTES = 256 << 20
@@ -255,6 +277,95 @@ def separable_run(vup, workloads, stream, reps):
                          "kernel": "vup_propagate_separable (k_sep_gemm + set-up, whole call)"}}
 
 
+def _errors_vs_fp64(orc, wl, b, e, Ps, mh_v, ks):
+    """Errors of each precision's P (and of the IPSA quantities computed from
+    it on the GPU) against the FP64 oracle on the sampled distributions ks;
+    Ps[prec] and mh_v[prec] hold the GPU's rows ks only."""
+    sub = wl.subset(ks)
+    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight)
+    mo, vo, ho = orc.ipsa(Po, e)
+    out = {"metric": f"max over {len(ks)} sampled distributions: column L1 of P, |d mean_hist|, "
+                     "|d var_hist| / var_hist, |d entropy| (nats), against the FP64 oracle"}
+    for prec, P in Ps.items():
+        Pg = P.astype(np.float64)
+        mg, vg, hg = mh_v[prec]
+        out[prec] = {"P_L1": float(np.abs(Pg - Po).sum(axis=1).max()),
+                     "mean_hist": float(np.abs(mg - mo).max()),
+                     "var_hist_rel": float((np.abs(vg - vo) / vo).max()),
+                     "entropy": float(np.abs(hg - ho).max())}
+    return out
+
+
+def config_runs(vup, workloads, name, stream, reps, keep):
+    """A 3-D or 4-D configuration: propagation at each density precision the
+    configuration names, and forward + backward (propagate + IPSA + adjoint
+    sweep, with the mixture-weight gradient where there are mixtures), each
+    with U / time and its fraction of the separable-form roofline
+    R(d) = (VALU lane-op peak) / d. The columns and IPSA quantities of 64
+    sampled distributions go to `keep` for the error against the FP64 oracle
+    (computed in the CPU-oracle leg)."""
+    import torch
+    wl = workloads.CONFIGS[name]()
+    D = wl.ndim
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    mu = torch.from_numpy(wl.mu).cuda()
+    sg = torch.from_numpy(wl.sigma).cuda()
+    w = None if wl.weight is None else torch.from_numpy(wl.weight).cuda()
+    win = vup.windows(g, mu, sg)
+    U = int(torch.prod((win[..., 1] - win[..., 0] + 1).clamp(min=0).to(torch.int64),
+                       dim=-1).sum().item())
+    f = vup.eval_grid(g, wl.model, wl.theta)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
+    out = {"workload": f"{name}: {'x'.join(map(str, wl.n))} grid, {wl.model} model, B={wl.B}, "
+                       f"K={wl.K}" + (f" {wl.C}-component mixtures" if wl.C > 1 else ""),
+           "updates": U, "sweep_form": mm.sweep}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            ev[0].record(stream)
+            r = fn()
+            ev[1].record(stream)
+            ev[1].synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        return float(np.mean(ts)), r
+
+    Ps, stats = {}, {}
+    for prec in PRECISIONS[name]:
+        ms, (P, _) = timed(lambda: vup.propagate(mm, mu, sg, w, prec, want_Z=False))
+        Ps[prec] = P.cpu().numpy()
+        stats[prec] = tuple(t.cpu().numpy() for t in vup.ipsa(mm, P))
+        ups = U / (ms * 1e-3)
+        out[f"propagate_{prec}"] = {"ms": ms, "updates_per_s": ups,
+                                    "frac_of_R(d)": ups * D / VALU_PEAK_OPS}
+    P32 = torch.from_numpy(Ps["fp32"]).cuda()
+    one = torch.ones(wl.K, dtype=torch.float64, device="cuda")
+
+    def fwd_bwd():
+        P, _ = vup.propagate(mm, mu, sg, w, "fp32", want_Z=False)
+        mh, _, _ = vup.ipsa(mm, P)
+        return vup.ipsa_backward(mm, mu, sg, w, P, mh, one, one)
+
+    ms, _ = timed(fwd_bwd)
+    mh, _, _ = vup.ipsa(mm, P32)
+    ms_b, _ = timed(lambda: vup.ipsa_backward(mm, mu, sg, w, P32, mh, one, one))
+    # forward d lane-ops per update, adjoint 3d + 2 (three FMAs per axis and
+    # the weight lookup-and-add), so the pair is bounded by peak / (4d + 2)
+    ups = U / (ms * 1e-3)
+    out["fwd_bwd_fp32"] = {"ms": ms, "backward_ms": ms_b, "updates_per_s": ups,
+                           "frac_of_peak/(4d+2)": ups * (4 * D + 2) / VALU_PEAK_OPS,
+                           "note": "U counted once; forward and adjoint each sweep U"
+                                   + ("; gradients wrt mu, sigma and the mixture weights"
+                                      if wl.C > 1 else "")}
+    ks = workloads.sample_indices(wl.K, 64, 21)
+    keep[name] = (wl, ks, {p: P[ks] for p, P in Ps.items()},
+                  {p: tuple(a[ks] for a in v) for p, v in stats.items()})
+    return out
+
+
 def timing_study_runs(vup, workloads, reps):
     """The timing experiment of Sec. 4.1 as a synthetic run: for L pdfs on
     N = 10^6 cells, the whole VUP pipeline (model evaluation, bin edges, model
@@ -391,7 +502,7 @@ def summarize_stats(csv_path, out_path):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--kernels-once":
-        return kernels_once()
+        return kernels_once(*sys.argv[2:3])
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
         return summarize_traffic(sys.argv[2], sys.argv[3])
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
@@ -522,12 +633,14 @@ def main():
 
     # ---- variants on the same workload -------------------------------------
     ev = ev[:2]
+    kept = {}
     if not args.no_variants:
         mm, _ = step()
         torch.cuda.synchronize()
         variants = {}
         Ps = {}
-        for prec in ("fp32", "bf16", "bf16x2", "fp8e4m3"):
+        stats = {}
+        for prec in PRECISIONS["grid1024"]:
             vup.propagate(mm, mu, sigma, None, prec, want_Z=False)
             torch.cuda.synchronize()
             times = []
@@ -538,6 +651,7 @@ def main():
                 ev[1].synchronize()
                 times.append(ev[0].elapsed_time(ev[1]))
             Ps[prec] = P
+            stats[prec] = tuple(t.cpu().numpy() for t in vup.ipsa(mm, P))
             t = float(np.mean(times)) * 1e-3
             variants[f"propagate_{prec}"] = {"updates_per_s": U / t, "ms": 1e3 * t}
         # forward + backward: propagate + IPSA + adjoint sweep
@@ -568,6 +682,12 @@ def main():
         log("[bench] IPSA views " + ", ".join(
             f"{k} {v['ms']:.3f} ms" for k, v in result["ipsa_views"].items()
             if isinstance(v, dict)))
+        for name in ("grid128_3d", "grid48_4d"):
+            variants[name] = config_runs(vup, workloads, name, stream, max(3, args.steps // 2),
+                                         kept)
+            log(f"[bench] {name}: " + ", ".join(
+                f"{k} {v['ms']:.3f} ms" for k, v in variants[name].items()
+                if isinstance(v, dict) and "ms" in v))
         result["timing_study"] = timing_study_runs(vup, workloads, 3)
         log("[bench] Sec. 4.1 timing study (whole pipeline, wall clock) " + ", ".join(
             f"L={k}: {v['ms']:.3f} ms" for k, v in result["timing_study"].items()
@@ -604,14 +724,15 @@ def main():
                       f"(seeded sample, {Us:.3e} updates, {tc:.1f} s)"}
         log(f"[bench] cpu oracle {Us / tc:.3e} updates/s on {nthreads} threads ({tc:.1f} s)")
         if Ps is not None:
-            err = {}
-            ke = ks[:64]
-            Po64 = Po[:64]
-            for prec, P in Ps.items():
-                Pg = P[torch.from_numpy(ke).to(dev)].cpu().numpy().astype(np.float64)
-                err[prec] = float(np.abs(Pg - Po64).sum(axis=1).max())
-            result["error_vs_fp64_oracle"] = {"metric": "max column L1 of P over 64 sampled k",
-                                              **err}
+            ke = workloads.sample_indices(wl.K, 64, 8)
+            result["error_vs_fp64_oracle"] = _errors_vs_fp64(
+                orc, wl, b, e, {p: P.cpu().numpy()[ke] for p, P in Ps.items()},
+                {p: tuple(a[ke] for a in v) for p, v in stats.items()}, ke)
+            for name, (wv, kv, Pv, sv) in kept.items():
+                fo = orc.eval_grid(wv.n, wv.lo, wv.hi, wv.model, wv.theta)
+                eo = orc.uniform_edges(fo, wv.B)
+                result["variants"][name]["error_vs_fp64_oracle"] = _errors_vs_fp64(
+                    orc, wv, orc.bins(fo, eo), eo, Pv, sv, kv)
     print(json.dumps(result), flush=True)
 
 

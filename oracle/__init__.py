@@ -16,6 +16,9 @@ Function -> paper passage it follows:
   moments          exact-f mean/variance of the propagated output; eq. IPSAvar
   ipsa             coarse-grained per-column variance and entropy (Sec. 5.2)
   ipsa_grad        derivative of those quantities w.r.t. the pdf parameters
+  rounding_l1_bound  largest column change that rounding (reduced-precision
+                   variants) can make when the value rounded is off by a
+                   relative eps (a bar for comparisons at those precisions)
 
 The IPSA probability matrix (Sec. 5.2, eq. IPSA and the per-column
 translation), its field lines and the marginal over locations are plain numpy
@@ -67,6 +70,9 @@ def _load():
     lib.orc_moments.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp, ctypes.c_long, ctypes.c_int,
                                 _dp, _dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp, ctypes.c_int]
     lib.orc_ipsa.argtypes = [_dp, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp, _dp]
+    lib.orc_rounding_l1_bound.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_long,
+                                          ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int]
     lib.orc_ipsa_grad.argtypes = [ctypes.c_int, _ip, _dp, _dp, _ip, ctypes.c_int, _dp,
                                   ctypes.c_long, ctypes.c_int, _dp, _dp, _dp, _ip, _dp, _dp, _dp,
                                   _dp, _dp, _dp, ctypes.c_int]
@@ -180,6 +186,24 @@ def propagate(n, lo, hi, bin_, B, mu, sigma, weight=None, n_sigma=4.0, precision
                       _p(sigma), _p(w), float(n_sigma), PREC_IDS[precision], _p(wn, _ip),
                       _p(P), _p(Z), int(nthreads))
     return P, Z
+
+
+def rounding_l1_bound(n, lo, hi, mu, sigma, weight=None, n_sigma=4.0, precision="bf16",
+                      eps=2.0 ** -19, nthreads=0):
+    """F[K]: bound on the column L1 distance between propagate(precision=...)
+    and any propagation that rounds each density from a value within relative
+    eps of the exact one (and normalises by its own rounded sum)."""
+    lib = _load()
+    d, n_a, lo_a, hi_a = _grid_args(n, lo, hi)
+    mu = _d(mu)
+    sigma = _d(sigma)
+    w = _d(weight)
+    K, C = mu.shape[0], mu.shape[1]
+    F = np.empty(K, dtype=np.float64)
+    lib.orc_rounding_l1_bound(d, _p(n_a, _ip), _p(lo_a), _p(hi_a), K, C, _p(mu), _p(sigma),
+                              _p(w), float(n_sigma), PREC_IDS[precision], float(eps), _p(F),
+                              int(nthreads))
+    return F
 
 
 def moments(n, lo, hi, f, mu, sigma, weight=None, n_sigma=4.0, fmu=None, nthreads=0):

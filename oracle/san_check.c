@@ -35,6 +35,9 @@ int orc_moments(int ndim, const int *n, const double *lo, const double *hi, cons
                 long K, int C, const double *mu, const double *sigma, const double *weight,
                 double ns, const double *fmu, double *mean, double *var, double *delta2,
                 int nthreads);
+int orc_rounding_l1_bound(int ndim, const int *n, const double *lo, const double *hi, long K,
+                          int C, const double *mu, const double *sigma, const double *weight,
+                          double ns, int prec, double eps, double *F, int nthreads);
 int orc_ipsa(const double *P, long K, int B, const double *edges, double *mean_hist,
              double *var, double *entropy);
 int orc_ipsa_grad(int ndim, const int *n, const double *lo, const double *hi, const int *bin,
@@ -131,6 +134,10 @@ static void run_case(int ndim, const int *n, int kind, int B, long K, int C, int
     orc_propagate(ndim, n, lo, hi, bin, B, K, C, mu, sg, w, 4.0, prec, NULL, P, Z, nthreads);
     orc_propagate(ndim, n, lo, hi, bin, B, K, C, mu, sg, w, 4.0, prec, win, P, Z, nthreads);
   }
+  double *F = xmalloc(sizeof(double) * K);
+  for (int prec = -1; prec <= 3; ++prec)
+    orc_rounding_l1_bound(ndim, n, lo, hi, K, C, mu, sg, w, 4.0, prec, 0x1p-19, F, nthreads);
+  free(F);
   double *fmu = xmalloc(sizeof(double) * K), *mean = xmalloc(sizeof(double) * K);
   double *var = xmalloc(sizeof(double) * K), *d2 = xmalloc(sizeof(double) * K);
   for (long k = 0; k < K; ++k) fmu[k] = orc_model_at(kind, ndim, theta, mu + (size_t)k * C * ndim);

@@ -385,6 +385,73 @@ int orc_propagate(int ndim, const int *n, const double *lo, const double *hi,
 }
 
 /* ------------------------------------------------------------------------ */
+/* rounding sensitivity of the reduced-precision variants (for test bars)    */
+/* ------------------------------------------------------------------------ */
+
+/* Largest change of a rounded density when the value handed to the rounding
+ * is off by a relative amount up to eps: the rounding is monotone, so every
+ * value in [w(1-eps), w(1+eps)] rounds to a value between the roundings of
+ * the two ends. The BF16 pair stays within 2^-17 of its argument on either
+ * side of a change of its high part, so there the change is bounded by the
+ * ends' difference plus 2^-16 w. FP32 and FP64 are not rounded to a coarser
+ * grid here: no change. */
+static double rounding_spread(double w, double eps, int prec) {
+  if (prec != OP_BF16 && prec != OP_BF16X2 && prec != OP_FP8E4M3) return 0.0;
+  double a = quantize(w * (1.0 - eps), prec);
+  double b = quantize(w, prec);
+  double c = quantize(w * (1.0 + eps), prec);
+  double m = fmax(fabs(c - b), fabs(b - a));
+  if (prec == OP_BF16X2 && orc_round_bf16(w * (1.0 - eps)) != orc_round_bf16(w * (1.0 + eps)))
+    m += ldexp(w, -16);
+  return m;
+}
+
+/* Bound on the column L1 distance between this oracle's reduced-precision P
+ * (orc_propagate with prec) and any computation that rounds each density
+ * from a value within relative eps of the exact one and normalises by the
+ * sum of its own rounded values. Per component: M = sum over window cells of
+ * rounding_spread, Z = sum of the rounded densities; a change of the rounded
+ * values totalling at most M moves the normalised column by at most
+ * 2 M / (Z - M) in L1. F[k] = sum_c pi_c 2 M_c / (Z_c - M_c); NaN for an
+ * invalid component, 0 for an empty one. */
+int orc_rounding_l1_bound(int ndim, const int *n, const double *lo, const double *hi, long K,
+                          int C, const double *mu, const double *sigma, const double *weight,
+                          double ns, int prec, double eps, double *F, int nthreads) {
+  og_grid g = make_grid(ndim, n, lo, hi);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long k = 0; k < K; ++k) {
+    double f = 0.0;
+    for (int c = 0; c < C; ++c) {
+      long kc = k * C + c;
+      const double *m = mu + kc * ndim, *s = sigma + kc * ndim;
+      int wlo[4], whi[4], bad = 0, empty = 0;
+      for (int d = 0; d < ndim; ++d) {
+        bad |= axis_window(lo[d], hi[d], n[d], m[d], s[d], ns, &wlo[d], &whi[d]);
+        if (whi[d] < wlo[d]) empty = 1;
+      }
+      if (bad) { f = NAN; break; }
+      if (empty) continue;
+      ksum z = {0.0, 0.0}, mm = {0.0, 0.0};
+      int j[4];
+      for (int d = 0; d < ndim; ++d) j[d] = wlo[d];
+      do {
+        double w = gauss_w(&g, j, m, s);
+        ks_add(&z, quantize(w, prec));
+        ks_add(&mm, rounding_spread(w, eps, prec));
+      } while (next_cell(ndim, wlo, whi, j));
+      double zc = ks_val(&z), mc = ks_val(&mm);
+      double pc = (C > 1) ? weight[kc] : 1.0;
+      f += pc * (mc < zc ? 2.0 * mc / (zc - mc) : 2.0);
+    }
+    F[k] = f;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* moments of the propagated output (exact f, quadrature form)               */
 /* ------------------------------------------------------------------------ */
 

@@ -5,12 +5,15 @@ Bars (per distribution k unless noted):
   bins, windows, model-matrix CSR, edges     bit-exact
   f (FP64 on both sides, libm vs ocml)       <= 8 ulp of max |f|
   P, FP32 density                            L1 column error <= 2e-5, |sum - 1| <= 1e-6
-  P, BF16 / BF16x2 / E4M3                    L1 <= 2u / 5e-5 / 0.125 (u = 2^-8; e4m3 bound
-                                             includes the flushed tail); sums <= 1e-6
+  P, BF16 / BF16x2 / E4M3                    against the same-precision oracle: L1 <= 2e-5
+                                             + the column's rounding-flip bound F (see
+                                             TOL_ACCUM); against FP64: the oracle's own
+                                             rounding error + that bar
   exact-f mean                               <= 1e-6 * (max f - min f)
   exact-f variance                           <= 1e-5 * Var + 1e-9 * range^2
   binned mean / variance                     same as exact-f bars
-  entropy                                    <= 1e-5 nats (FP32), 2u(1 + ln B) (BF16);
+  binned mean / variance, reduced precision  from the column's L1 bar (_binned_reduced)
+  entropy                                    <= 1e-5 nats (FP32);
                                              the kernel alone on the oracle's P:
                                              2^-22 (H + 1) (FP32 logarithm per term)
   gradients (FP32 adjoint vs FP64 analytic)  rtol 2e-3 + atol 1e-5 max|g|
@@ -30,7 +33,6 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
-U_BF16 = 2.0 ** -8
 
 
 def _say(*a):
@@ -214,12 +216,14 @@ def test_ragged_shapes(vup, orc, case, precision):
         _check_moments(_cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), o["mean_hist"],
                        o["var_hist"], rng_f, "binned")
     else:
-        # against the oracle's same-precision result (the rounding rule is the
-        # same; the GPU rounds an FP32 product, the oracle the exact FP64 value)
-        tol = {"bf16": 2 * U_BF16, "bf16x2": 5e-5, "fp8e4m3": 0.125}[precision]
-        _check_P(_cpu(gp["P"]), o["P"], tol, f"P {precision} vs same-precision oracle")
+        # against the oracle's same-precision result (bars at TOL_ACCUM)
         P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, o["bin"], wl.B, wl.mu, wl.sigma, wl.weight)
-        _check_P(_cpu(gp["P"]), P64, tol, f"P {precision} vs FP64 oracle")
+        F = orc.rounding_l1_bound(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, wl.weight, wl.n_sigma,
+                                  precision, EPS_DENSITY)
+        Pg = _cpu(gp["P"])
+        bar = _check_reduced(Pg, o["P"], P64, F, f"P {precision}")
+        _binned_reduced(_cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), o["mean_hist"],
+                        o["var_hist"], o["P"], Pg, bar, o["edges"], f"binned {precision}")
 
 
 def test_edge_cases(vup, orc):
@@ -272,63 +276,182 @@ def test_determinism(vup):
 
 
 # ---------------------------------------------------------------------------
-# full-size configurations, sampled distributions
+# full-size configurations: every column against the oracle
 # ---------------------------------------------------------------------------
-def _sampled(vup, orc, wl, precision, nsample, seed, tol_l1, moments=True):
-    _say(f"[{wl.name} {precision}] K={wl.K} sampled {nsample}")
+# Reduced-precision bars. The oracle's reduced-precision variant rounds every
+# density with the same rule as the kernel (RNE to BF16, the BF16 hi + lo
+# pair, or E4M3 of 448 w) and normalises by the sum of the same rounded
+# values. The kernel rounds the FP32 product of FP32 per-axis factors: each
+# factor is within 2 FP32 ulps of exp (the exponential of the head of an FP64
+# argument, times one plus its tail), and d factors take d - 1 products (and
+# one more for E4M3's scale of 448), so the value rounded is within
+# 2d + d/2 <= 10 ulps (6e-7) of the exact density; EPS_DENSITY = 2^-19
+# (1.9e-6) leaves a factor of three. A cell can therefore round differently
+# only if its exact density lies within EPS_DENSITY of a rounding midpoint;
+# orc.rounding_l1_bound sums, per column, how far such cells can move the
+# normalised column (pinned on the CPU against random and adversarial
+# perturbations). The bar against the same-precision oracle is that bound
+# plus the FP32 bar of the accumulation, 2e-5; against FP64, additionally the
+# oracle's own rounding error of the column (itself pinned against the
+# worst-case bound 2u).
+TOL_ACCUM = 2e-5
+EPS_DENSITY = 2.0 ** -19
+
+
+def _binned_reduced(mg, vg, mq, vq, Pq, Pg, bar_l1, e, label):
+    """binned mean and variance at a reduced precision against the oracle of
+    the same precision. With both columns of unit mass, a column L1 distance
+    L moves the mean by at most L S / 2 and the variance by at most 3 L S^2 / 4,
+    S being the width of the bin centres the two columns occupy (shift the
+    centres to the middle of that span: |c - s| <= S/2 and |E - s| <= S/2)."""
+    c = 0.5 * (e[:-1] + e[1:])
+    occ = (Pq > 0) | (Pg > 0)
+    S = np.array([c[o].max() - c[o].min() if o.any() else 0.0 for o in occ])
+    em = np.abs(mg - mq) - (0.5 * bar_l1 * S + 1e-12)
+    ev = np.abs(vg - vq) - (0.75 * bar_l1 * S ** 2 + 1e-12)
+    _say(f"  {label}: max |dE| {np.abs(mg - mq).max():.3e}, max |dVar| "
+         f"{np.abs(vg - vq).max():.3e}; worst excess over bar {em.max():.2e} / {ev.max():.2e}")
+    assert (em <= 0).all() and (ev <= 0).all(), label
+
+
+def _check_reduced(Pg, Pq, P64, F, label):
+    """P at a reduced precision: per column L1 <= F + 2e-5 against the same-
+    precision oracle, <= own + F + 2e-5 against FP64; returns the bar."""
+    Pg = Pg.astype(np.float64)
+    bar = TOL_ACCUM + F
+    l1 = np.abs(Pg - Pq).sum(axis=1)
+    own = np.abs(Pq - P64).sum(axis=1)
+    l64 = np.abs(Pg - P64).sum(axis=1)
+    sums = np.abs(Pg.sum(axis=1) - 1.0)
+    _say(f"  {label} vs same-precision oracle: max L1 {l1.max():.3e}, max L1 - bar "
+         f"{(l1 - bar).max():.2e}, max rounding bound F {F.max():.2e} (nonzero in "
+         f"{(F > 0).mean():.1%} of columns); vs FP64: max L1 {l64.max():.3e} (oracle's own "
+         f"{own.max():.3e}); max |sum-1| {sums.max():.2e}")
+    assert (Pg >= 0).all()
+    assert (l1 <= bar).all(), label
+    assert (l64 <= own + bar).all(), label
+    assert sums.max() <= 1e-6, label
+    return bar
+
+
+def _binned_bars(mg, vg, hg, mo, vo, ho, rng_f, label):
+    """binned mean, variance and entropy from the kernel's P against the
+    oracle's, with the FP32 bars (mean 1e-6 range, variance 1e-5 Var +
+    1e-9 range^2, entropy 1e-5 nats)."""
+    _check_moments(mg, vg, mo, vo, rng_f, label)
+    eh = np.abs(hg - ho).max()
+    _say(f"  {label} entropy: max |dH| {eh:.3e} (bar 1e-5)")
+    assert eh <= 1e-5, label
+
+
+def _full_size(vup, orc, wl, precision, moments=True):
+    """Every column of the configuration against the oracle (the oracle runs
+    all K distributions, multi-threaded): P, the binned IPSA quantities and,
+    at FP32, the exact-f moments."""
+    _say(f"[{wl.name} {precision}] K={wl.K}, all columns")
     gp = _gpu_pipeline(vup, wl, precision, moments=moments)
-    ks = workloads.sample_indices(wl.K, nsample, seed)
-    sub = wl.subset(ks)
     f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
     e = orc.uniform_edges(f, wl.B)
     b = orc.bins(f, e)
-    oprec = "fp64" if precision == "fp32" else precision
-    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight, precision=oprec)
-    Pg = _cpu(gp["P"])[ks]
-    l1 = _check_P(Pg, Po, tol_l1, f"P {precision} sampled")
-    P64 = Po
-    if precision != "fp32":
-        P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, sub.mu, sub.sigma, sub.weight)
-        l1 = _check_P(Pg, P64, tol_l1, f"P {precision} vs FP64")
     rng_f = e[-1] - e[0]
+    Pg = _cpu(gp["P"])
+    P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, wl.mu, wl.sigma, wl.weight)
     mh, vh, hh = orc.ipsa(P64, e)
+    if precision == "fp32":
+        l1 = _check_P(Pg, P64, 2e-5, f"P {precision}")
+        _binned_bars(_cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), _cpu(gp["entropy"]), mh, vh,
+                     hh, rng_f, "binned")
+    else:
+        Pq, _ = orc.propagate(wl.n, wl.lo, wl.hi, b, wl.B, wl.mu, wl.sigma, wl.weight,
+                              precision=precision)
+        F = orc.rounding_l1_bound(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, wl.weight, wl.n_sigma,
+                                  precision, EPS_DENSITY)
+        bar = _check_reduced(Pg, Pq, P64, F, f"P {precision}")
+        l1 = np.abs(Pg.astype(np.float64) - P64).sum(axis=1).max()
+        mq, vq, hq = orc.ipsa(Pq, e)
+        mg, vg, hg = _cpu(gp["mean_hist"]), _cpu(gp["var_hist"]), _cpu(gp["entropy"])
+        _binned_reduced(mg, vg, mq, vq, Pq, Pg, bar, e, f"binned {precision}")
+        _say(f"  binned {precision} vs FP64: max |dE| {np.abs(mg - mh).max():.3e}, "
+             f"max |dVar|/Var {(np.abs(vg - vh) / vh).max():.3e}, "
+             f"max |dH| {np.abs(hg - hh).max():.3e}")
     if moments:
-        mo, vo, _ = orc.moments(wl.n, wl.lo, wl.hi, f, sub.mu, sub.sigma, sub.weight)
-        _check_moments(_cpu(gp["mean"])[ks], _cpu(gp["var"])[ks], mo, vo, rng_f, "exact-f")
-    return gp, ks, (mh, vh, hh), l1
+        mo, vo, _ = orc.moments(wl.n, wl.lo, wl.hi, f, wl.mu, wl.sigma, wl.weight)
+        _check_moments(_cpu(gp["mean"]), _cpu(gp["var"]), mo, vo, rng_f, "exact-f")
+    return gp, l1
 
 
-def test_grid1024_fp32_sampled(vup, orc):
-    wl = workloads.grid1024()
-    gp, ks, (mh, vh, hh), _ = _sampled(vup, orc, wl, "fp32", 48, 1, 2e-5)
-    rng_f = _cpu(gp["edges"])[-1] - _cpu(gp["edges"])[0]
-    _check_moments(_cpu(gp["mean_hist"])[ks], _cpu(gp["var_hist"])[ks], mh, vh, rng_f, "binned")
-    assert np.abs(_cpu(gp["entropy"])[ks] - hh).max() <= 1e-5
-    # every column of the full run is normalised
-    assert np.abs(_cpu(gp["P"]).astype(np.float64).sum(axis=1) - 1).max() <= 1e-6
+def test_grid1024_fp32_all_columns(vup, orc):
+    _full_size(vup, orc, workloads.grid1024(), "fp32")
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2", "fp8e4m3"])
+def test_grid1024_reduced_precision_all_columns(vup, orc, precision):
+    _full_size(vup, orc, workloads.grid1024(), precision, moments=False)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x2"])
-def test_grid128_3d_sampled(vup, orc, precision):
-    wl = workloads.grid128_3d()
-    tol = {"fp32": 2e-5, "bf16": 2 * U_BF16, "bf16x2": 5e-5}[precision]
-    gp, ks, (mh, vh, hh), l1 = _sampled(vup, orc, wl, precision, 48, 3, tol,
-                                        moments=(precision == "fp32"))
-    rng_f = _cpu(gp["edges"])[-1] - _cpu(gp["edges"])[0]
-    if precision == "fp32":
-        _check_moments(_cpu(gp["mean_hist"])[ks], _cpu(gp["var_hist"])[ks], mh, vh, rng_f,
-                       "binned")
-    else:
-        eh = np.abs(_cpu(gp["entropy"])[ks] - hh).max()
-        _say(f"  entropy err {eh:.3e} (bar {2 * U_BF16 * (1 + math.log(wl.B)):.2e})")
-        assert eh <= 2 * U_BF16 * (1 + math.log(wl.B)) * (1 if precision == "bf16" else 0.05)
+def test_grid128_3d_all_columns(vup, orc, precision):
+    _full_size(vup, orc, workloads.grid128_3d(), precision, moments=(precision == "fp32"))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp8e4m3"])
-def test_grid48_4d_sampled(vup, orc, precision):
-    wl = workloads.grid48_4d()
-    tol = {"fp32": 2e-5, "fp8e4m3": 0.125}[precision]
-    _sampled(vup, orc, wl, precision, 32, 5, tol, moments=(precision == "fp32"))
+def test_grid48_4d_all_columns(vup, orc, precision):
+    _full_size(vup, orc, workloads.grid48_4d(), precision, moments=(precision == "fp32"))
+
+
+# ---------------------------------------------------------------------------
+# eq. (IPSAvar): the local expected squared deviation of vup_moments
+# ---------------------------------------------------------------------------
+def _check_delta2(vup, orc, wl):
+    """delta2 from vup_moments against the oracle's 1/2 sum p (f - M(mu))^2
+    (the oracle evaluates M(mu) on the host). delta2 = (Var + (E - M)^2)/2,
+    so its bar follows from the moment bars: half the variance bar plus
+    |E - M| times the mean bar (and an ulp-level term for M(mu) itself)."""
+    _say(f"[delta2 {wl.name}] K={wl.K}")
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
+    e = orc.uniform_edges(f, wl.B)
+    mm = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(e).to(DEV))
+    mg, vg, dg = vup.moments(mm, wl.mu, wl.sigma, wl.weight, model=wl.model, theta=wl.theta,
+                             n_sigma=wl.n_sigma)
+    fmu = np.array([orc.model_at(wl.model, wl.mu[k, 0], wl.theta) for k in range(wl.K)])
+    mo, vo, do = orc.moments(wl.n, wl.lo, wl.hi, f, wl.mu, wl.sigma, wl.weight, wl.n_sigma,
+                             fmu=fmu)
+    rng_f = e[-1] - e[0]
+    _check_moments(_cpu(mg), _cpu(vg), mo, vo, rng_f, "exact-f")
+    dg = _cpu(dg)
+    bar = (0.5 * (1e-5 * np.abs(vo) + 1e-9 * rng_f ** 2) + np.abs(mo - fmu) * 1e-6 * rng_f
+           + 1e-14 * (1 + np.abs(fmu)) ** 2)
+    err = np.abs(dg - do)
+    _say(f"  delta2: max |err| {err.max():.3e}, max err/bar {(err / bar).max():.3f}")
+    assert (err <= bar).all()
+    # the identity the kernel uses, on its own outputs
+    assert np.allclose(dg, 0.5 * (_cpu(vg) + (_cpu(mg) - fmu) ** 2), rtol=1e-12, atol=1e-15)
+
+
+def test_delta2_grid64(vup, orc):
+    _check_delta2(vup, orc, workloads.grid64())
+
+
+def test_delta2_grid1024_all(vup, orc):
+    _check_delta2(vup, orc, workloads.grid1024())
+
+
+@pytest.mark.parametrize("case", [c for c in RAGGED if c[7] == 1], ids=[c[0] for c in RAGGED
+                                                                         if c[7] == 1])
+def test_delta2_ragged(vup, orc, case):
+    name, n, lo, hi, model, theta, B, C, sr = case
+    wl = workloads.random_workload(name, n, lo, hi, model, B, 150, C, sr, seed=91, theta=theta)
+    _check_delta2(vup, orc, wl)
+
+
+def test_delta2_rejects_model_of_other_ndim(vup):
+    wl = workloads.grid64()
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    f = vup.eval_grid(g, wl.model)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B))
+    with pytest.raises(vup.VupError):
+        vup.moments(mm, wl.mu, wl.sigma, model="ring4")
 
 
 # ---------------------------------------------------------------------------
@@ -369,17 +492,20 @@ def test_backward_grid64_all(vup, orc):
     _grad_case(vup, orc, wl, np.arange(wl.K), 40)
 
 
-def test_backward_grid1024_sampled(vup, orc):
+def test_backward_grid1024_fd_subset(vup, orc):
+    """The 64 seeded locations of the finite-difference subset at 1024^2 (the
+    oracle's analytic gradient there is pinned against central differences on
+    the CPU)."""
     wl = workloads.grid1024()
-    _say("[backward grid1024 sampled]")
-    ks = workloads.fd_subset(wl.K, 24)
+    _say("[backward grid1024, 64-location subset]")
+    ks = workloads.fd_subset(wl.K, 64)
     _grad_case(vup, orc, wl, ks, 41)
 
 
 def test_backward_mixtures_4d_sampled(vup, orc):
     wl = workloads.grid48_4d()
     _say("[backward grid48_4d mixtures sampled]")
-    _grad_case(vup, orc, wl, workloads.sample_indices(wl.K, 16, 42), 42)
+    _grad_case(vup, orc, wl, workloads.sample_indices(wl.K, 256, 42), 42)
 
 
 def test_backward_ragged(vup, orc):
@@ -499,6 +625,25 @@ def test_separable_ipsa_example_full_size(vup, orc, s_l):
     Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(fo, eo), wl.B, sub.mu, sub.sigma,
                           n_sigma=wl.n_sigma)
     _check_P(_cpu(P)[ks], Po, 2e-5, f"P separable Sec. 5.3 example sigma_l={s_l}")
+
+
+def test_separable_1024_family_all_rows(vup, orc):
+    """The banded form on the full-size tensor-product family: 1024^2 grid on
+    [-3,3]^2, sincos model, B = 256, 256 x 256 locations on the midpoint
+    subgrid with one shared sigma = 0.25 per axis (U = 6.4e9), every one of
+    the 65 536 rows against the oracle, and against the general propagation
+    of the same distributions."""
+    n, lo, hi, B, M = (1024, 1024), (-3.0, -3.0), (3.0, 3.0), 256, 256
+    m = workloads.subgrid_midpoints(lo[0], hi[0], M)
+    s = np.full(M, 0.25)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "sincos2", B, m, m, s, s,
+                                           "1024^2 family, all rows")
+    _check_P(Pg, Po, 2e-5, "P separable 1024^2 family")
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+    Pgen, _ = vup.propagate(mm, mu, sg)
+    d = np.abs(Pg.astype(np.float64) - _cpu(Pgen)).sum(axis=1).max()
+    _say(f"  separable vs general kernel: max L1 {d:.2e}")
+    assert d <= 2e-5
 
 
 @pytest.mark.parametrize("case", SEP_PATHS, ids=[c[0] for c in SEP_PATHS])

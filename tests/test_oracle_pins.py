@@ -598,6 +598,61 @@ def test_reduced_precision_columns_still_sum_to_one(orc):
         assert np.abs(P - P64).sum(axis=1).max() <= tol
 
 
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2", "fp8e4m3"])
+def test_rounding_l1_bound_covers_perturbed_roundings(orc, precision):
+    """The bar of the reduced-precision comparisons: a propagation that rounds
+    each density from a value perturbed by a relative amount up to eps (and
+    normalises by its own rounded sum) stays within F = rounding_l1_bound of
+    the oracle's same-precision column, for random perturbations and for the
+    adversarial one that pushes every cell to the side where its rounding
+    changes most; the adversarial one reaches a good part of F, so the bound
+    is not vacuous. Densities, windows and the histogram are written out here
+    in numpy from their definitions (eq. gaussh, eq. (5))."""
+    n, lo, hi = (30, 26), (-3.0, -3.0), (3.0, 3.0)
+    wl = workloads.random_workload("flip", n, lo, hi, "sincos2", 20, 9, 2, (0.15, 0.6), seed=44)
+    f = orc.eval_grid(n, lo, hi, "sincos2")
+    e = orc.uniform_edges(f, wl.B)
+    b = orc.bins(f, e).reshape(n)
+    eps = 2.0 ** -10
+    Pq, _ = orc.propagate(n, lo, hi, b.ravel(), wl.B, wl.mu, wl.sigma, wl.weight,
+                          precision=precision)
+    F = orc.rounding_l1_bound(n, lo, hi, wl.mu, wl.sigma, wl.weight, precision=precision,
+                              eps=eps)
+    win, _, _ = orc.windows(n, lo, hi, wl.mu, wl.sigma)
+    x = [lo[d] + (np.arange(n[d]) + 0.5) * ((hi[d] - lo[d]) / n[d]) for d in range(2)]
+    rb = np.vectorize(orc.round_bf16)
+    r8 = np.vectorize(orc.round_e4m3)
+    quant = {"bf16": rb, "bf16x2": lambda v: rb(v) + rb(v - rb(v)),
+             "fp8e4m3": lambda v: r8(448.0 * v) / 448.0}[precision]
+    rng = np.random.default_rng(45)
+
+    def column(k, mode):
+        col = np.zeros(wl.B)
+        for c in range(wl.C):
+            (a0, b0), (a1, b1) = win[k, c]
+            t0 = (x[0][a0:b0 + 1] - wl.mu[k, c, 0]) / wl.sigma[k, c, 0]
+            t1 = (x[1][a1:b1 + 1] - wl.mu[k, c, 1]) / wl.sigma[k, c, 1]
+            w = np.exp(-0.5 * (t0[:, None] ** 2 + t1[None, :] ** 2))
+            if mode == "adversarial":
+                up, mid, dn = quant(w * (1 + eps)), quant(w), quant(w * (1 - eps))
+                q = np.where(np.abs(up - mid) >= np.abs(mid - dn), up, dn)
+            else:
+                q = quant(w * (1 + eps * rng.uniform(-1, 1, size=w.shape)))
+            h = np.bincount(b[a0:b0 + 1, a1:b1 + 1].ravel(), weights=q.ravel(),
+                            minlength=wl.B)
+            col += wl.weight[k, c] * h / q.sum()
+        return col
+
+    reach = 0.0
+    for k in range(wl.K):
+        for _ in range(3):
+            assert np.abs(column(k, "random") - Pq[k]).sum() <= F[k]
+        adv = np.abs(column(k, "adversarial") - Pq[k]).sum()
+        assert adv <= F[k]
+        reach = max(reach, adv / F[k])
+    assert reach > 0.2, reach
+
+
 def test_workload_generators_shapes():
     wl = workloads.grid1024()
     assert wl.mu.shape == (65536, 1, 2) and wl.sigma.min() >= 0.05 and wl.sigma.max() <= 0.5
