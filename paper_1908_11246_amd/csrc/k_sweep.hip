@@ -24,6 +24,8 @@
 // The input probability matrix is never materialised.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vup_device.hpp"
 #include "vup_internal.hpp"
 
@@ -250,19 +252,26 @@ __device__ __forceinline__ uint32_t map_at(const MapVec<SW>& m, int j) {
 // ===========================================================================
 // ---------------------------------------------------------------------------
 // Fixed-point histogram accumulation.
-// The density of a cell is the product go * gl of its row factor and its
-// fastest-axis factor. Cells are split into 3 x 3 magnitude classes by the row
-// factor (go >= 2^-4, >= 2^-8, smaller) and by the largest factor of their
-// strip; every class has its own LDS histogram and its own scale
-//     scale[rc][cc] = K / (qfac * rowbound[rc] * colmass[cc]),
-// where colmass is the exact factor sum of the strips in class cc, rowbound an
-// upper bound of the row factors' sum in class rc, qfac >= 1 the largest
-// relative increase of a density by the precision's rounding, and
-// K = 2^32 - 2^20 - (cells). A cell adds floor(w * scale + u) with a fixed
-// dither u = (j + 1/2)/SW that depends only on its position j in the strip, so
-// no class total can exceed 2^32: nothing overflows, tail cells keep a fine
-// quantum, and rounding is unbiased on average. Integer adds are exact, so
-// the result does not depend on scheduling.
+// Densities are accumulated as 32-bit fixed-point integers with integer LDS
+// atomics: exact, independent of scheduling, and not limited by the rate of
+// LDS float atomics. A component's scale is K / (qfac * bound of its mass),
+// K = 2^32 - 2^20 - (cells), qfac >= 1 the largest relative increase of a
+// density by the precision's rounding, so no total can overflow; a cell adds
+// floor(w * scale + u) with a fixed dither u in (0, 1), so rounding is unbiased
+// on average and cells below one quantum still count.
+// Cell form: the LDS holds NC copies of the histogram interleaved by bin (bin
+// b, copy c at word b NC + c); the cells of strip s (of SW fastest-axis cells)
+// in window row r go to copy (s + r cols) mod NC, cols being the strips a
+// workgroup walks side by side, so the NC lanes next to each other use NC
+// different copies and a wave's random bin addresses spread over the banks.
+// Each copy has its own scale from its exact mass, a cyclic convolution of the
+// strip masses by residue mod NC with the row-factor sums by residue (which
+// factor over the axes), so its quantum is about 1/NC of the component's. The
+// dither is a 16-row by SW-column ordered pattern, u = j/SW + (r mod 16 +
+// 1/2) / (16 SW), whose 16 SW values over a block are all distinct, so in a
+// smooth region the rounding bias averages to at most 1/(32 SW) quantum.
+// Run form: three classes by the row factor (>= 2^-4, >= 2^-8, smaller), one
+// stacked histogram each, and a per-thread dither (see below).
 // ---------------------------------------------------------------------------
 constexpr float kClassT1 = 0.0625f;      // 2^-4
 constexpr float kClassT2 = 0.00390625f;  // 2^-8
@@ -276,13 +285,6 @@ __host__ __device__ constexpr double prec_qfac() {
   return PREC == VUP_BF16 ? 1.0 + 1.0 / 256 : PREC == VUP_BF16X2 ? 1.0 + 1.0 / 65536
          : PREC == VUP_FP8E4M3 ? 1.125 : 1.0 + 1.0 / 1048576;
 }
-
-// per-component scales shared by all threads (LDS)
-struct PropScales {
-  float srow[3];
-  float scol[3];
-  double unscale[9];  // 1 / scale of each class (FP64)
-};
 
 // the model matrix's run form is used for this propagation (FP32 densities):
 // forced by the sweep mode, or chosen when runs along the fastest axis are at
@@ -312,131 +314,245 @@ __device__ __forceinline__ double row_mass(const SweepArgs& a, const float* smem
   return Zrows;
 }
 
-template <int PREC>
-__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
-                                            int sw, double* red, PropScales* ps) {
+// Factor tables of the cell-form propagation: every axis' factors from the
+// FP64 exponential, each rounded once to FP32. Outer axes d < D-1:
+// tab_d[i] = g_d(lo_d + i), i < W_d. Fastest axis: tab_L[jj] for jj < ns*sw,
+// cell colbase + jj, zero outside the window.
+// exp(a) for a <= 0 in FP64 with few registers: a = n ln2 + r, |r| <= ln2/2,
+// ln 2 split in a head and a tail (Cody and Waite's argument reduction), and
+// exp(r) by its Taylor series to degree 11 (truncation below 3e-13 relative),
+// so the FP32 rounding of the result is the correctly rounded value except
+// within about 2^-40 of a rounding tie.
+__device__ __forceinline__ double exp_nonpos(double a) {
+  if (a < -745.0) return 0.0;
+  const double n = rint(a * 1.4426950408889634);     // a / ln 2
+  double r = fma(-n, 0.6931471805599453, a);          // ln 2, head
+  r = fma(-n, 2.3190468138462996e-17, r);             // ln 2, tail
+  double p = 1.0 / 39916800.0;                        // 1/11!
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ float gauss_factor_exact(double x, double mu, double rsig) {
+  const double t = (x - mu) * rsig;
+  return (float)exp_nonpos(-0.5 * (t * t));
+}
+
+__device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* smem, const Win& w,
+                                                   long long kc, int sw, int colbase, int ns) {
   const int D = a.g.ndim;
-  const float* tabL = smem + pick4(a.L.tab_off, D - 1);
-  // column classes: by the largest factor of each strip
-  double cm[3] = {0.0, 0.0, 0.0};
-  for (int st = threadIdx.x; st < ns; st += kThreads) {
-    float gmax = 0.0f;
-    double sum = 0.0;
-    for (int j = 0; j < sw; ++j) {
-      const float g = tabL[st * sw + j];
-      gmax = fmaxf(gmax, g);
-      sum += (double)g;
-    }
-    const int cc = mag_class(gmax);
-    cm[0] += cc == 0 ? sum : 0.0;
-    cm[1] += cc == 1 ? sum : 0.0;
-    cm[2] += cc == 2 ? sum : 0.0;
-  }
-  double colmass[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) colmass[c] = block_sum(cm[c], red);
-  // row factor sum bound per class: total row mass, and rows * class ceiling
-  const double Zrows = row_mass(a, smem, w, red);
-  const double R = (double)w.R;
-  const double cells = R * (double)(ns * sw);
-  double K = 4294967296.0 - 1048576.0 - cells;
-  if (PREC == VUP_FP8E4M3) K *= 0.5;  // subnormal rounding of tiny values
-  if (threadIdx.x == 0) {
-    if (a.L.ncls > 1) {
-      const double rowbound[3] = {Zrows, fmin(Zrows, R * (double)kClassT1),
-                                  fmin(Zrows, R * (double)kClassT2)};
-      for (int r = 0; r < 3; ++r) ps->srow[r] = (float)(K / (prec_qfac<PREC>() * rowbound[r]));
-      for (int c = 0; c < 3; ++c) ps->scol[c] = colmass[c] > 0.0 ? (float)(1.0 / colmass[c]) : 0.0f;
-    } else {
-      // a single class: one scale for the whole window
-      const double cmass = colmass[0] + colmass[1] + colmass[2];
-      for (int r = 0; r < 3; ++r) ps->srow[r] = (float)(K / (prec_qfac<PREC>() * Zrows));
-      for (int c = 0; c < 3; ++c) ps->scol[c] = (float)(1.0 / cmass);
+  for (int d = 0; d < 3; ++d) {
+    if (d + 1 < D) {
+      float* tab = smem + a.L.tab_off[d];
+      const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
+      for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+        tab[i] = gauss_factor_exact(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                    rsig);
     }
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c)
-        ps->unscale[r * 3 + c] =
-            ps->scol[c] > 0.0f ? 1.0 / ((double)ps->srow[r] * (double)ps->scol[c]) : 0.0;
+  }
+  const int L = D - 1;
+  int loL, WL;
+  last_axis(w, D, loL, WL);
+  float* tab = smem + pick4(a.L.tab_off, L);
+  const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
+  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+    const int j = colbase + jj;
+    float v = 0.0f;
+    if (j >= loL && j < loL + WL)
+      v = gauss_factor_exact(cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j),
+                             mu, rsig);
+    tab[jj] = v;
   }
 }
 
-// Row table of the propagation: (go, go * srow[class], map offset, class).
-__device__ __forceinline__ void build_rows_prop(const SweepArgs& a, float* smem, const Win& w,
-                                                long long r0, int rc, const PropScales* ps) {
+// per-copy scales of the cell form, shared by all threads (LDS)
+struct PropScales {
+  double scale[16];    // fixed-point units per unit of density, per copy
+  double unscale[16];  // 1 / scale (0 for a copy without cells)
+  float scalef[16];    // scale rounded to FP32
+};
+constexpr int kPropScalesFloats = (int)(sizeof(PropScales) / sizeof(float));
+constexpr int kPropScaleScratch = 16 + 16 + 256 + 16;  // doubles: A, G, partials, S
+
+// Exact mass of each histogram copy of component kc (the copy of strip s in
+// window row r is (s + r cols) mod nc) and its scale K / (qfac mass). With A[a]
+// the factor mass of the strips s = a (mod nc) and S[b] the row-factor mass of
+// the rows r = b (mod nc), copy c holds the sum over a + b cols = c (mod nc) of
+// A[a] S[b]. Rows are flat indices over the slower axes (axis 0 slowest), so
+// with x the last slower axis (W_x cells), row r = o W_x + i_x and
+// S[b] = sum over the outer rows o of go(o) G[(b - o W_x) mod nc], G[e] the
+// sum of axis x's factors at i_x = e (mod nc). FP64, in a fixed order. The
+// row table's LDS serves as scratch (it is rebuilt after this).
+template <int PREC>
+__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
+                                            int sw, int cols, PropScales* ps) {
+  static_assert(kThreads == 256, "256 partial sums");
   const int D = a.g.ndim;
-  float4* rt = reinterpret_cast<float4*>(smem + a.L.row_off);
+  const int nc = a.L.cpw;
+  const int t = threadIdx.x;
+  double* scr = reinterpret_cast<double*>(smem + a.L.row_off);
+  double* A = scr;           // [16] strip masses by residue
+  double* G = scr + 16;      // [16] axis x's factor sums by residue
+  double* part = scr + 32;   // [256] partial row sums
+  double* S = scr + 288;     // [16] row-factor masses by residue
+  const float* tabL = smem + pick4(a.L.tab_off, D - 1);
+  const int Wx = D > 1 ? pick4(w.W, D - 2) : 1;
+  if (t < nc) {
+    double sa = 0.0;
+    for (int st = t; st < ns; st += nc)
+      for (int j = 0; j < sw; ++j) sa += (double)tabL[st * sw + j];
+    A[t] = sa;
+    double sg = 0.0;
+    if (D > 1) {
+      const float* tx = smem + pick4(a.L.tab_off, D - 2);
+      for (int i = t; i < Wx; i += nc) sg += (double)tx[i];
+    } else {
+      sg = t == 0 ? 1.0 : 0.0;  // one row, r = 0, of factor 1
+    }
+    G[t] = sg;
+  }
+  __syncthreads();
+  // thread t: residue b = t mod nc, outer rows o = t / nc + k (256 / nc)
+  // outer rows (window rows number below 2^31): 4-D walks (i0, i1) with a
+  // carry instead of dividing
+  const int outer = D > 1 ? (int)(w.R / Wx) : 1;
+  const int b = t & (nc - 1), per = kThreads / nc;
+  double sp = 0.0;
+  const int W1 = D == 4 ? w.W[1] : 1;
+  int o = t / nc;
+  int i0 = o / W1, i1 = o - i0 * W1;
+  const int s0 = per / W1, s1 = per - s0 * W1;  // the step per in (i0, i1)
+  for (; o < outer; o += per) {
+    double go = 1.0;
+    if (D >= 3) go = (double)smem[a.L.tab_off[0] + i0];
+    if (D == 4) go *= (double)smem[a.L.tab_off[1] + i1];
+    sp += go * G[(int)(((unsigned)b - (unsigned)o * (unsigned)Wx) & (unsigned)(nc - 1))];
+    i1 += s1;
+    i0 += s0;
+    if (i1 >= W1) {
+      i1 -= W1;
+      ++i0;
+    }
+  }
+  part[t] = sp;
+  __syncthreads();
+  if (t < nc) {
+    double sb = 0.0;
+    for (int k = t; k < kThreads; k += nc) sb += part[k];
+    S[t] = sb;
+  }
+  __syncthreads();
+  const double cells = (double)w.R * (double)(ns * sw);
+  double K = 4294967296.0 - 1048576.0 - cells;
+  if (PREC == VUP_FP8E4M3) K *= 0.5;  // subnormal rounding can more than double tiny values
+  // U[d] = sum of S[b] over b cols = d (mod nc); copy c holds
+  // sum over a of A[a] U[(c - a) mod nc]
+  double* U = part;  // the partials are consumed
+  if (t < nc) {
+    double u = 0.0;
+    for (int bb = 0; bb < nc; ++bb)
+      if (((bb * cols) & (nc - 1)) == t) u += S[bb];
+    U[t] = u;
+  }
+  __syncthreads();
+  if (t < nc) {
+    double m = 0.0;
+    for (int aa = 0; aa < nc; ++aa) m += A[aa] * U[(t - aa) & (nc - 1)];
+    const double sc = m > 0.0 ? K / (prec_qfac<PREC>() * m) : 0.0;
+    ps->scale[t] = sc;
+    ps->unscale[t] = sc > 0.0 ? 1.0 / sc : 0.0;
+    ps->scalef[t] = (float)sc;
+  }
+  __syncthreads();
+}
+
+// Row table of the cell form: (go, map offset), with the row factor go the
+// product of the slower axes' factors taken in FP64 and rounded once.
+__device__ __forceinline__ void build_rows_prop(const SweepArgs& a, float* smem, const Win& w,
+                                                long long r0, int rc) {
+  const int D = a.g.ndim;
+  float2* rt = reinterpret_cast<float2*>(smem + a.L.row_off);
   for (int r = threadIdx.x; r < rc; r += kThreads) {
     int t = (int)r0 + r;
-    float go = 1.0f;
+    double go = 1.0;
     int off = 0;  // the padded bin map has fewer than 2^31 elements
 #pragma unroll
     for (int d = 2; d >= 0; --d) {
       if (d <= D - 2) {
         const int i = d == 0 ? t : t % w.W[d];
         if (d > 0) t /= w.W[d];
-        go *= smem[a.L.tab_off[d] + i];
+        go *= (double)smem[a.L.tab_off[d] + i];
         off += (w.lo[d] + i) * (int)a.g.rowstride[d];
       }
     }
-    const int cls = a.L.ncls > 1 ? mag_class(go) : 0;
-    rt[r] = make_float4(go, go * ps->srow[cls], __int_as_float(off), __int_as_float(cls));
+    rt[r] = make_float2((float)go, __int_as_float(off));
   }
 }
 
 template <int SW, int PREC>
-__device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int rc, int colbase,
-                                          int ns, const PropScales* ps) {
+__device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r0, int rc,
+                                          int colbase, int ns, const PropScales* ps) {
   const int cols = ns < kThreads ? ns : kThreads;
   const int P0 = kThreads / cols;
   const int col = threadIdx.x % cols;
   const int ph = threadIdx.x / cols;
   if (ph >= P0) return;
-  const float4* rt = reinterpret_cast<const float4*>(smem + a.L.row_off);
-  const int cpc = a.L.cpw;  // copies per class
-  const int strideb = a.L.hist_stride * 4;
-  // byte offset between row classes (3 column classes x cpc copies each)
-  const int rcstep = 3 * cpc * strideb;
-  char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off) + (ph & (cpc - 1)) * strideb;
+  const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
+  const int cm = a.L.cpw - 1;     // copies - 1 (a power of two minus one)
+  const int cshift = a.L.cshift;  // byte offset of (bin, copy): (4 bin) << cshift + 4 copy
+  char* hist = reinterpret_cast<char*>(smem + a.L.hist_off);
   const float* tabL = smem + pick4(a.L.tab_off, a.g.ndim - 1);
   for (int s = col; s < ns; s += cols) {
     float gl[SW];
-    float gmax = 0.0f;
 #pragma unroll
-    for (int j = 0; j < SW; ++j) {
-      gl[j] = tabL[s * SW + j];
-      gmax = fmaxf(gmax, gl[j]);
-    }
-    const int cc = a.L.ncls > 1 ? mag_class(gmax) : 0;
-    const float scol = ps->scol[cc];
-    char* lh = hbase + cc * cpc * strideb;
+    for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
     const uint16_t* mbase = a.binmap + colbase + s * SW;
-    // one row of the strip: the row entry and the strip's bin codes
     struct Row {
-      float4 e;
+      float2 e;
+      float sc;  // scale of the strip-row's copy
       MapVec<SW> mv;
+    };
+    // the copy of strip s in window row r0 + r: (s + (r0 + r) cols) mod nc
+    auto copy_of = [&](int r) {
+      return (int)(((unsigned)(r0 + r) * (unsigned)cols + (unsigned)s) & (unsigned)cm);
     };
     auto load = [&](int r, Row& x) {
       x.e = rt[r];
-      x.mv = load_map<SW>(mbase + (unsigned)__float_as_int(x.e.z));
+      x.sc = ps->scalef[copy_of(r)];
+      x.mv = load_map<SW>(mbase + (unsigned)__float_as_int(x.e.y));
     };
-    auto accumulate = [&](const Row& x) {
-      const int rcl = a.L.ncls > 1 ? __float_as_int(x.e.w) : 0;
-      char* lr = lh + rcl * rcstep;
-      const float gos = x.e.y * scol;
-      float qs = 0.0f;
-      if constexpr (PREC != VUP_FP32) {
-        qs = ps->srow[rcl] * scol * (PREC == VUP_FP8E4M3 ? (1.0f / 448.0f) : 1.0f);
+    auto accumulate = [&](int r, const Row& x) {
+      // this strip-row's copy and its scale; the ordered dither's row part
+      char* hb = hist + 4 * copy_of(r);
+      const float sc = x.sc;
+      const float ub = ((float)(r & 15) + 0.5f) * (1.0f / (16.0f * (float)SW));
+      float gos = 0.0f, qs = 0.0f;
+      if constexpr (PREC == VUP_FP32) {
+        gos = x.e.x * sc;
+      } else {
+        qs = sc * (PREC == VUP_FP8E4M3 ? (1.0f / 448.0f) : 1.0f);
       }
 #pragma unroll
       for (int j = 0; j < SW; ++j) {
-        const float u = ((float)j + 0.5f) * (1.0f / (float)SW);
+        const float u = (float)j * (1.0f / (float)SW) + ub;
         float v;
         if constexpr (PREC == VUP_FP32) {
           v = fmaf(gos, gl[j], u);
         } else {
           v = fmaf(quantize<PREC>(x.e.x * gl[j]), qs, u);
         }
-        uint32_t* slot = reinterpret_cast<uint32_t*>(lr + map_at<SW>(x.mv, j));
+        uint32_t* slot = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j) << cshift));
         __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     };
@@ -449,19 +565,64 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
     for (;;) {
       const int r2 = r + P0;
       if (r2 < rc) load(r2, rb);
-      accumulate(ra);
+      accumulate(r, ra);
       if (r2 >= rc) break;
       r = r2 + P0;
       if (r < rc) load(r, ra);
-      accumulate(rb);
+      accumulate(r2, rb);
       if (r >= rc) break;
     }
   }
 }
 
-// Unscale the class histograms of component kc, normalise by the sum over all
-// slots (cells without a bin included) and add the weighted column into Pk.
-// Histogram copy i of class cl sits at hist + (cl * cpc + i) * stride.
+// Unscale the interleaved histogram copies of component kc (bin b, copy c at
+// word b nc + c), normalise by the sum over all slots (cells without a bin
+// included) and add the weighted column into Pk.
+__device__ __forceinline__ void finish_cells(const SweepArgs& a, const uint32_t* hist, int nc,
+                                             const double* unscale, double* red, long long kc,
+                                             float* Pk, bool written) {
+  const int B = a.B;
+  auto slot = [&](int b) {
+    double v = 0.0;
+    const uint32_t* h = hist + (size_t)b * nc;
+    if (nc >= 4) {
+      for (int c = 0; c < nc; c += 4) {
+        const uint4 q = *reinterpret_cast<const uint4*>(h + c);
+        v += (double)q.x * unscale[c] + (double)q.y * unscale[c + 1] +
+             (double)q.z * unscale[c + 2] + (double)q.w * unscale[c + 3];
+      }
+    } else {
+      for (int c = 0; c < nc; ++c) v += (double)h[c] * unscale[c];
+    }
+    return v;
+  };
+  const double wk = (a.d.C > 1) ? a.d.weight[kc] : 1.0;
+  if (B + 1 <= 2 * kThreads) {
+    const int b0 = threadIdx.x, b1 = threadIdx.x + kThreads;
+    const double v0 = b0 <= B ? slot(b0) : 0.0;
+    const double v1 = b1 <= B ? slot(b1) : 0.0;
+    const double Zc = block_sum(v0 + v1, red);
+    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+    const double f = wk / Zc;
+    if (b0 < B) Pk[b0] = (float)((written ? (double)Pk[b0] : 0.0) + v0 * f);
+    if (b1 < B) Pk[b1] = (float)((written ? (double)Pk[b1] : 0.0) + v1 * f);
+    return;
+  }
+  double zpart = 0.0;
+  for (int b = threadIdx.x; b <= B; b += kThreads) zpart += slot(b);
+  const double Zc = block_sum(zpart, red);
+  if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+  const double f = wk / Zc;
+  for (int b = threadIdx.x; b < B; b += kThreads) {
+    const double prev = written ? (double)Pk[b] : 0.0;
+    Pk[b] = (float)(prev + slot(b) * f);
+  }
+}
+
+// Run form: unscale the class histograms of component kc, normalise by the
+// sum over all slots (cells without a bin included) and add the weighted
+// column into Pk. Histogram copy i of class cl sits at hist + (cl * cpc + i) *
+// stride.
 __device__ __forceinline__ void finish_component(const SweepArgs& a, const uint32_t* hist, int ncls,
                                                  int cpc, const double* unscale, double* red,
                                                  long long kc, float* Pk, bool written) {
@@ -512,17 +673,18 @@ __device__ __forceinline__ void finish_column(const SweepArgs& a, float* Pk, boo
   }
 }
 
+// four waves per SIMD: the occupancy the cell form's LDS allows (about 40 KB
+// per workgroup), so the kernel is held to 128 VGPRs
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, 4) void k_propagate(SweepArgs a) {
   extern __shared__ float smem[];
   if (PREC == VUP_FP32 && runs_chosen(a)) return;  // k_propagate_runs does the work
   const long long k = block_k(a);
   if (k >= a.d.K) return;
   const int D = a.g.ndim;
-  const int ncls = a.L.ncls;
-  const int cpc = a.L.cpw;
+  const int nc = a.L.cpw;
   double* red = reinterpret_cast<double*>(smem + a.L.red_off);
-  PropScales* ps = reinterpret_cast<PropScales*>(red + 16);
+  PropScales* ps = reinterpret_cast<PropScales*>(smem + a.L.red_off + 96);
   const uint32_t* hist = reinterpret_cast<const uint32_t*>(smem + a.L.hist_off);
   float* Pk = a.P + k * (long long)a.B;
   bool anybad = false;
@@ -545,24 +707,28 @@ __global__ __launch_bounds__(kThreads) void k_propagate(SweepArgs a) {
     const int colbase = (loL / sw) * sw;
     const int ns = (loL + WL - 1) / sw - loL / sw + 1;
     __syncthreads();  // LDS reuse across components
-    build_tables(a, smem, w, kc, sw, colbase, ns);
-    for (int i = threadIdx.x; i < ncls * cpc * a.L.hist_stride; i += kThreads)
-      smem[a.L.hist_off + i] = 0.0f;
+    build_tables_exact(a, smem, w, kc, sw, colbase, ns);
+    {
+      uint4* h4 = reinterpret_cast<uint4*>(smem + a.L.hist_off);
+      for (int i = threadIdx.x; i < a.L.hist_stride / 4; i += kThreads)
+        h4[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
     __syncthreads();
-    prop_scales<PREC>(a, smem, w, ns, sw, red, ps);
-    for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
-      const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
+    prop_scales<PREC>(a, smem, w, ns, sw, ns < kThreads ? ns : kThreads, ps);
+    const int rr = a.L.rrows;
+    for (long long r0 = 0; r0 < w.R; r0 += rr) {
+      const int rc = (int)((w.R - r0) < rr ? (w.R - r0) : rr);
       __syncthreads();
-      build_rows_prop(a, smem, w, r0, rc, ps);
+      build_rows_prop(a, smem, w, r0, rc);
       __syncthreads();
       switch (sw) {
-        case 4: prop_rows<4, PREC>(a, smem, rc, colbase, ns, ps); break;
-        case 8: prop_rows<8, PREC>(a, smem, rc, colbase, ns, ps); break;
-        default: prop_rows<16, PREC>(a, smem, rc, colbase, ns, ps); break;
+        case 4: prop_rows<4, PREC>(a, smem, (int)r0, rc, colbase, ns, ps); break;
+        case 8: prop_rows<8, PREC>(a, smem, (int)r0, rc, colbase, ns, ps); break;
+        default: prop_rows<16, PREC>(a, smem, (int)r0, rc, colbase, ns, ps); break;
       }
     }
     __syncthreads();
-    finish_component(a, hist, ncls, cpc, ps->unscale, red, kc, Pk, written);
+    finish_cells(a, hist, nc, ps->unscale, red, kc, Pk, written);
     written = true;
   }
   finish_column(a, Pk, anybad, written);
@@ -1597,10 +1763,12 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out, in
   }
   off = round_up(off, 4);
   L.row_off = off;
-  off += kind == kSweepRuns
-             ? 4 * L.rrows
-             : kind == kSweepBwdRuns ? 8 * kBwdRowChunk
-                                     : (kind == kSweepPropagate ? 4 : 2) * kRowChunk;
+  if (kind == kSweepPropagate) L.rrows = kPropRowChunk;
+  // (the cell form's row table, 2 floats per row, is also the scratch of its
+  // per-copy scales: kPropScaleScratch doubles)
+  off += kind == kSweepRuns ? 4 * L.rrows
+         : kind == kSweepPropagate ? round_up(std::max(2 * L.rrows, 2 * kPropScaleScratch), 4)
+         : kind == kSweepBwdRuns ? 8 * kBwdRowChunk : 2 * kRowChunk;
   L.trow_off = -1;
   if (kind == kSweepBackward) {
     L.trow_off = off;
@@ -1611,26 +1779,21 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out, in
   L.cpw = 0;
   L.ncls = 1;
   if (kind == kSweepPropagate) {
-    // stride = 1 mod 32 so consecutive copies shift banks by one
-    const int stride = round_up(B + 1, 32) + 1;
-    L.hist_stride = stride;
-    const int budget = 48 * 1024 / 4 - 64;
-    const int opts[5][2] = {{9, 2}, {9, 1}, {1, 4}, {1, 2}, {1, 1}};
-    int pick = 4;
-    for (int i = 0; i < 5; ++i)
-      if (off + opts[i][0] * opts[i][1] * stride <= budget) {
-        pick = i;
-        break;
-      }
-    if (pick == 4)  // nothing fits the occupancy budget: take the richest that fits at all
-      for (int i = 0; i < 5; ++i)
-        if (off + opts[i][0] * opts[i][1] * stride <= 160 * 1024 / 4 - 64) {
-          pick = i;
-          break;
-        }
-    L.ncls = opts[pick][0];
-    L.cpw = opts[pick][1];
-    off += L.ncls * L.cpw * stride;
+    // NC histogram copies interleaved by bin: the most (up to 16) that keep a
+    // workgroup within about 40 KB of LDS (four workgroups per CU), else the
+    // most that fit at all; hist_stride holds the words to clear (NC (B + 1)
+    // rounded up to a multiple of four, for 16-byte stores)
+    const int budget = 40 * 1024 / 4 - 96 - kPropScalesFloats;
+    int nc = 16;
+    while (nc > 1 && off + round_up(nc * (B + 1), 4) > budget) nc /= 2;
+    while (nc > 1 && off + round_up(nc * (B + 1), 4) > 160 * 1024 / 4 - 96 - kPropScalesFloats)
+      nc /= 2;
+    L.ncls = 1;
+    L.cpw = nc;
+    L.cshift = 0;
+    while ((1 << L.cshift) < nc) ++L.cshift;
+    L.hist_stride = round_up(nc * (B + 1), 4);
+    off += L.hist_stride;
   } else if (kind == kSweepRuns) {
     // three row classes, one copy each
     const int stride = round_up(B + 1, 32) + 1;
@@ -1649,6 +1812,7 @@ bool sweep_layout(const vup_grid& g, int B, SweepKind kind, SweepLayout* out, in
   off = round_up(off, 4);
   L.red_off = off;
   off += 96;  // 16 doubles of reduction scratch, per-component scales, window ints
+  if (kind == kSweepPropagate) off += round_up(kPropScalesFloats, 4);  // per-copy scales
   L.bytes = (size_t)off * 4;
   *out = L;
   return L.bytes <= 160 * 1024;

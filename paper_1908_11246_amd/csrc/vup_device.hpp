@@ -18,6 +18,8 @@ constexpr int kRowChunk = 512;    // rows of the row table held in LDS at once
 // eight workgroups (eight waves per SIMD, the kernel held to 64 VGPRs) fit on
 // a CU; with fewer distributions than resident workgroups, 512 (fewer passes)
 constexpr int kRunRowChunk = 256;
+// rows per row-table pass of the cell-form propagation (16-byte entries, 4 KB)
+constexpr int kPropRowChunk = 256;
 constexpr int kMaxSW = 16;        // widest strip of the fastest axis
 constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
 

@@ -17,12 +17,13 @@ struct SweepLayout {
   int tab_off[4];
   int cap[4];
   int row_off;      // row table: [rrows] / [kBwdRowChunk] entries in the run forms, [kRowChunk] in the cell forms
-  int rrows;        // rows per row-table pass of the run-form propagation
+  int rrows;        // rows per row-table pass of the propagation (run and cell forms)
   int trow_off;     // float4[kRowChunk] (backward only, else -1)
   int hist_off;     // histogram copies (propagate) or v table (backward)
-  int hist_stride;  // floats per histogram copy
-  int cpw;          // histogram copies per magnitude class
-  int ncls;         // magnitude classes (9, or 1 when LDS is short; 3 in the run form)
+  int hist_stride;  // floats per histogram copy (run form); words of all copies (cell form)
+  int cpw;          // histogram copies (cell form: interleaved by bin, a power of two)
+  int cshift;       // log2(cpw) (cell form)
+  int ncls;         // magnitude classes (1 in the cell form, 3 in the run form)
   int red_off;      // double scratch
   int g_off;        // FP64 prefix sums of the fastest-axis factors (run form)
   size_t bytes;

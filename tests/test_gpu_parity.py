@@ -281,13 +281,14 @@ def test_determinism(vup):
 # Reduced-precision bars. The oracle's reduced-precision variant rounds every
 # density with the same rule as the kernel (RNE to BF16, the BF16 hi + lo
 # pair, or E4M3 of 448 w) and normalises by the sum of the same rounded
-# values. The kernel rounds the FP32 product of FP32 per-axis factors: each
-# factor is within 2 FP32 ulps of exp (the exponential of the head of an FP64
-# argument, times one plus its tail), and d factors take d - 1 products (and
-# one more for E4M3's scale of 448), so the value rounded is within
-# 2d + d/2 <= 10 ulps (6e-7) of the exact density; EPS_DENSITY = 2^-19
-# (1.9e-6) leaves a factor of three. A cell can therefore round differently
-# only if its exact density lies within EPS_DENSITY of a rounding midpoint;
+# values. The kernel rounds an FP32 density built from per-axis factors that
+# are each the FP64 exponential rounded once to FP32 (0.5 ulp): the row factor
+# is their product over the slower axes taken in FP64 and rounded once, then
+# multiplied by the fastest axis' factor in FP32 (and by 448 for E4M3), so the
+# value rounded is within (d - 1)/2 + 1/2 + 1/2 + 1/2 + 1/2 <= 3.5 ulps
+# (2.1e-7) of the exact density for d <= 4; EPS_DENSITY = 2^-21 (4.8e-7)
+# leaves a factor of two. A cell can therefore round differently only if its
+# exact density lies within EPS_DENSITY of a rounding midpoint;
 # orc.rounding_l1_bound sums, per column, how far such cells can move the
 # normalised column (pinned on the CPU against random and adversarial
 # perturbations). The bar against the same-precision oracle is that bound
@@ -295,7 +296,7 @@ def test_determinism(vup):
 # oracle's own rounding error of the column (itself pinned against the
 # worst-case bound 2u).
 TOL_ACCUM = 2e-5
-EPS_DENSITY = 2.0 ** -19
+EPS_DENSITY = 2.0 ** -21
 
 
 def _binned_reduced(mg, vg, mq, vq, Pq, Pg, bar_l1, e, label):
