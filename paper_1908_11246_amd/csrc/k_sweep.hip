@@ -477,26 +477,83 @@ __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, con
   __syncthreads();
 }
 
-// Row table of the cell form: (go, map offset), with the row factor go the
-// product of the slower axes' factors taken in FP64 and rounded once.
+// Window row r of the cell form as mixed-radix digits over the slower axes
+// (axis 0 slowest, axis D-2 the least significant digit). A thread starts at
+// its first row with one division per axis and then steps by kThreads rows
+// with carries, so the row table is built without dividing.
+struct RowIt {
+  int i[3];
+};
+
+__device__ __forceinline__ void rowit_init(RowIt& it, long long r, const Win& w, int D) {
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    it.i[d] = 0;
+    if (d <= D - 2) {
+      if (d > 0) {
+        it.i[d] = (int)(r % w.W[d]);
+        r /= w.W[d];
+      } else {
+        it.i[d] = (int)r;
+      }
+    }
+  }
+}
+
+// digits of the step kThreads (uniform)
+__device__ __forceinline__ RowIt rowit_step_digits(const Win& w, int D) {
+  RowIt s;
+  long long r = kThreads;
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    s.i[d] = 0;
+    if (d <= D - 2) {
+      if (d > 0) {
+        s.i[d] = (int)(r % w.W[d]);
+        r /= w.W[d];
+      } else {
+        s.i[d] = (int)r;
+      }
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ void rowit_step(RowIt& it, const RowIt& s, const Win& w, int D) {
+  int carry = 0;
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d <= D - 2) {
+      it.i[d] += s.i[d] + carry;
+      carry = 0;
+      if (d > 0 && it.i[d] >= w.W[d]) {  // i + step + carry < 2 W: one wrap at most
+        it.i[d] -= w.W[d];
+        carry = 1;
+      }
+    }
+  }
+}
+
+// Row table of the cell form for rows [r0, r0 + rc): (go, map offset), with
+// the row factor go the product of the slower axes' factors taken in FP64 and
+// rounded once. Thread t holds the digits of row r0 + t and advances them by
+// kThreads per row it builds (chunks are multiples of kThreads rows).
 __device__ __forceinline__ void build_rows_prop(const SweepArgs& a, float* smem, const Win& w,
-                                                long long r0, int rc) {
+                                                int rc, RowIt& it, const RowIt& step) {
   const int D = a.g.ndim;
   float2* rt = reinterpret_cast<float2*>(smem + a.L.row_off);
   for (int r = threadIdx.x; r < rc; r += kThreads) {
-    int t = (int)r0 + r;
     double go = 1.0;
     int off = 0;  // the padded bin map has fewer than 2^31 elements
 #pragma unroll
-    for (int d = 2; d >= 0; --d) {
+    for (int d = 0; d < 3; ++d) {
       if (d <= D - 2) {
-        const int i = d == 0 ? t : t % w.W[d];
-        if (d > 0) t /= w.W[d];
-        go *= (double)smem[a.L.tab_off[d] + i];
-        off += (w.lo[d] + i) * (int)a.g.rowstride[d];
+        go *= (double)smem[a.L.tab_off[d] + it.i[d]];
+        off += (w.lo[d] + it.i[d]) * (int)a.g.rowstride[d];
       }
     }
     rt[r] = make_float2((float)go, __int_as_float(off));
+    rowit_step(it, step, w, D);
   }
 }
 
@@ -716,10 +773,13 @@ __global__ __launch_bounds__(kThreads, 4) void k_propagate(SweepArgs a) {
     __syncthreads();
     prop_scales<PREC>(a, smem, w, ns, sw, ns < kThreads ? ns : kThreads, ps);
     const int rr = a.L.rrows;
+    RowIt it;
+    rowit_init(it, threadIdx.x, w, D);
+    const RowIt step = rowit_step_digits(w, D);
     for (long long r0 = 0; r0 < w.R; r0 += rr) {
       const int rc = (int)((w.R - r0) < rr ? (w.R - r0) : rr);
       __syncthreads();
-      build_rows_prop(a, smem, w, r0, rc);
+      build_rows_prop(a, smem, w, rc, it, step);
       __syncthreads();
       switch (sw) {
         case 4: prop_rows<4, PREC>(a, smem, (int)r0, rc, colbase, ns, ps); break;

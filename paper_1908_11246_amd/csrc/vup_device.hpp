@@ -18,8 +18,10 @@ constexpr int kRowChunk = 512;    // rows of the row table held in LDS at once
 // eight workgroups (eight waves per SIMD, the kernel held to 64 VGPRs) fit on
 // a CU; with fewer distributions than resident workgroups, 512 (fewer passes)
 constexpr int kRunRowChunk = 256;
-// rows per row-table pass of the cell-form propagation (16-byte entries, 4 KB)
-constexpr int kPropRowChunk = 256;
+// rows per row-table pass of the cell-form propagation (8-byte entries, 4 KB;
+// a multiple of the workgroup size, as its row builder steps by whole
+// workgroups)
+constexpr int kPropRowChunk = 512;
 constexpr int kMaxSW = 16;        // widest strip of the fastest axis
 constexpr int kMaxBinsPerThread = (VUP_MAX_BINS + 1 + kThreads - 1) / kThreads;
 
