@@ -244,8 +244,10 @@ size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My);
  * conventions as vup_propagate with K = M[0]*M[1], ncomp = 1 (Z[k] =
  * Zx[mx] * Zy[my], the window mass). T is built from the model matrix's runs
  * of equal bin along y (one difference of FP64 prefix sums per run). Families
- * with M[1] < 16 (e.g. one shared alpha factor) tile the contraction over
- * bins instead of over my. Needs ndim == 2, and B <= 512 when n[1] > 65534.
+ * with M[1] < 16 (e.g. one shared alpha factor) are too narrow for the
+ * contraction's tiles and are propagated by the general sweep of
+ * vup_propagate (FP32) instead, with the same outputs. Needs ndim == 2, and
+ * B <= 512 when n[1] > 65534.
  *   ws: dev, 256-byte aligned, ws_bytes >= vup_separable_workspace_bytes.
  * ------------------------------------------------------------------------ */
 int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, size_t ws_bytes,

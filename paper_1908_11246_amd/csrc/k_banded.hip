@@ -15,11 +15,16 @@
 //                    once (rows up to 4096 cells)
 //   k_sep_runs       the same with read-modify-writes of T (rows up to 65534)
 //   k_sep_scatter    T cell by cell (longer rows): one wave per (ix, 64 my),
-//                    conflict-free LDS accumulation (lane = my), same-bin
-//                    cells summed in registers
+//                    conflict-free LDS accumulation (lane = my), each run of
+//                    same-bin cells summed in an FP64 register and rounded
+//                    once (a run can span tens of thousands of cells)
 //   k_sep_gemm       the banded contraction on the matrix cores, 16x16x4 FP32
 //                    MFMA, LDS-staged T blocks, one workgroup per 16 my x 4
 //                    bins x 256 mx
+// Families with fewer than 16 locations along y (e.g. one shared alpha factor,
+// M_y = 1) give the contraction too few columns to fill its tiles; they are
+// propagated by the general sweep instead (k_sep_expand writes their per-
+// distribution parameters into the workspace).
 #include <hip/hip_runtime.h>
 
 #include "vup_device.hpp"
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(64) void k_sep_scatter(SepArgs a) {
   const float* Ay = a.A[1] + (my < My ? my : 0);
   const int none = 4 * B;
   int cur = none;
-  float acc = 0.0f;
+  double acc = 0.0;
   for (int iy0 = lo; iy0 <= hi; iy0 += 64) {
     const int mine = (iy0 + lane <= hi) ? (int)row[iy0 + lane] : none;
     const int cnt = (hi - iy0 + 1) < 64 ? (hi - iy0 + 1) : 64;
@@ -134,16 +139,16 @@ __global__ __launch_bounds__(64) void k_sep_scatter(SepArgs a) {
         if (j0 + j < cnt) {
           const int code = __builtin_amdgcn_readlane(mine, j0 + j);
           if (code != cur) {
-            if (cur < none) trow[(cur >> 2) * 64 + lane] += acc;
-            acc = 0.0f;
+            if (cur < none) trow[(cur >> 2) * 64 + lane] += (float)acc;
+            acc = 0.0;
             cur = code;
           }
-          acc += v[j];
+          acc += (double)v[j];
         }
       }
     }
   }
-  if (cur < none) trow[(cur >> 2) * 64 + lane] += acc;
+  if (cur < none) trow[(cur >> 2) * 64 + lane] += (float)acc;
   __syncthreads();
   if (my < My) {
     float* Trow = a.T + (long long)ix * B * My;
@@ -367,12 +372,12 @@ static size_t runs_tiled_lds(int B, int ny) {
 #define VUP_SEP_BINS 4
 #endif
 constexpr int kSepBins = VUP_SEP_BINS;  // bins per workgroup of the contraction
+// families with fewer locations along y go to the general sweep
+constexpr int kSepMinMy = 16;
 
-// BT = false: a workgroup owns 16 my x NB bins (the column tile q is bin
-// b0 + q, its 16 columns the my); BT = true (families with M_y < 16, e.g. a
-// shared alpha axis, M_y = 1): one my and 16 NB bins (column tile q holds
-// bins b0 + 16 q .. + 15).
-template <int NB, bool BT>
+// A workgroup owns 16 my x NB bins (the column tile q is bin b0 + q, its 16
+// columns the my).
+template <int NB>
 __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   constexpr int kPitch = 16 * NB + 16;
   constexpr int kTile = 16 * kPitch;
@@ -380,8 +385,8 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
-  const int my0 = BT ? blockIdx.x : blockIdx.x * 16;
-  const int b0 = BT ? blockIdx.y * 16 * NB : blockIdx.y * NB;
+  const int my0 = blockIdx.x * 16;
+  const int b0 = blockIdx.y * NB;
   const int mxb = blockIdx.z * 256;
   // windows of this wave's four tiles (uniform), and of the workgroup's 16
   int tlo[4], thi[4];
@@ -424,32 +429,16 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
         const int e = threadIdx.x + 256 * u;
         const int ix = ix0 + e / (4 * NB);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (BT) {
-          // four consecutive bins of one my
-          const int b = b0 + 16 * ((e >> 2) % NB) + 4 * (e & 3);
-          if (ix <= ghi && ix < nx) {
-            const float* src = a.T + ((long long)ix * B + b) * My + my0;
-            if (My == 1 && (B & 3) == 0 && b + 3 < B) {
-              v = *reinterpret_cast<const float4*>(src);
-            } else {
-              if (b < B) v.x = src[0];
-              if (b + 1 < B) v.y = src[My];
-              if (b + 2 < B) v.z = src[2 * My];
-              if (b + 3 < B) v.w = src[3 * My];
-            }
-          }
-        } else {
-          const int b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
-          if (ix <= ghi && ix < nx && b < B) {
-            const float* src = a.T + ((long long)ix * B + b) * My + my;
-            if (vec && my + 3 < My) {
-              v = *reinterpret_cast<const float4*>(src);
-            } else {
-              if (my < My) v.x = src[0];
-              if (my + 1 < My) v.y = src[1];
-              if (my + 2 < My) v.z = src[2];
-              if (my + 3 < My) v.w = src[3];
-            }
+        const int b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
+        if (ix <= ghi && ix < nx && b < B) {
+          const float* src = a.T + ((long long)ix * B + b) * My + my;
+          if (vec && my + 3 < My) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else {
+            if (my < My) v.x = src[0];
+            if (my + 1 < My) v.y = src[1];
+            if (my + 2 < My) v.z = src[2];
+            if (my + 3 < My) v.w = src[3];
           }
         }
         tv[u] = v;
@@ -515,30 +504,6 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   }
   // D[4 lk + r][li] = C[tile mx + 4 lk + r][column li of tile q]; normalise and
   // store
-  if constexpr (BT) {
-    const int my = my0;
-    const double zy = a.Zd[1][my];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mx = mxb + 16 * (4 * j + w) + 4 * lk + r;
-        if (mx >= Mx) continue;
-        const double z = a.Zd[0][mx] * zy;
-        const double rz = 1.0 / z;
-        const long long k = (long long)mx * My + my;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int b = b0 + 16 * q + li;
-          if (b < B)
-            a.P[k * B + b] = (z > 0.0) ? (float)((double)acc[j][q][r] * rz)
-                                       : (z == 0.0 ? 0.0f : __builtin_nanf(""));
-        }
-        if (a.Z && blockIdx.y == 0 && li == 0) a.Z[k] = z;
-      }
-    }
-    return;
-  }
   const int my = my0 + li;
   if (my >= My) return;
   const double zy = a.Zd[1][my];
@@ -572,8 +537,23 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   }
 }
 
+// per-distribution parameters of a family propagated by the general sweep:
+// mu[k][0][d], sigma[k][0][d] for k = mx M_y + my
+__global__ __launch_bounds__(256) void k_sep_expand(int Mx, int My, const double* mux,
+                                                    const double* muy, const double* sgx,
+                                                    const double* sgy, double* mu, double* sg) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (long long)Mx * My) return;
+  const int mx = (int)(k / My), my = (int)(k % My);
+  mu[2 * k] = mux[mx];
+  mu[2 * k + 1] = muy[my];
+  sg[2 * k] = sgx[mx];
+  sg[2 * k + 1] = sgy[my];
+}
+
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  if (My < kSepMinMy) return 2 * al((size_t)Mx * My * 2 * sizeof(double));
   size_t o = 0;
   const size_t ld0 = ((size_t)Mx + 255) / 256 * 256;
   o += al(((size_t)g.n[0] + 16) * ld0 * 4);
@@ -589,6 +569,24 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
                             const double* mu_y, const double* sg_x, const double* sg_y,
                             double ns, void* ws, float* P, double* Z, hipStream_t s) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  if (My < kSepMinMy) {
+    const long long K = (long long)Mx * My;
+    double* mu = static_cast<double*>(ws);
+    double* sg = reinterpret_cast<double*>(static_cast<char*>(ws) + al((size_t)K * 16));
+    hipLaunchKernelGGL(k_sep_expand, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, Mx, My,
+                       mu_x, mu_y, sg_x, sg_y, mu, sg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    vup_dists d{};
+    d.K = K;
+    d.ncomp = 1;
+    d.ndim = 2;
+    d.n_sigma = ns;
+    d.mu = mu;
+    d.sigma = sg;
+    d.weight = nullptr;
+    return launch_propagate(mm, d, VUP_FP32, P, Z, s);
+  }
   SepArgs a{};
   for (int d = 0; d < 2; ++d) {
     a.n[d] = mm.grid.n[d];
@@ -659,15 +657,9 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int NB = kSepBins;
-  if (My < 16) {
-    hipLaunchKernelGGL((k_sep_gemm<NB, true>), dim3(My, (mm.B + 16 * NB - 1) / (16 * NB),
-                                                    (Mx + 255) / 256),
-                       dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_sep_gemm<NB, false>), dim3((My + 15) / 16, (mm.B + NB - 1) / NB,
-                                                     (Mx + 255) / 256),
-                       dim3(256), 0, s, a);
-  }
+  hipLaunchKernelGGL((k_sep_gemm<NB>), dim3((My + 15) / 16, (mm.B + NB - 1) / NB,
+                                            (Mx + 255) / 256),
+                     dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -240,6 +240,8 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VUP_EWORKSPACE, "workspace not 256-byte aligned");
   const size_t need = vup::sep_workspace_bytes(mm->grid, mm->B, s->M[0], s->M[1]);
   if (ws_bytes < need) return fail(VUP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  // families with fewer than 16 locations along y go through the general sweep
+  if (s->M[1] < 16 && (r = check_sweep(mm, vup::kSweepPropagate))) return r;
   if ((r = check_device())) return r;
   return launched(vup::launch_separable(*mm, s->M[0], s->M[1], s->mu[0], s->mu[1], s->sigma[0],
                                         s->sigma[1], s->n_sigma, ws, P, Z, (hipStream_t)stream),

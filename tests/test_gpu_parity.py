@@ -588,16 +588,18 @@ def test_separable_grid64(vup, orc):
 
 SEP_PATHS = [
     # (label, n, Mx, My, B): rows over 4096 cells (T by read-modify-write),
-    # rows over 65534 cells (T cell by cell), more than 256 x locations
+    # rows over 65534 cells (T cell by cell), more than 256 x locations, and a
+    # family with fewer than 16 y locations (propagated by the general sweep)
     ("long_rows", (6, 5000), 5, 300, 37),
-    ("very_long_rows", (2, 65536), 2, 3, 20),
-    ("wide_x", (300, 40), 300, 5, 64),
+    ("very_long_rows", (2, 65536), 2, 17, 20),
+    ("wide_x", (300, 40), 300, 17, 64),
+    ("narrow_y", (70, 90), 40, 5, 33),
 ]
 
 
 def test_separable_shared_alpha_axis(vup, orc):
     """A family with one shared alpha factor (M_y = 1), as in the Sec. 5.3
-    example: the bin-tiled contraction, against the oracle."""
+    example (propagated by the general sweep, M_y < 16), against the oracle."""
     n, lo, hi = (200, 150), (-5.0, -1.0), (5.0, 1.0)
     mux = workloads.subgrid_midpoints(-5.0, 5.0, 40)
     for s_l in (0.05, 3.0):
@@ -612,8 +614,8 @@ def test_separable_shared_alpha_axis(vup, orc):
 @pytest.mark.parametrize("s_l", [0.05, 3.0])
 def test_separable_ipsa_example_full_size(vup, orc, s_l):
     """The Sec. 5.3 example at full size (N = 10^6, B = 1000, 1000 locations)
-    in the banded form with the shared alpha factor: sampled rows against the
-    oracle."""
+    through vup_propagate_separable with the shared alpha factor (M_y = 1, so
+    the general sweep): every row against the oracle."""
     wl = workloads.ipsa_example(s_l)
     g = vup.make_grid(wl.n, wl.lo, wl.hi)
     fo = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
@@ -621,11 +623,9 @@ def test_separable_ipsa_example_full_size(vup, orc, s_l):
     mm = vup.build_model_matrix(g, torch.from_numpy(fo).to(DEV), torch.from_numpy(eo).to(DEV))
     P, Z, _ = vup.propagate_separable(mm, wl.mu[:, 0, 0], [0.0], wl.sigma[:, 0, 0], [0.25],
                                       wl.n_sigma)
-    ks = workloads.sample_indices(wl.K, 5, 13)
-    sub = wl.subset(ks)
-    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(fo, eo), wl.B, sub.mu, sub.sigma,
+    Po, _ = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(fo, eo), wl.B, wl.mu, wl.sigma,
                           n_sigma=wl.n_sigma)
-    _check_P(_cpu(P)[ks], Po, 2e-5, f"P separable Sec. 5.3 example sigma_l={s_l}")
+    _check_P(_cpu(P), Po, 2e-5, f"P separable Sec. 5.3 example sigma_l={s_l}")
 
 
 def test_separable_1024_family_all_rows(vup, orc):
