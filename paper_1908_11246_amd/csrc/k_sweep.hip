@@ -594,23 +594,32 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
       char* hb = hist + 4 * copy_of(r);
       const float sc = x.sc;
       const float ub = ((float)(r & 15) + 0.5f) * (1.0f / (16.0f * (float)SW));
-      float gos = 0.0f, qs = 0.0f;
+      float gos = 0.0f, qs = 0.0f, gq = 0.0f;
       if constexpr (PREC == VUP_FP32) {
         gos = x.e.x * sc;
       } else {
+        // E4M3 rounds 448 w: the row factor carries the 448
         qs = sc * (PREC == VUP_FP8E4M3 ? (1.0f / 448.0f) : 1.0f);
+        gq = PREC == VUP_FP8E4M3 ? x.e.x * 448.0f : x.e.x;
       }
 #pragma unroll
-      for (int j = 0; j < SW; ++j) {
-        const float u = (float)j * (1.0f / (float)SW) + ub;
-        float v;
+      for (int j = 0; j < SW; j += 2) {
+        const float u0 = (float)j * (1.0f / (float)SW) + ub;
+        const float u1 = (float)(j + 1) * (1.0f / (float)SW) + ub;
+        float v0, v1;
         if constexpr (PREC == VUP_FP32) {
-          v = fmaf(gos, gl[j], u);
+          v0 = fmaf(gos, gl[j], u0);
+          v1 = fmaf(gos, gl[j + 1], u1);
         } else {
-          v = fmaf(quantize<PREC>(x.e.x * gl[j]), qs, u);
+          float q0, q1;
+          quantize2<PREC>(gq * gl[j], gq * gl[j + 1], q0, q1);
+          v0 = fmaf(q0, qs, u0);
+          v1 = fmaf(q1, qs, u1);
         }
-        uint32_t* slot = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j) << cshift));
-        __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        uint32_t* s0 = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j) << cshift));
+        uint32_t* s1 = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j + 1) << cshift));
+        __hip_atomic_fetch_add(s0, (uint32_t)v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(s1, (uint32_t)v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     };
     // rows two at a time in ping-pong buffers: one row's bin codes are in

@@ -176,6 +176,41 @@ __device__ __forceinline__ float round_e4m3(float x) {
   return x < 0.015625f ? sub : __uint_as_float(rn);
 }
 
+// The same roundings for two values at once with gfx950's packed conversions
+// (v_cvt_pk_bf16_f32, v_cvt_pk_fp8_f32 to OCP E4M3; both round to nearest
+// even, checked bit for bit against the software roundings above, ties and
+// E4M3 subnormals included). For VUP_FP8E4M3 the inputs are 448 w and the
+// outputs the E4M3 values (the common scale cancels in P).
+typedef __bf16 vup_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float vup_f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void bf16_pair(float a, float b, float& ra, float& rb) {
+  const vup_bf16x2 v = __builtin_convertvector((vup_f32x2){a, b}, vup_bf16x2);
+  const uint32_t pk = __builtin_bit_cast(uint32_t, v);
+  ra = __uint_as_float(pk << 16);
+  rb = __uint_as_float(pk & 0xFFFF0000u);
+}
+
+template <int PREC>
+__device__ __forceinline__ void quantize2(float a, float b, float& qa, float& qb) {
+  if constexpr (PREC == VUP_BF16) {
+    bf16_pair(a, b, qa, qb);
+  } else if constexpr (PREC == VUP_BF16X2) {
+    float ha, hb, la, lb;
+    bf16_pair(a, b, ha, hb);
+    bf16_pair(a - ha, b - hb, la, lb);
+    qa = ha + la;
+    qb = hb + lb;
+  } else if constexpr (PREC == VUP_FP8E4M3) {
+    const int f8 = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    qa = __builtin_amdgcn_cvt_f32_fp8(f8, 0);
+    qb = __builtin_amdgcn_cvt_f32_fp8(f8, 1);
+  } else {
+    qa = a;
+    qb = b;
+  }
+}
+
 template <int PREC>
 __device__ __forceinline__ float quantize(float w) {
   if constexpr (PREC == VUP_BF16) {
