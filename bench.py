@@ -31,6 +31,9 @@ Profiling helpers (rocprofv3 wraps the program; see profiles/):
   --summarize-traffic F W     FETCH_SIZE / WRITE_SIZE counter CSVs of two
                               --kernels-once runs -> profiles/traffic_grid1024.*
   --summarize-stats CSV OUT   rocprofv3 kernel_stats.csv -> markdown table
+  --summarize-pmc OUT U CSV.. counter CSVs of --pmc passes over one
+                              --kernels-once workload (U updates, as it
+                              prints) -> markdown table of per-kernel counters
 """
 import argparse
 import ctypes
@@ -102,6 +105,10 @@ def kernels_once(name="grid1024"):
     mu = torch.from_numpy(wl.mu).cuda()
     sigma = torch.from_numpy(wl.sigma).cuda()
     w = None if wl.weight is None else torch.from_numpy(wl.weight).cuda()
+    win = vup.windows(g, mu, sigma)
+    U = int(torch.prod((win[..., 1] - win[..., 0] + 1).clamp(min=0).to(torch.int64),
+                       dim=-1).sum().item())
+    print(f"kernels-once {name}: U = {U} cell-distribution updates per sweep", flush=True)
     f = vup.eval_grid(g, wl.model, wl.theta)
     mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B), want_bin=False)
     P, _ = vup.propagate(mm, mu, sigma, w, "fp32", want_Z=False)
@@ -487,6 +494,75 @@ def summarize_traffic(fetch_csv, write_csv):
     print(json.dumps(out, indent=1))
 
 
+# counter-derived fractions: GRBM_GUI_ACTIVE counts busy cycles on each of the
+# 8 XCDs (rocprofv3 sums the instances); a CU issues at most one wave64 VALU
+# instruction per cycle (four SIMDs, 16 lanes, four cycles each), so
+#   VALU issue   = SQ_INSTS_VALU / (256 CUs x cycles)
+#   VALU busy    = 4 SQ_ACTIVE_INST_VALU (quad-cycles) / (1024 SIMDs x cycles)
+#   LDS conflict = SQ_LDS_BANK_CONFLICT / (256 CUs x cycles)
+#   MFMA busy    = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles)
+N_XCD, N_CU, N_SIMD = 8, 256, 1024
+SWEEP_FRAGMENTS = ("k_propagate", "k_moments", "k_backward")
+
+
+def summarize_pmc(out_path, updates, csv_paths):
+    """Per-dispatch hardware counters of rocprofv3 --pmc passes over one
+    --kernels-once run each (same dispatch order in every pass), merged into a
+    markdown table with the fractions above and, for the sweep kernels (each
+    sweeps every update once), VALU and LDS lane-instructions per update."""
+    disp = {}
+    for i, path in enumerate(csv_paths):
+        for r in _counter_rows(path):
+            d = int(r["Dispatch_Id"])
+            e = disp.setdefault(d, {"name": r["Kernel_Name"], "p": {}})
+            key = (r["Counter_Name"], i)  # summed over the instances (XCDs) of one pass
+            e["p"][key] = e["p"].get(key, 0.0) + float(r["Counter_Value"])
+    for e in disp.values():
+        # a counter taken in several passes (GRBM_GUI_ACTIVE) is averaged over them
+        acc = {}
+        for (cname, _), v in e["p"].items():
+            acc.setdefault(cname, []).append(v)
+        e["c"] = {cname: sum(v) / len(v) for cname, v in acc.items()}
+    lines = ["| kernel | cycles / XCD | waves | VALU instr | VALU issue | VALU busy | "
+             "LDS instr | LDS bank-conflict | MFMA busy | VALU lane-instr / update | "
+             "LDS lane-instr / update |", "|---" * 11 + "|"]
+
+    def f(v, fmt):
+        return "—" if v is None else format(v, fmt)
+    for d in sorted(disp):
+        name, c = disp[d]["name"], disp[d]["c"]
+        if not name.startswith(("vup::", "void vup::")) or c.get("SQ_WAVES", 1.0) < 256:
+            continue
+        short = name[5:] if name.startswith("void ") else name
+        short = short.split("(")[0]
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD or None
+        get = c.get
+        valu_issue = get("SQ_INSTS_VALU") / (N_CU * cyc) if cyc and "SQ_INSTS_VALU" in c else None
+        valu_busy = (4 * get("SQ_ACTIVE_INST_VALU") / (N_SIMD * cyc)
+                     if cyc and "SQ_ACTIVE_INST_VALU" in c else None)
+        conf = (get("SQ_LDS_BANK_CONFLICT") / (N_CU * cyc)
+                if cyc and "SQ_LDS_BANK_CONFLICT" in c else None)
+        mfma = (get("SQ_VALU_MFMA_BUSY_CYCLES") / (N_SIMD * cyc)
+                if cyc and "SQ_VALU_MFMA_BUSY_CYCLES" in c else None)
+        sweep = any(t in short for t in SWEEP_FRAGMENTS) and updates
+        vpu = 64 * get("SQ_INSTS_VALU") / updates if sweep and "SQ_INSTS_VALU" in c else None
+        lpu = 64 * get("SQ_INSTS_LDS") / updates if sweep and "SQ_INSTS_LDS" in c else None
+        lines.append(f"| `{short[:60]}` | {f(cyc, '.4g')} | {f(get('SQ_WAVES'), '.0f')} | "
+                     f"{f(get('SQ_INSTS_VALU'), '.4g')} | {f(valu_issue, '.3f')} | "
+                     f"{f(valu_busy, '.3f')} | {f(get('SQ_INSTS_LDS'), '.4g')} | {f(conf, '.3f')} | "
+                     f"{f(mfma, '.3f')} | {f(vpu, '.2f')} | {f(lpu, '.2f')} |")
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1908_11246_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    text = "\n".join(lines) + f"\n\nKernel sources (csrc/, sorted) sha256: {h.hexdigest()}\n"
+    with open(out_path, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
 def summarize_stats(csv_path, out_path):
     rows = _counter_rows(csv_path)
     lines = ["| kernel | calls | avg (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
@@ -507,6 +583,8 @@ def main():
         return summarize_traffic(sys.argv[2], sys.argv[3])
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
         return summarize_stats(sys.argv[2], sys.argv[3])
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
+        return summarize_pmc(sys.argv[2], float(sys.argv[3]), sys.argv[4:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

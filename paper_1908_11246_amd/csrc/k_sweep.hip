@@ -135,7 +135,9 @@ __device__ __forceinline__ long long block_k(const SweepArgs& a) {
   return (b & 7) * a.kpx + (b >> 3);
 }
 
-// strip width minimising the sweep time estimate of one component
+// strip width minimising the sweep time estimate of one component: passes
+// over the rows times (cells of a strip + a per-row cost of three cells'
+// worth, the measured best of the values tried)
 __device__ __forceinline__ int choose_sw(int loL, int WL, long long R, int maxsw) {
   int best = 4;
   long long bestc = 0x7fffffffffffffffll;
@@ -144,7 +146,7 @@ __device__ __forceinline__ int choose_sw(int loL, int WL, long long R, int maxsw
     const int cols = ns < kThreads ? ns : kThreads;
     const int P0 = kThreads / cols;
     const long long ncg = (ns + kThreads - 1) / kThreads;
-    const long long c = ((R + P0 - 1) / P0) * ncg * (sw + 6);
+    const long long c = ((R + P0 - 1) / P0) * ncg * (sw + 3);
     if (c < bestc) {
       bestc = c;
       best = sw;
@@ -567,8 +569,9 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
   if (ph >= P0) return;
   const float2* rt = reinterpret_cast<const float2*>(smem + a.L.row_off);
   const int cm = a.L.cpw - 1;     // copies - 1 (a power of two minus one)
-  const int cshift = a.L.cshift;  // byte offset of (bin, copy): (4 bin) << cshift + 4 copy
-  char* hist = reinterpret_cast<char*>(smem + a.L.hist_off);
+  // byte address of (bin, copy): hist + (4 bin) << cshift + 4 copy
+  const uint32_t cmul = 1u << a.L.cshift;
+  const uint32_t hist = lds_addr(smem + a.L.hist_off);
   const float* tabL = smem + pick4(a.L.tab_off, a.g.ndim - 1);
   for (int s = col; s < ns; s += cols) {
     float gl[SW];
@@ -591,7 +594,7 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
     };
     auto accumulate = [&](int r, const Row& x) {
       // this strip-row's copy and its scale; the ordered dither's row part
-      char* hb = hist + 4 * copy_of(r);
+      const uint32_t hb = hist + 4 * copy_of(r);
       const float sc = x.sc;
       const float ub = ((float)(r & 15) + 0.5f) * (1.0f / (16.0f * (float)SW));
       float gos = 0.0f, qs = 0.0f, gq = 0.0f;
@@ -616,8 +619,10 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
           v0 = fmaf(q0, qs, u0);
           v1 = fmaf(q1, qs, u1);
         }
-        uint32_t* s0 = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j) << cshift));
-        uint32_t* s1 = reinterpret_cast<uint32_t*>(hb + (map_at<SW>(x.mv, j + 1) << cshift));
+        // codes j (low half) and j + 1 (high half) of one packed word
+        const uint32_t pk = x.mv.v[j >> 1];
+        vup_lds_u32* s0 = (vup_lds_u32*)(uintptr_t)mad_lo16(pk, cmul, hb);
+        vup_lds_u32* s1 = (vup_lds_u32*)(uintptr_t)mad_hi16(pk, cmul, hb);
         __hip_atomic_fetch_add(s0, (uint32_t)v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_add(s1, (uint32_t)v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
@@ -912,22 +917,11 @@ __device__ __forceinline__ void build_rows_runs(const SweepArgs& a, float* smem,
   }
 }
 
-// FP64 load from an LDS byte address. The run kernel uses no static LDS, so
-// its dynamic LDS (and the prefix sums at its start) begins at address 0.
+// FP64 load from an LDS byte address (lds_addr of the prefix sums plus
+// 8 column, formed by mad_lo16 from a run record in one VALU op)
 typedef const __attribute__((address_space(3))) double lds_f64;
 __device__ __forceinline__ double lds_load_f64(uint32_t byte_addr) {
   return *(lds_f64*)(size_t)byte_addr;
-}
-
-// (x & 0xFFFF) * 8 in one VALU op (a shift with a 16-bit operand select),
-// which the compiler otherwise splits into a shift and a mask
-__device__ __forceinline__ uint32_t lo16_times8(uint32_t x) {
-  uint32_t r;
-  asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
-      "src1_sel:WORD_0"
-      : "=v"(r)
-      : "v"(x));
-  return r;
 }
 
 // value of lane (l + 1) mod 16 within each 16-lane row (DPP row rotate)
@@ -941,6 +935,7 @@ __device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int r
   const int wv = threadIdx.x >> 6;
   const RunRow* rt = reinterpret_cast<const RunRow*>(smem + a.L.row_off);
   char* hbase = reinterpret_cast<char*>(smem + a.L.hist_off);
+  const uint32_t gaddr = lds_addr(smem + a.L.g_off);  // FP64 prefix sums G
   const double u = ((double)threadIdx.x + 0.5) * (1.0 / kThreads);
   const int bl = (rc + 3) >> 2;
   const int rend = min((gi + 1) * bl, rc);
@@ -958,14 +953,16 @@ __device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int r
       const uint32_t nx = (l == kRunGroup - 1) ? dn : dc;
       if (left > 0) {
         const double v =
-            fma(lds_load_f64(lo16_times8(nx)) - lds_load_f64(lo16_times8(c)), row.rs, u);
+            fma(lds_load_f64(mad_lo16_k<8>(nx, gaddr)) - lds_load_f64(mad_lo16_k<8>(c, gaddr)),
+                row.rs, u);
         uint32_t* slot = reinterpret_cast<uint32_t*>(lh + (c >> 16));
         __hip_atomic_fetch_add(slot, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     };
     // four runs per lane per pass: the four record loads are in flight
-    // together. Records past the segment (at most 79) are read but unused;
-    // the run buffer is padded for them.
+    // together (a step no lane of the wave needs is branched over). Records
+    // past the segment (at most 79) are read but unused; the run buffer is
+    // padded for them.
     uint32_t cur = rp[l];
     uint32_t dcur = next_lane(cur);
     for (int q0 = l; q0 - l < cnt; q0 += 4 * kRunGroup) {
@@ -1512,16 +1509,6 @@ __device__ __forceinline__ f32x4v lds_load_f4(uint32_t byte_addr) {
   return *(lds_f4*)(size_t)byte_addr;
 }
 
-// (x & 0xFFFF) * 16 in one VALU op
-__device__ __forceinline__ uint32_t lo16_times16(uint32_t x) {
-  uint32_t r;
-  asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
-      "src1_sel:WORD_0"
-      : "=v"(r)
-      : "v"(x));
-  return r;
-}
-
 // G3[c] = (G0, G1, G2, -) for c = 0 .. n (sums over the window columns below
 // c); the FP64 window totals go to tot[0..2].
 __device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem, long long kc,
@@ -1629,6 +1616,7 @@ __device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc
   const int wv = threadIdx.x >> 6;
   const BwdRunRow* rt = reinterpret_cast<const BwdRunRow*>(smem + a.L.row_off);
   const char* vt = reinterpret_cast<const char*>(smem + a.L.hist_off);
+  const uint32_t gaddr = lds_addr(smem);  // G3 (16-byte entries per column)
   struct {
     float a0, l1, l2, o1[NO > 0 ? NO : 1], o2[NO > 0 ? NO : 1];
   } b = {};
@@ -1654,8 +1642,8 @@ __device__ __forceinline__ void bwd_runs(const SweepArgs& a, float* smem, int rc
     auto step = [&](uint32_t c, uint32_t dc, uint32_t dn, int left) {
       const uint32_t nx = (l == kRunGroup - 1) ? dn : dc;
       if (left > 0) {
-        const f32x4v gs = lds_load_f4(lo16_times16(c));
-        const f32x4v ge = lds_load_f4(lo16_times16(nx));
+        const f32x4v gs = lds_load_f4(mad_lo16_k<16>(c, gaddr));
+        const f32x4v ge = lds_load_f4(mad_lo16_k<16>(nx, gaddr));
         const float vb = *reinterpret_cast<const float*>(vt + (c >> 16));
         a0 = fmaf(vb, ge.x - gs.x, a0);
         a1 = fmaf(vb, ge.y - gs.y, a1);

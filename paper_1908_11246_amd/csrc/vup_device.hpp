@@ -176,6 +176,36 @@ __device__ __forceinline__ float round_e4m3(float x) {
   return x < 0.015625f ? sub : __uint_as_float(rn);
 }
 
+// LDS byte address of a pointer into LDS (an address-space cast, so it holds
+// wherever the compiler places the kernel's LDS).
+typedef __attribute__((address_space(3))) char vup_lds_char;
+typedef __attribute__((address_space(3))) uint32_t vup_lds_u32;
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const vup_lds_char*)p;
+}
+
+// m * (low or high 16 bits of x) + c in one VALU op (v_mad_u32_u16, op_sel
+// picking the half): an address from a packed 16-bit code; m < 2^16
+__device__ __forceinline__ uint32_t mad_lo16(uint32_t x, uint32_t m, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(m), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t mad_hi16(uint32_t x, uint32_t m, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(x), "v"(m), "v"(c));
+  return r;
+}
+// M * (low 16 bits of x) + c for a uniform c and an inline-constant M
+// (0 < M <= 64): no register for either
+template <int M>
+__device__ __forceinline__ uint32_t mad_lo16_k(uint32_t x, uint32_t c) {
+  static_assert(M > 0 && M <= 64, "an inline constant");
+  uint32_t r;
+  asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(M), "s"(c));
+  return r;
+}
+
 // The same roundings for two values at once with gfx950's packed conversions
 // (v_cvt_pk_bf16_f32, v_cvt_pk_fp8_f32 to OCP E4M3; both round to nearest
 // even, checked bit for bit against the software roundings above, ties and
