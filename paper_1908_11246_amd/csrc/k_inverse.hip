@@ -12,9 +12,9 @@
 //                     row's factor product staged, one multiply-add per cell
 //                     and component
 //   k_posterior_mean  E[x_d | y in b, k] = sum over the bin's cells of
-//                     post x_d, one wave per (t, b) walking the model
-//                     matrix's compressed-by-bin cell list in order (fixed
-//                     summation order)
+//                     post x_d, one wave per (t, b) walking the part of the
+//                     model matrix's compressed-by-bin cell list inside the
+//                     window's index range (fixed summation order)
 #include <hip/hip_runtime.h>
 
 #include "vup_device.hpp"
@@ -46,6 +46,7 @@ struct PostArgs {
   float* post;
   double* mean;
   int gtab;                 // the fastest-axis factor table fits in LDS
+  int vec;                  // rows of post take float4 stores (n_L % 4 == 0, aligned)
   double rn[4];             // 1 / n_d, for the index arithmetic of the means
 };
 
@@ -98,36 +99,39 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
   // shared by all rows of this distribution
   float* gtab = sfb + C * B;
   if (a.gtab && kok) {
-    for (int e = threadIdx.x; e < C * nL; e += blockDim.x) {
-      const int c = e / nL, col = e - c * nL;
-      float g = 0.0f;
-      if (col >= swin[c][D - 1][0] && col <= swin[c][D - 1][1])
-        g = gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col), smu[c][D - 1],
-                           srs[c][D - 1]);
-      gtab[e] = g;
+    // only the window's columns: the cells read no others
+    for (int c = 0; c < C; ++c) {
+      const int wlo = swin[c][D - 1][0], whi = swin[c][D - 1][1];
+      for (int col = wlo + (int)threadIdx.x; col <= whi; col += blockDim.x)
+        gtab[c * nL + col] = gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
+                                            smu[c][D - 1], srs[c][D - 1]);
     }
   }
   __syncthreads();
   const bool bad = sbad != 0;
   float* post = a.post + (long long)t * a.N;
-  for (int r = blockIdx.x; r < a.rows; r += gridDim.x) {
-    // the row's multi-index and, per component, the product of the factors of
-    // all axes but the fastest (0 when the row is outside the window)
-    int j[4] = {0, 0, 0, 0};
-    {
-      int q = r;
-      for (int d = D - 2; d >= 0; --d) {
-        j[d] = q % a.n[d];
-        q /= a.n[d];
-      }
-    }
+  // a row's factor product per component (0 outside the component's window)
+  // and the columns any window covers; outside them, and in rows no window
+  // covers, post is 0 (NaN for an invalid distribution)
+  struct RowInfo {
     float rf[VUP_MAX_COMP];
     int clo[VUP_MAX_COMP], chi[VUP_MAX_COMP];
+    int ulo, uhi;
+  };
+  auto row_info = [&](int r, RowInfo& ri) {
+    int j[4] = {0, 0, 0, 0};
+    int q = r;
+    for (int d = D - 2; d >= 0; --d) {
+      j[d] = q % a.n[d];
+      q /= a.n[d];
+    }
+    ri.ulo = 0x7fffffff;
+    ri.uhi = -1;
 #pragma unroll
     for (int c = 0; c < VUP_MAX_COMP; ++c) {
-      rf[c] = 0.0f;
-      clo[c] = 0;
-      chi[c] = -1;
+      ri.rf[c] = 0.0f;
+      ri.clo[c] = 0;
+      ri.chi[c] = -1;
       if (c < C) {
         bool in = true;
         float f = 1.0f;
@@ -136,40 +140,124 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
           if (in) f *= gauss_factor_r(cell_centre(a.lo[d], a.hi[d], a.n[d], j[d]), smu[c][d],
                                       srs[c][d]);
         }
-        if (in) {
-          rf[c] = f;
-          clo[c] = swin[c][D - 1][0];
-          chi[c] = swin[c][D - 1][1];
+        if (in && swin[c][D - 1][1] >= swin[c][D - 1][0]) {
+          ri.rf[c] = f;
+          ri.clo[c] = swin[c][D - 1][0];
+          ri.chi[c] = swin[c][D - 1][1];
+          ri.ulo = min(ri.ulo, ri.clo[c]);
+          ri.uhi = max(ri.uhi, ri.chi[c]);
         }
       }
     }
-    const uint16_t* brow = a.binmap + (long long)r * a.pitch;
-    float* prow = post + (long long)r * nL;
-    for (int col = threadIdx.x; col < nL; col += blockDim.x) {
-      const uint32_t code = brow[col];
-      float v = 0.0f;
-      if (code < 4u * (uint32_t)B) {
-        const int b = (int)(code >> 2);
+  };
+  auto cell = [&](const RowInfo& ri, int col, uint32_t code) {
+    float v = 0.0f;
+    if (code < 4u * (uint32_t)B) {
+      const int b = (int)(code >> 2);
 #pragma unroll
-        for (int c = 0; c < VUP_MAX_COMP; ++c) {
-          if (c < C && col >= clo[c] && col <= chi[c]) {
-            const float g = a.gtab ? gtab[c * nL + col]
-                                   : gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
-                                                    smu[c][D - 1], srs[c][D - 1]);
-            v = fmaf(rf[c] * g, sfb[c * B + b], v);
-          }
+      for (int c = 0; c < VUP_MAX_COMP; ++c) {
+        if (c < C && col >= ri.clo[c] && col <= ri.chi[c]) {
+          const float g = a.gtab ? gtab[c * nL + col]
+                                 : gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
+                                                  smu[c][D - 1], srs[c][D - 1]);
+          v = fmaf(ri.rf[c] * g, sfb[c * B + b], v);
         }
       }
-      prow[col] = bad ? __builtin_nanf("") : v;
+    }
+    return v;
+  };
+  if (a.vec) {
+    // four columns per thread: one 8-byte load of bin codes, one 16-byte store
+    const float fill = bad ? __builtin_nanf("") : 0.0f;
+    for (int r = blockIdx.x; r < a.rows; r += gridDim.x) {
+      RowInfo ri;
+      row_info(r, ri);
+      const uint16_t* brow = a.binmap + (long long)r * a.pitch;
+      float4* prow4 = reinterpret_cast<float4*>(post + (long long)r * nL);
+      for (int c4 = threadIdx.x; c4 < (nL >> 2); c4 += blockDim.x) {
+        const int col0 = 4 * c4;
+        float4 o = make_float4(fill, fill, fill, fill);
+        if (!bad && col0 + 3 >= ri.ulo && col0 <= ri.uhi) {
+          const uint2 cw = *reinterpret_cast<const uint2*>(brow + col0);
+          o.x = cell(ri, col0, cw.x & 0xFFFFu);
+          o.y = cell(ri, col0 + 1, cw.x >> 16);
+          o.z = cell(ri, col0 + 2, cw.y & 0xFFFFu);
+          o.w = cell(ri, col0 + 3, cw.y >> 16);
+        }
+        prow4[c4] = o;
+      }
+    }
+  } else {
+    for (int r = blockIdx.x; r < a.rows; r += gridDim.x) {
+      RowInfo ri;
+      row_info(r, ri);
+      const uint16_t* brow = a.binmap + (long long)r * a.pitch;
+      float* prow = post + (long long)r * nL;
+      for (int col = threadIdx.x; col < nL; col += blockDim.x) {
+        float v = 0.0f;
+        if (col >= ri.ulo && col <= ri.uhi) v = cell(ri, col, brow[col]);
+        prow[col] = bad ? __builtin_nanf("") : v;
+      }
     }
   }
 }
 
+// first positions s in [s0, s1) of the ascending cell list with list[s] >= x0
+// and with list[s] >= x1 (s1 if none), by the whole wave, both searches in the
+// same rounds (their loads in flight together): each round probes 64
+// positions spread over a search's remaining range and keeps the part between
+// the last probe below its target and the first at or above it, so a range of
+// n shrinks to n / 65 per round
+struct WaveSearch {
+  long long lo, hi;  // the answer lies in [lo, hi]
+};
+
+__device__ __forceinline__ long long probe_at(const WaveSearch& w, int i) {
+  return w.lo + ((w.hi - w.lo) * (i + 1)) / 65;  // in (lo, hi) while hi - lo > 64
+}
+
+__device__ __forceinline__ void narrow(WaveSearch& w, bool ge) {
+  const unsigned long long m = __ballot(ge);
+  const int f = m ? __builtin_ctzll(m) : 64;  // first probe at or above the target
+  const long long pf = probe_at(w, f), pb = probe_at(w, f - 1);
+  if (f < 64) w.hi = pf;
+  if (f > 0) w.lo = pb + 1;
+}
+
+__device__ __forceinline__ long long finish_search(const int* list, const WaveSearch& w,
+                                                   long long x, int lane) {
+  const long long p = w.lo + lane;
+  const bool ge = p < w.hi && (long long)list[p] >= x;
+  const unsigned long long m = __ballot(ge);
+  return m ? w.lo + __builtin_ctzll(m) : w.hi;
+}
+
+__device__ __forceinline__ void wave_lower_bounds(const int* list, long long s0, long long s1,
+                                                  long long x0, long long x1, int lane,
+                                                  long long& r0, long long& r1) {
+  WaveSearch a{s0, s1}, b{s0, s1};
+  for (;;) {
+    const bool on_a = a.hi - a.lo > 64, on_b = b.hi - b.lo > 64;  // uniform
+    if (!on_a && !on_b) break;
+    const int va = on_a ? list[probe_at(a, lane)] : 0;
+    const int vb = on_b ? list[probe_at(b, lane)] : 0;
+    if (on_a) narrow(a, (long long)va >= x0);
+    if (on_b) narrow(b, (long long)vb >= x1);
+  }
+  r0 = finish_search(list, a, x0, lane);
+  r1 = finish_search(list, b, x1, lane);
+}
+
 // one wave per (t, b): lanes take the bin's cells lane, lane + 64, ... of the
-// compressed-by-bin list; the wave sum fixes the order. With cell centres
-// x_d = lo_d + (j_d + 1/2) h_d, the sums are kept as S0 = sum q and
-// S_d = sum q j_d (FP64) and combined at the end; the row-major index is split
-// with a double reciprocal and one correction step.
+// compressed-by-bin list; the wave sum fixes the order. Only the part of the
+// list inside the row-major index range of the distribution's window (the
+// bounding box of its components' windows) can hold nonzero posteriors: the
+// wave finds it by search and walks it with the same lane assignment as a
+// walk of the whole list, skipping the loads of cells outside the box (their
+// terms are exact zeros), so the sums do not depend on the skipping. With
+// cell centres x_d = lo_d + (j_d + 1/2) h_d, the sums are kept as S0 = sum q
+// and S_d = sum q j_d (FP64) and combined at the end; the row-major index is
+// split with a double reciprocal and one correction step.
 __global__ __launch_bounds__(256) void k_posterior_mean(PostArgs a) {
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -177,27 +265,73 @@ __global__ __launch_bounds__(256) void k_posterior_mean(PostArgs a) {
   if (b >= a.B) return;  // whole waves leave together
   const long long s0 = a.offsets[b], s1 = a.offsets[b + 1];
   const float* post = a.post + t * a.N;
-  const int D = a.ndim;
+  const int D = a.ndim, C = a.C;
+  double* out = a.mean + (t * a.B + b) * a.ndim;
+  // the posterior row is NaN (the same conditions as k_posterior): mean NaN,
+  // 0 for a bin without cells
+  const long long k = a.sel[t];
+  bool bad = !(k >= 0 && k < a.K);
+  int blo[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff}, bhi[4] = {-1, -1, -1, -1};
+  bool any = false;  // some component's window is not empty
+  if (!bad) {
+    for (int c = 0; c < C; ++c) {
+      bool cin = true;
+      int wl[4], wh[4];
+      for (int d = 0; d < D; ++d) {
+        const long long pidx = (k * C + c) * D + d;
+        if (!axis_window(a.lo[d], a.hi[d], a.n[d], a.mu[pidx], a.sigma[pidx], a.ns, wl[d], wh[d]))
+          bad = true;
+        cin = cin && wh[d] >= wl[d];
+      }
+      if (!isfinite(a.Z[k * C + c])) bad = true;
+      if (cin) {
+        any = true;
+        for (int d = 0; d < D; ++d) {
+          blo[d] = min(blo[d], wl[d]);
+          bhi[d] = max(bhi[d], wh[d]);
+        }
+      }
+    }
+    for (int e = lane; e < a.B; e += 64)
+      if (!isfinite(a.P[k * a.B + e])) bad = true;
+    bad = __ballot(bad) != 0;
+  }
+  // a bin without mass has post 0 on all its cells (k_posterior's factor is 0
+  // there): its sums are exact zeros, so the mean is 0 without a walk
+  if (bad || !any || !(a.P[k * a.B + b] > 0.0f)) {
+    if (lane < D) out[lane] = (bad && s1 > s0) ? __builtin_nan("") : 0.0;
+    return;
+  }
+  // row-major index range of the window box, and its part of the list
+  long long first = 0, last = 0;
+  for (int d = 0; d < D; ++d) {
+    first = first * a.n[d] + blo[d];
+    last = last * a.n[d] + bhi[d];
+  }
+  long long sa, sb;
+  wave_lower_bounds(a.perm, s0, s1, first, last + 1, lane, sa, sb);
   double S0 = 0.0, S[4] = {0.0, 0.0, 0.0, 0.0};
+  // four cells per lane per pass, their loads in flight together; lane l
+  // takes the cells s0 + l + 64 m in increasing m whatever the pass size, so
+  // the sums are those of a walk of the whole list
   constexpr int U = 4;
-  for (long long s = s0 + lane; s < s1; s += 64 * U) {
-    int ci[U];
-    float q[U];
+  // start at the pass of the whole-list walk that reaches sa
+  const long long sstart = s0 + ((sa - s0) / (64 * U)) * (64 * U);
+  for (long long s = sstart + lane; s < sb; s += 64 * U) {
+    int ci[U], jd[U][4];
+    bool in[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const long long su = s + 64 * u;
-      ci[u] = su < s1 ? a.perm[su] : -1;
+      ci[u] = (su >= sa && su < sb) ? a.perm[su] : -1;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) q[u] = ci[u] >= 0 ? post[ci[u]] : 0.0f;
-#pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (ci[u] < 0) continue;
-      const double qd = (double)q[u];
-      S0 += qd;
-      int rest = ci[u];
+      in[u] = ci[u] >= 0;
+      int rest = ci[u] < 0 ? 0 : ci[u];
 #pragma unroll
       for (int d = 3; d >= 1; --d) {
+        jd[u][d] = 0;
         if (d < D) {
           const int n = a.n[d];
           int quo = (int)((double)rest * a.rn[d]);
@@ -209,15 +343,28 @@ __global__ __launch_bounds__(256) void k_posterior_mean(PostArgs a) {
             ++quo;
             rem -= n;
           }
-          S[d] += qd * (double)rem;
+          jd[u][d] = rem;
+          in[u] = in[u] && rem >= blo[d] && rem <= bhi[d];
           rest = quo;
         }
       }
-      S[0] += qd * (double)rest;
+      jd[u][0] = rest;
+      in[u] = in[u] && rest >= blo[0] && rest <= bhi[0];
+    }
+    float q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = in[u] ? post[ci[u]] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!in[u]) continue;
+      const double qd = (double)q[u];
+      S0 += qd;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (d < D) S[d] += qd * (double)jd[u][d];
     }
   }
   S0 = wave_sum(S0);
-  double* out = a.mean + (t * a.B + b) * a.ndim;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     if (d < D) {
@@ -262,9 +409,13 @@ hipError_t launch_posterior(const vup_mm& mm, const vup_dists& d, int64_t n_sel,
   for (int x = 0; x < 4; ++x) a.rn[x] = 1.0 / a.n[x];
   const int nL = a.n[a.ndim - 1];
   a.gtab = (size_t)d.ncomp * (mm.B + nL) * sizeof(float) <= 65536 ? 1 : 0;
+  a.vec = (nL % 4 == 0) && ((reinterpret_cast<uintptr_t>(post) & 15u) == 0);
   const size_t lds = (size_t)d.ncomp * (mm.B + (a.gtab ? nL : 0)) * sizeof(float);
-  // about eight rows per workgroup, so the per-bin factors are set up rarely
-  long long gx = (mm.rows + 7) / 8;
+  // about 32 rows per workgroup, so the per-bin factors and the factor table
+  // are set up rarely, but at least 4096 workgroups in all while rows last
+  long long gx = (mm.rows + 31) / 32;
+  const long long want = (4096 + n_sel - 1) / n_sel;
+  if (gx < want) gx = want < mm.rows ? want : mm.rows;
   gx = gx < 1 ? 1 : (gx > 4096 ? 4096 : gx);
   hipLaunchKernelGGL(k_posterior, dim3((unsigned)gx, (unsigned)n_sel), dim3(256), lds, s, a);
   hipError_t e = hipGetLastError();
