@@ -124,7 +124,8 @@ def kernels_once(name="grid1024"):
         # (256 x 256 locations, shared sigma = 0.25)
         m = workloads.subgrid_midpoints(wl.lo[0], wl.hi[0], 256)
         s = np.full(256, 0.25)
-        vup.propagate_separable(mm, m, m, s, s, want_Z=False)
+        for prec in ("fp32", "bf16", "bf16x2"):
+            vup.propagate_separable(mm, m, m, s, s, want_Z=False, precision=prec)
     torch.cuda.synchronize()
     src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -244,9 +245,10 @@ def ipsa_views(vup, mm, P, mu, sigma, stream, reps):
 
 
 MFMA_FP32_PEAK_TFLOPS = 157.3
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense
 
 
-def separable_run(vup, workloads, stream, reps):
+def separable_run(vup, workloads, stream, reps, keep=None):
     """The banded MFMA form on a tensor-product family at full scale: 1024^2
     grid on [-3,3]^2, sincos model, B = 256, 256 x 256 locations on the
     midpoint subgrid with one shared sigma = 0.25 per axis (4-sigma windows).
@@ -254,7 +256,9 @@ def separable_run(vup, workloads, stream, reps):
     sums, the run scatter and the MFMA contraction); the MFMA roofline counts
     the banded contraction's algorithmic flops 2 B M_y sum_mx |window_x(mx)|
     against that whole time, so its fraction is a lower bound for the
-    contraction kernel."""
+    contraction kernel. The same for the BF16 and split-BF16 contractions
+    (against the dense BF16 MFMA peak); `keep` receives 64 sampled rows of
+    each precision's P for the error against the oracle."""
     import torch
     n, lo, hi, B, M, sg = (1024, 1024), (-3.0, -3.0), (3.0, 3.0), 256, 256, 0.25
     g = vup.make_grid(n, lo, hi)
@@ -272,16 +276,33 @@ def separable_run(vup, workloads, stream, reps):
     wx, wy = wlen[:, 0], wlen[:, 1]
     U = float(wx.sum().item() * wy.sum().item())
     flops = 2.0 * B * M * float(wx.sum().item())
-    ms = _time_on(stream, lambda: vup.propagate_separable(mm, m, m, s, s, ws=ws, want_Z=False),
-                  reps)
-    ach = flops / (ms * 1e-3) / 1e12
-    return {"workload": "1024^2 grid on [-3,3]^2, sincos model, B=256, 256x256 locations on "
-                        "the midpoint subgrid, shared sigma=0.25, 4-sigma windows",
-            "ms": ms, "updates": U, "updates_per_s": U / (ms * 1e-3),
-            "roofline": {"bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / MFMA_FP32_PEAK_TFLOPS,
-                         "algorithmic_flops": flops,
-                         "kernel": "vup_propagate_separable (k_sep_gemm + set-up, whole call)"}}
+    out = {"workload": "1024^2 grid on [-3,3]^2, sincos model, B=256, 256x256 locations on "
+                       "the midpoint subgrid, shared sigma=0.25, 4-sigma windows",
+           "updates": U}
+    rows = workloads.sample_indices(M * M, 64, 9)
+    for prec, peak, kern in (("fp32", MFMA_FP32_PEAK_TFLOPS, "k_sep_gemm"),
+                             ("bf16", MFMA_BF16_PEAK_TFLOPS, "k_sep_gemm_bf16<2, false>"),
+                             ("bf16x2", MFMA_BF16_PEAK_TFLOPS, "k_sep_gemm_bf16<2, true> "
+                              "(three BF16 products per term)")):
+        ms = _time_on(stream, lambda: vup.propagate_separable(mm, m, m, s, s, ws=ws, want_Z=False,
+                                                              precision=prec), reps)
+        P, _, _ = vup.propagate_separable(mm, m, m, s, s, ws=ws, want_Z=False, precision=prec)
+        torch.cuda.synchronize()
+        if keep is not None:
+            keep[prec] = P.cpu().numpy()[rows]
+        ach = flops / (ms * 1e-3) / 1e12
+        entry = {"ms": ms, "updates_per_s": U / (ms * 1e-3),
+                 "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                              "frac": ach / peak, "algorithmic_flops": flops,
+                              "kernel": f"vup_propagate_separable ({kern} + set-up, whole call)"}}
+        if prec == "fp32":
+            out.update(entry)
+        else:
+            out[prec] = entry
+    if keep is not None:
+        keep["rows"] = rows
+        keep["m"] = m
+    return out
 
 
 def _errors_vs_fp64(orc, wl, b, e, Ps, mh_v, ks):
@@ -751,10 +772,12 @@ def main():
         result["variants"] = variants
         result["ipsa_views"] = ipsa_views(vup, mm, Ps["fp32"], mu, sigma, stream,
                                           max(3, args.steps // 2))
-        sep = separable_run(vup, workloads, stream, max(3, args.steps // 2))
+        sep_keep = {}
+        sep = separable_run(vup, workloads, stream, max(3, args.steps // 2), sep_keep)
         variants["propagate_separable"] = sep
-        log(f"[bench] separable (banded MFMA) {sep['ms']:.3f} ms, "
-            f"{sep['updates_per_s']:.3e} updates/s, MFMA frac {sep['roofline']['frac']:.3f}")
+        log(f"[bench] separable (banded MFMA) FP32 {sep['ms']:.3f} ms, "
+            f"{sep['updates_per_s']:.3e} updates/s, MFMA frac {sep['roofline']['frac']:.3f}; "
+            f"BF16 {sep['bf16']['ms']:.3f} ms, split BF16 {sep['bf16x2']['ms']:.3f} ms")
         result["ipsa_example"] = ipsa_example_runs(vup, workloads, stream,
                                                    max(3, args.steps // 2))
         log("[bench] IPSA views " + ", ".join(
@@ -806,6 +829,20 @@ def main():
             result["error_vs_fp64_oracle"] = _errors_vs_fp64(
                 orc, wl, b, e, {p: P.cpu().numpy()[ke] for p, P in Ps.items()},
                 {p: tuple(a[ke] for a in v) for p, v in stats.items()}, ke)
+            # the banded form's precisions on its family (sampled rows)
+            m_s, rows = sep_keep["m"], sep_keep["rows"]
+            Msep = len(m_s)
+            mu_s = np.zeros((len(rows), 1, 2))
+            mu_s[:, 0, 0] = m_s[rows // Msep]
+            mu_s[:, 0, 1] = m_s[rows % Msep]
+            fs = orc.eval_grid((1024, 1024), (-3.0, -3.0), (3.0, 3.0), "sincos2")
+            Pso, _ = orc.propagate((1024, 1024), (-3.0, -3.0), (3.0, 3.0),
+                                   orc.bins(fs, orc.uniform_edges(fs, 256)), 256, mu_s,
+                                   np.full_like(mu_s, 0.25))
+            for prec in ("fp32", "bf16", "bf16x2"):
+                err = float(np.abs(sep_keep[prec].astype(np.float64) - Pso).sum(axis=1).max())
+                tgt = result["variants"]["propagate_separable"]
+                (tgt if prec == "fp32" else tgt[prec])["P_L1_vs_fp64_oracle_64_rows"] = err
             for name, (wv, kv, Pv, sv) in kept.items():
                 fo = orc.eval_grid(wv.n, wv.lo, wv.hi, wv.model, wv.theta)
                 eo = orc.uniform_edges(fo, wv.B)

@@ -223,6 +223,8 @@ typedef struct vup_sepdists {
   double n_sigma;          /* truncation half-width in standard deviations, > 0 */
   const double* mu[2];     /* dev [M[d]] FP64                                    */
   const double* sigma[2];  /* dev [M[d]] FP64; <= 0 or non-finite -> NaN rows    */
+  int32_t precision;       /* operands of the contraction: VUP_FP32 (0), VUP_BF16,
+                              VUP_BF16X2 (see vup_propagate_separable)           */
 } vup_sepdists;
 
 /* --------------------------------------------------------------------------
@@ -240,14 +242,21 @@ size_t vup_separable_workspace_bytes(const vup_mm* mm, int32_t Mx, int32_t My);
  *   P[k][b] = sum_ix A_x[ix][mx] T[ix][b][my] / (Zx[mx] Zy[my]),
  *   T[ix][b][my] = sum_{iy : bin(ix,iy) = b} A_y[iy][my].
  * T is a scatter over one axis; the contraction over the other is a banded
- * dense product evaluated on the matrix cores (FP32 MFMA). Same outputs and
+ * dense product evaluated on the matrix cores. s->precision picks its
+ * operands: VUP_FP32 (FP32 MFMA), VUP_BF16 (A_x and T rounded to bfloat16,
+ * nearest even; BF16 MFMA with FP32 accumulation; each term within
+ * (1 + 2^-8)^2 - 1 of the FP32 operands' product, so a column's L1 error
+ * grows by at most about 2^-7) or VUP_BF16X2 (each operand as hi + lo
+ * bfloat16, the product as hi*hi + hi*lo + lo*hi: within 3 * 2^-16 per
+ * term). T stays FP32 in the workspace either way. Same outputs and
  * conventions as vup_propagate with K = M[0]*M[1], ncomp = 1 (Z[k] =
  * Zx[mx] * Zy[my], the window mass). T is built from the model matrix's runs
  * of equal bin along y (one difference of FP64 prefix sums per run). Families
  * with M[1] < 16 (e.g. one shared alpha factor) are too narrow for the
  * contraction's tiles and are propagated by the general sweep of
- * vup_propagate (FP32) instead, with the same outputs. Needs ndim == 2, and
- * B <= 512 when n[1] > 65534.
+ * vup_propagate (FP32 densities, whatever s->precision) instead, with the
+ * same outputs. Needs ndim == 2, and B <= 512 when n[1] > 65534.
+ * EINVAL: precision other than VUP_FP32, VUP_BF16, VUP_BF16X2.
  *   ws: dev, 256-byte aligned, ws_bytes >= vup_separable_workspace_bytes.
  * ------------------------------------------------------------------------ */
 int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, size_t ws_bytes,

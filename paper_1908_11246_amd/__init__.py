@@ -60,7 +60,8 @@ class VupDists(ctypes.Structure):
 
 class VupSepDists(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32 * 2), ("n_sigma", ctypes.c_double),
-                ("mu", ctypes.c_void_p * 2), ("sigma", ctypes.c_void_p * 2)]
+                ("mu", ctypes.c_void_p * 2), ("sigma", ctypes.c_void_p * 2),
+                ("precision", ctypes.c_int32)]
 
 
 class VupMM(ctypes.Structure):
@@ -340,8 +341,10 @@ class SeparableWorkspace:
 
 
 def propagate_separable(mm: ModelMatrix, mu_x, mu_y, sigma_x, sigma_y, n_sigma: float = 4.0,
-                        ws: Optional[SeparableWorkspace] = None, want_Z: bool = True):
-    """eq. VUP for the tensor-product family k = mx*My + my (banded MFMA form)."""
+                        ws: Optional[SeparableWorkspace] = None, want_Z: bool = True,
+                        precision: str = "fp32"):
+    """eq. VUP for the tensor-product family k = mx*My + my (banded MFMA form);
+    precision "fp32", "bf16" or "bf16x2" picks the contraction's operands."""
     mx = _dev_f64(mu_x, mm.device)
     my = _dev_f64(mu_y, mm.device)
     sx = _dev_f64(sigma_x, mm.device)
@@ -356,6 +359,7 @@ def propagate_separable(mm: ModelMatrix, mu_x, mu_y, sigma_x, sigma_y, n_sigma: 
     s.n_sigma = float(n_sigma)
     s.mu[0], s.mu[1] = mx.data_ptr(), my.data_ptr()
     s.sigma[0], s.sigma[1] = sx.data_ptr(), sy.data_ptr()
+    s.precision = PRECISIONS[precision]
     _check(_load().vup_propagate_separable(ctypes.byref(mm.mm), ctypes.byref(s), _vp(ws.ptr),
                                            ws.nbytes, _ptr(P), _ptr(Z), _vp(_stream())))
     return P, Z, ws

@@ -21,6 +21,8 @@
 //   k_sep_gemm       the banded contraction on the matrix cores, 16x16x4 FP32
 //                    MFMA, LDS-staged T blocks, one workgroup per 16 my x 4
 //                    bins x 256 mx
+//   k_sep_gemm_bf16  the same with BF16 operands (or hi + lo BF16 pairs) on
+//                    16x16x32 BF16 MFMA, FP32 accumulation
 // Families with fewer than 16 locations along y (e.g. one shared alpha factor,
 // M_y = 1) give the contraction too few columns to fill its tiles; they are
 // propagated by the general sweep instead (k_sep_expand writes their per-
@@ -45,8 +47,11 @@ struct SepArgs {
   int pitch;
   const uint16_t* binmap;
   // workspace
-  float* A[2];     // A_x: [n_x + 16][ldA0], zero past n_x and past M_x; A_y: [n_y][M_y]
+  float* A[2];     // A_x: [n_x + 32][ldA0], zero past n_x and past M_x; A_y: [n_y][M_y]
   int ldA0;        // M_x rounded up to a multiple of 256
+  __bf16* At[2];   // A_x rounded to BF16, hi and lo = bf16(A - hi), transposed:
+                   // [ldA0][ldt], zero past n_x (the BF16 contraction's operands)
+  int ldt;         // n_x + 32 rounded up to a multiple of 8
   double* Zd[2];   // [M_d]
   int* win[2];     // [M_d][2]
   float* T;        // [n_x][B][M_y]
@@ -59,18 +64,28 @@ struct SepArgs {
 };
 
 // one block per (axis, m): column m of A_d, its sum and its window. A_x also
-// gets its zero padding (16 rows past n_x, columns up to ldA0), so that the
-// contraction reads it without bounds checks.
+// gets its zero padding (32 rows past n_x, columns up to ldA0), so that the
+// contractions read it without bounds checks.
 __global__ __launch_bounds__(256) void k_axis_factors(SepArgs a) {
   const int d = blockIdx.y;
   const int m = blockIdx.x;
   const int ld = d == 0 ? a.ldA0 : a.M[1];
   const int n = a.n[d];
-  const int rows = d == 0 ? n + 16 : n;
+  const int rows = d == 0 ? n + 32 : n;
   if (m >= ld) return;
   float* col = a.A[d] + m;
+  // axis x also writes its transposed BF16 rows (ldt >= rows entries)
+  const int rowsw = d == 0 ? a.ldt : rows;
+  __bf16* th = d == 0 ? a.At[0] + (long long)m * a.ldt : nullptr;
+  __bf16* tl = d == 0 ? a.At[1] + (long long)m * a.ldt : nullptr;
   if (m >= a.M[d]) {
-    for (int i = threadIdx.x; i < rows; i += 256) col[(long long)i * ld] = 0.0f;
+    for (int i = threadIdx.x; i < rowsw; i += 256) {
+      if (i < rows) col[(long long)i * ld] = 0.0f;
+      if (d == 0) {
+        th[i] = (__bf16)0.0f;
+        tl[i] = (__bf16)0.0f;
+      }
+    }
     return;
   }
   __shared__ double red[kWaves];
@@ -78,12 +93,19 @@ __global__ __launch_bounds__(256) void k_axis_factors(SepArgs a) {
   int jlo, jhi;
   const bool ok = axis_window(a.lo[d], a.hi[d], n, mu, sg, a.ns, jlo, jhi);
   double zp = 0.0;
-  for (int i = threadIdx.x; i < rows; i += 256) {
+  for (int i = threadIdx.x; i < rowsw; i += 256) {
     float v = 0.0f;
     if (ok && i < n && i >= jlo && i <= jhi)
       v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg);
-    col[(long long)i * ld] = v;
-    zp += (double)v;
+    if (i < rows) {
+      col[(long long)i * ld] = v;
+      zp += (double)v;
+    }
+    if (d == 0) {
+      const __bf16 h = (__bf16)v;
+      th[i] = h;
+      tl[i] = (__bf16)(v - (float)h);
+    }
   }
   const double Z = block_sum(zp, red);
   if (threadIdx.x == 0) {
@@ -537,6 +559,202 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
   }
 }
 
+// The same contraction on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation): A_x and T rounded to BF16 (nearest even), or, with
+// SPLIT, each written as hi + lo (hi = bf16(v), lo = bf16(v - hi)) and the
+// product taken as hi hi + hi lo + lo hi (the dropped lo lo term is below
+// 2^-16 of it). One MFMA covers 32 rows of ix: lane (li, g) holds rows
+// ix0 + 8 g .. + 7 of A's column mx and of T's column my, the same rows in
+// the same slots of both operands, so the sum over the chunk does not depend
+// on how the instruction orders its k. T blocks are staged in LDS as BF16
+// with ix contiguous ([bin][my][ix], row pitch 40), so a lane's eight values
+// are one 16-byte read; A_x comes as the transposed BF16 copies that
+// k_axis_factors writes (rows of ix, zero past n_x), also one 16-byte read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int NB, bool SPLIT>
+__global__ __launch_bounds__(256, 4) void k_sep_gemm_bf16(SepArgs a) {
+  constexpr int kPB = 40;                 // BF16 per (bin, my) row: 32 ix + 8 pad
+  constexpr int kTileB = NB * 16 * kPB;   // one chunk's T block (BF16 elements)
+  constexpr int kParts = SPLIT ? 2 : 1;   // hi (and lo) blocks
+  __shared__ __attribute__((aligned(16))) __bf16 Ts[2 * kParts * kTileB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int Mx = a.M[0], My = a.M[1], B = a.B, nx = a.n[0];
+  const int my0 = blockIdx.x * 16;
+  const int b0 = blockIdx.y * NB;
+  const int mxb = blockIdx.z * 256;
+  int tlo[4], thi[4];
+  int glo = 0x7fffffff, ghi = -1;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int mx = mxb + 16 * t + li;
+    int lo = 0x7fffffff, hi = -1;
+    if (mx < Mx) {
+      const int l = a.win[0][2 * mx], h = a.win[0][2 * mx + 1];
+      if (h >= l) {
+        lo = l;
+        hi = h;
+      }
+    }
+    for (int o = 8; o > 0; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o, 64));
+      hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    glo = min(glo, lo);
+    ghi = max(ghi, hi);
+    if ((t & 3) == w) {
+      tlo[t >> 2] = lo;
+      thi[t >> 2] = hi;
+    }
+  }
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[j][q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  if (ghi >= glo) {
+    const bool vec = (My & 3) == 0;
+    // staging: element e = threadIdx.x + 256 u -> (ix row of the chunk, bin
+    // q, four my); 32 rows x NB bins x 4 float4 = 128 NB float4 per chunk
+    constexpr int kPer = NB / 2;
+    auto load_t = [&](int ix0, float4 (&tv)[kPer]) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int ix = ix0 + e / (4 * NB);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int b = b0 + (e >> 2) % NB, my = my0 + 4 * (e & 3);
+        if (ix <= ghi && ix < nx && b < B) {
+          const float* src = a.T + ((long long)ix * B + b) * My + my;
+          if (vec && my + 3 < My) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else {
+            if (my < My) v.x = src[0];
+            if (my + 1 < My) v.y = src[1];
+            if (my + 2 < My) v.z = src[2];
+            if (my + 3 < My) v.w = src[3];
+          }
+        }
+        tv[u] = v;
+      }
+    };
+    auto store_t = [&](int buf, const float4 (&tv)[kPer]) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int r = e / (4 * NB), q = (e >> 2) % NB, m4 = 4 * (e & 3);
+        __bf16* hi = Ts + (buf * kParts) * kTileB + (q * 16 + m4) * kPB + r;
+        const float v[4] = {tv[u].x, tv[u].y, tv[u].z, tv[u].w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const __bf16 h = (__bf16)v[m];
+          hi[m * kPB] = h;
+          if constexpr (SPLIT) hi[kTileB + m * kPB] = (__bf16)(v[m] - (float)h);
+        }
+      }
+    };
+    // A operands: row mx of the transposed BF16 copies, ix0 + 8 lg .. + 7 in
+    // one 16-byte load (rows are zero past n_x up to ix n_x + 31)
+    const long long ldt = a.ldt;
+    const __bf16* Ah = a.At[0] + (long long)(mxb + 16 * w + li) * ldt + 8 * lg;
+    const __bf16* Al = a.At[1] + (long long)(mxb + 16 * w + li) * ldt + 8 * lg;
+    auto live = [&](int j, int ix0) { return tlo[j] <= ix0 + 31 && thi[j] >= ix0; };
+    auto load_a = [&](int ix0, bf16x8 (&h)[4], bf16x8 (&l)[4]) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (live(j, ix0)) {
+          h[j] = *reinterpret_cast<const bf16x8*>(Ah + 64 * j * ldt + ix0);
+          if constexpr (SPLIT) l[j] = *reinterpret_cast<const bf16x8*>(Al + 64 * j * ldt + ix0);
+        }
+      }
+    };
+    const int c0 = glo >> 5, c1 = ghi >> 5;
+    float4 tv[kPer];
+    load_t(32 * c0, tv);
+    store_t(0, tv);
+    // BF16: the next chunk's A is loaded during the current MFMAs (ping-pong
+    // registers); SPLIT holds twice the operands and loads each chunk's A at
+    // its start instead, which keeps both variants within 128 VGPRs
+    auto mfmas = [&](int ix0, int buf, const bf16x8 (&ch)[4], const bf16x8 (&cl)[4]) {
+      const __bf16* Th = Ts + (buf * kParts) * kTileB + li * kPB + 8 * lg;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (live(j, ix0)) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const bf16x8 th = *reinterpret_cast<const bf16x8*>(Th + q * 16 * kPB);
+            acc[j][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[j], th, acc[j][q], 0, 0, 0);
+            if constexpr (SPLIT) {
+              const bf16x8 tl = *reinterpret_cast<const bf16x8*>(Th + kTileB + q * 16 * kPB);
+              acc[j][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[j], tl, acc[j][q], 0, 0, 0);
+              acc[j][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl[j], th, acc[j][q], 0, 0, 0);
+            }
+          }
+        }
+      }
+    };
+    if constexpr (SPLIT) {
+      // twice the operands: each chunk's A is loaded at its start
+      bf16x8 h[4], l[4];
+      __syncthreads();
+      for (int c = c0, buf = 0; c <= c1; ++c, buf ^= 1) {
+        const int ix0 = 32 * c;
+        const bool more = c < c1;
+        if (more) load_t(ix0 + 32, tv);
+        load_a(ix0, h, l);
+        mfmas(ix0, buf, h, l);
+        if (more) store_t(buf ^ 1, tv);
+        __syncthreads();
+      }
+    } else {
+      // the next chunk's A is loaded during the current MFMAs (ping-pong)
+      bf16x8 ha[4], hb[4], unused[4];
+      load_a(32 * c0, ha, unused);
+      __syncthreads();
+      auto step = [&](int c, int buf, bf16x8 (&ch)[4], bf16x8 (&nh)[4]) {
+        const int ix0 = 32 * c;
+        const bool more = c < c1;
+        if (more) {
+          load_t(ix0 + 32, tv);
+          load_a(ix0 + 32, nh, unused);
+        }
+        mfmas(ix0, buf, ch, unused);
+        if (more) store_t(buf ^ 1, tv);
+        __syncthreads();
+      };
+      for (int c = c0; c <= c1; c += 2) {
+        step(c, 0, ha, hb);
+        if (c + 1 <= c1) step(c + 1, 1, hb, ha);
+      }
+    }
+  }
+  const int my = my0 + li;
+  if (my >= My) return;
+  const double zy = a.Zd[1][my];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mx = mxb + 16 * (4 * j + w) + 4 * lg + r;
+      if (mx >= Mx) continue;
+      const double z = a.Zd[0][mx] * zy;
+      const double rz = 1.0 / z;
+      const long long k = (long long)mx * My + my;
+      float* dst = a.P + k * B + b0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const float o = (z > 0.0) ? (float)((double)acc[j][q][r] * rz)
+                                  : (z == 0.0 ? 0.0f : __builtin_nanf(""));
+        if (b0 + q < B) dst[q] = o;
+      }
+      if (a.Z && blockIdx.y == 0) a.Z[k] = z;
+    }
+  }
+}
+
 // per-distribution parameters of a family propagated by the general sweep:
 // mu[k][0][d], sigma[k][0][d] for k = mx M_y + my
 __global__ __launch_bounds__(256) void k_sep_expand(int Mx, int My, const double* mux,
@@ -556,18 +774,20 @@ size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My) {
   if (My < kSepMinMy) return 2 * al((size_t)Mx * My * 2 * sizeof(double));
   size_t o = 0;
   const size_t ld0 = ((size_t)Mx + 255) / 256 * 256;
-  o += al(((size_t)g.n[0] + 16) * ld0 * 4);
+  o += al(((size_t)g.n[0] + 32) * ld0 * 4);
   o += al((size_t)g.n[1] * My * 4);
   o += al((size_t)Mx * 8) + al((size_t)My * 8);
   o += al((size_t)Mx * 8) + al((size_t)My * 8);
   o += al((size_t)g.n[0] * B * My * 4);
   o += al((size_t)(g.n[1] + 1) * My * 8);
+  const size_t ldt = ((size_t)g.n[0] + 32 + 7) / 8 * 8;
+  o += 2 * al(ld0 * ldt * 2);
   return o;
 }
 
 hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x,
                             const double* mu_y, const double* sg_x, const double* sg_y,
-                            double ns, void* ws, float* P, double* Z, hipStream_t s) {
+                            double ns, int prec, void* ws, float* P, double* Z, hipStream_t s) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   if (My < kSepMinMy) {
     const long long K = (long long)Mx * My;
@@ -606,7 +826,7 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   char* w = static_cast<char*>(ws);
   a.ldA0 = (Mx + 255) / 256 * 256;
   a.A[0] = reinterpret_cast<float*>(w);
-  w += al(((size_t)a.n[0] + 16) * a.ldA0 * 4);
+  w += al(((size_t)a.n[0] + 32) * a.ldA0 * 4);
   a.A[1] = reinterpret_cast<float*>(w);
   w += al((size_t)a.n[1] * My * 4);
   a.Zd[0] = reinterpret_cast<double*>(w);
@@ -620,6 +840,11 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   a.T = reinterpret_cast<float*>(w);
   w += al((size_t)a.n[0] * mm.B * My * 4);
   a.G = reinterpret_cast<double*>(w);
+  w += al(((size_t)a.n[1] + 1) * My * 8);
+  a.ldt = (a.n[0] + 32 + 7) / 8 * 8;
+  a.At[0] = reinterpret_cast<__bf16*>(w);
+  w += al((size_t)a.ldA0 * a.ldt * 2);
+  a.At[1] = reinterpret_cast<__bf16*>(w);
   a.runs = reinterpret_cast<const uint32_t*>(static_cast<const char*>(mm.ws) + mm.off_runs);
   a.rowptr = reinterpret_cast<const int*>(static_cast<const char*>(mm.ws) + mm.off_rowptr);
   a.P = P;
@@ -657,9 +882,17 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int NB = kSepBins;
-  hipLaunchKernelGGL((k_sep_gemm<NB>), dim3((My + 15) / 16, (mm.B + NB - 1) / NB,
-                                            (Mx + 255) / 256),
-                     dim3(256), 0, s, a);
+  const dim3 grid((My + 15) / 16, (mm.B + NB - 1) / NB, (Mx + 255) / 256);
+  // the BF16 contraction takes two bins per workgroup (its operand registers
+  // then fit the 128-VGPR budget of four waves per SIMD)
+  constexpr int NBH = 2;
+  const dim3 gridh((My + 15) / 16, (mm.B + NBH - 1) / NBH, (Mx + 255) / 256);
+  if (prec == VUP_BF16)
+    hipLaunchKernelGGL((k_sep_gemm_bf16<NBH, false>), gridh, dim3(256), 0, s, a);
+  else if (prec == VUP_BF16X2)
+    hipLaunchKernelGGL((k_sep_gemm_bf16<NBH, true>), gridh, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sep_gemm<NB>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -236,6 +236,9 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
     return fail(VUP_EINVAL, "n_sigma must be finite and > 0");
   if (!s->mu[0] || !s->mu[1] || !s->sigma[0] || !s->sigma[1] || !P)
     return fail(VUP_EINVAL, "mu, sigma or P is NULL");
+  if (s->precision != VUP_FP32 && s->precision != VUP_BF16 && s->precision != VUP_BF16X2)
+    return fail(VUP_EINVAL, "separable precision %d: VUP_FP32, VUP_BF16 or VUP_BF16X2",
+                s->precision);
   if (!ws) return fail(VUP_EWORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VUP_EWORKSPACE, "workspace not 256-byte aligned");
   const size_t need = vup::sep_workspace_bytes(mm->grid, mm->B, s->M[0], s->M[1]);
@@ -244,7 +247,8 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
   if (s->M[1] < 16 && (r = check_sweep(mm, vup::kSweepPropagate))) return r;
   if ((r = check_device())) return r;
   return launched(vup::launch_separable(*mm, s->M[0], s->M[1], s->mu[0], s->mu[1], s->sigma[0],
-                                        s->sigma[1], s->n_sigma, ws, P, Z, (hipStream_t)stream),
+                                        s->sigma[1], s->n_sigma, s->precision, ws, P, Z,
+                                        (hipStream_t)stream),
                   "vup_propagate_separable");
 }
 

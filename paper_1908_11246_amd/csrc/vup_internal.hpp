@@ -63,7 +63,7 @@ bool runs_allowed(const vup_mm& mm);
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My);
 hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x,
                             const double* mu_y, const double* sg_x, const double* sg_y,
-                            double ns, void* ws, float* P, double* Z, hipStream_t s);
+                            double ns, int prec, void* ws, float* P, double* Z, hipStream_t s);
 
 // workspace sizing shared by vup_bin_workspace_bytes and vup_bin
 struct WsLayout {

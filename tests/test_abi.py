@@ -267,3 +267,35 @@ def test_posterior_arguments(lib):
                 None) == EINVAL
     assert post(ctypes.byref(vup.VupMM()), ctypes.byref(d), 3, dummy, dummy, dummy, dummy, None,
                 None) == EWORKSPACE
+
+
+def test_separable_arguments(lib):
+    mm = _fake_mm(lib)
+    dummy = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    need = lib.vup_separable_workspace_bytes(ctypes.byref(mm), 20, 20)
+    assert need > 0
+    s = vup.VupSepDists()
+    s.M[0], s.M[1] = 20, 20
+    s.n_sigma = 4.0
+    s.mu[0], s.mu[1], s.sigma[0], s.sigma[1] = 0x1000, 0x2000, 0x3000, 0x4000
+    sep = lib.vup_propagate_separable
+    # the contraction's operand format: FP32, BF16 or split BF16 only
+    for bad in (3, -1, 7):
+        s.precision = bad
+        assert sep(ctypes.byref(mm), ctypes.byref(s), ws, need, dummy, None, None) == EINVAL
+        assert b"precision" in lib.vup_last_error()
+    s.precision = 1
+    assert sep(ctypes.byref(mm), ctypes.byref(s), ws, need - 1, dummy, None, None) == EWORKSPACE
+    assert sep(ctypes.byref(mm), ctypes.byref(s), ctypes.c_void_p(0x100001), need, dummy, None,
+               None) == EWORKSPACE
+    s.M[1] = 0
+    assert sep(ctypes.byref(mm), ctypes.byref(s), ws, need, dummy, None, None) == EINVAL
+    s.M[1] = 20
+    s.n_sigma = 0.0
+    assert sep(ctypes.byref(mm), ctypes.byref(s), ws, need, dummy, None, None) == EINVAL
+    s.n_sigma = 4.0
+    assert sep(ctypes.byref(mm), ctypes.byref(s), ws, need, None, None, None) == EINVAL
+    mm3 = _fake_mm(lib, n=(4, 4))
+    mm3.grid = _grid((4, 4, 4), (0, 0, 0), (1, 1, 1))
+    assert sep(ctypes.byref(mm3), ctypes.byref(s), ws, need, dummy, None, None) == EUNSUPPORTED

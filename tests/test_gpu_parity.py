@@ -551,12 +551,12 @@ def test_autograd_function_matches_adjoint(vup):
 # ---------------------------------------------------------------------------
 # separable (banded MFMA) form for tensor-product families
 # ---------------------------------------------------------------------------
-def _sep_case(vup, orc, n, lo, hi, model, B, mux, muy, sgx, sgy, label):
-    _say(f"[separable {label}] n={n} B={B} M=({len(mux)},{len(muy)})")
+def _sep_case(vup, orc, n, lo, hi, model, B, mux, muy, sgx, sgy, label, precision="fp32"):
+    _say(f"[separable {label}] n={n} B={B} M=({len(mux)},{len(muy)}) {precision}")
     g = vup.make_grid(n, lo, hi)
     f = vup.eval_grid(g, model)
     mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, B))
-    P, Z, _ = vup.propagate_separable(mm, mux, muy, sgx, sgy)
+    P, Z, _ = vup.propagate_separable(mm, mux, muy, sgx, sgy, precision=precision)
     # the same K = Mx*My distributions through the general path and the oracle
     Mx, My = len(mux), len(muy)
     mu = np.zeros((Mx * My, 1, 2))
@@ -628,6 +628,66 @@ def test_separable_ipsa_example_full_size(vup, orc, s_l):
     _check_P(_cpu(P), Po, 2e-5, f"P separable Sec. 5.3 example sigma_l={s_l}")
 
 
+# Bars of the BF16 contractions against the FP64 oracle. Every term a t of
+# the contraction is non-negative (a = A_x factor, t = T sum of A_y factors)
+# and the terms of a column sum to its mass 1. BF16 keeps 8 significant
+# bits, so a and t rounded to nearest even are within 2^-8 of themselves and
+# the product within (1 + 2^-8)^2 - 1 = 2^-7 + 2^-16 of a t; the column's L1
+# error grows by at most that over the FP32 form's 2e-5 (FP32 operands and
+# accumulation). Families with few x cells per window get close to it (a
+# column then sums a handful of terms, so little of the rounding cancels:
+# 4.8e-3 on 6 x cells). Split BF16: hi + lo is within 2^-16 of each operand
+# and the dropped lo*lo term is below 2^-16 a t, so each term is within
+# 3 * 2^-16 of a t. The same bounds hold for the column sums (|sum - 1|).
+SEP_BARS = {"bf16": 2e-5 + 2.0 ** -7 + 2.0 ** -16, "bf16x2": 2e-5 + 3 * 2.0 ** -16}
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2"])
+def test_separable_bf16_grid64(vup, orc, precision):
+    wl = workloads.grid64()
+    m = workloads.subgrid_midpoints(-3.0, 3.0, 16)
+    s = np.full(16, 0.25)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, wl.n, wl.lo, wl.hi, wl.model, wl.B, m, m, s, s,
+                                           "grid64", precision)
+    bar = SEP_BARS[precision]
+    _check_P(Pg, Po, bar, f"P separable {precision} vs oracle", tol_sum=bar)
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("case", [c for c in SEP_PATHS if c[3] >= 16],
+                         ids=[c[0] for c in SEP_PATHS if c[3] >= 16])
+def test_separable_bf16_paths(vup, orc, case, precision):
+    """The BF16 contractions on rows over 4096 and over 65534 cells and on more
+    than 256 x locations (chunks of 32 rows of ix, ragged at both ends)."""
+    label, n, Mx, My, B = case
+    lo, hi = (-2.0, -3.0), (2.5, 3.0)
+    rng = np.random.default_rng(sum(n) + Mx)
+    mux = rng.uniform(lo[0], hi[0], Mx)
+    muy = rng.uniform(lo[1], hi[1], My)
+    sgx = rng.uniform(0.1, 0.8, Mx)
+    sgy = rng.uniform(0.01, 0.5, My)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "sincos2", B, mux, muy, sgx, sgy,
+                                           label, precision)
+    bar = SEP_BARS[precision]
+    _check_P(Pg, Po, bar, f"P separable {precision} {label}", tol_sum=bar)
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2"])
+def test_separable_bf16_1024_family_all_rows(vup, orc, precision):
+    """The BF16 contractions on the full-size 1024^2 family (256 x 256
+    locations, shared sigma = 0.25): every row against the oracle."""
+    n, lo, hi, B, M = (1024, 1024), (-3.0, -3.0), (3.0, 3.0), 256, 256
+    m = workloads.subgrid_midpoints(lo[0], hi[0], M)
+    s = np.full(M, 0.25)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "sincos2", B, m, m, s, s,
+                                           "1024^2 family, all rows", precision)
+    bar = SEP_BARS[precision]
+    _check_P(Pg, Po, bar, f"P separable {precision} 1024^2 family", tol_sum=bar)
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
 def test_separable_1024_family_all_rows(vup, orc):
     """The banded form on the full-size tensor-product family: 1024^2 grid on
     [-3,3]^2, sincos model, B = 256, 256 x 256 locations on the midpoint
@@ -662,7 +722,8 @@ def test_separable_paths(vup, orc, case):
     assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
 
 
-def test_separable_ragged_and_edge_cases(vup, orc):
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x2"])
+def test_separable_ragged_and_edge_cases(vup, orc, precision):
     rng = np.random.default_rng(50)
     n, lo, hi = (61, 75), (-3.0, -2.0), (3.0, 2.5)
     mux = rng.uniform(-3.2, 3.2, 37)
@@ -672,12 +733,14 @@ def test_separable_ragged_and_edge_cases(vup, orc):
     mux[3] = 30.0          # empty window on x: whole row block of k is zero
     sgy[5] = 0.0           # invalid: NaN rows
     Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "timing2", 45, mux, muy, sgx,
-                                           sgy, "ragged")
+                                           sgy, "ragged", precision)
     k = np.arange(37 * 21)
     bad = (k % 21) == 5
     empty = (k // 21) == 3
     ok = ~bad & ~empty
-    _check_P(Pg[ok], Po[ok], 2e-5, "P separable ragged")
+    bar = SEP_BARS.get(precision, 2e-5)
+    _check_P(Pg[ok], Po[ok], bar, f"P separable ragged {precision}",
+             tol_sum=SEP_BARS.get(precision, 1e-6))
     assert np.isnan(Pg[bad]).all() and np.isnan(Zg[bad]).all()
     assert (Pg[empty & ~bad] == 0).all() and (Zg[empty & ~bad] == 0).all()
 
