@@ -984,9 +984,12 @@ __device__ __forceinline__ void prop_runs(const SweepArgs& a, float* smem, int r
   }
 }
 
-// RR: rows per row-table pass (the layout's rrows)
+// RR: rows per row-table pass (the layout's rrows). Seven waves per SIMD: at
+// eight the 64-VGPR budget spilled a few per-thread addresses of the finish,
+// and their scratch writes doubled the kernel's HBM write traffic (138 MB per
+// launch at grid1024 against the 67 MB of P) for no gain in time
 template <int RR>
-__global__ __launch_bounds__(kThreads, 8) void k_propagate_runs(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
   extern __shared__ float smem[];
   if (!runs_chosen(a)) return;  // k_propagate does the work
   const long long k = block_k(a);
@@ -1187,10 +1190,16 @@ __global__ __launch_bounds__(kThreads) void k_moments(SweepArgs a) {
     __syncthreads();
     build_tables(a, smem, w, kc, sw, colbase, ns);
     double A1 = 0.0, A2 = 0.0;
+    // row tables with the incremental digits (no division per row); chunks
+    // of kRowChunk rows, a multiple of the workgroup size
+    static_assert(kRowChunk % kThreads == 0, "row chunks of whole workgroup steps");
+    RowIt it;
+    rowit_init(it, threadIdx.x, w, D);
+    const RowIt step = rowit_step_digits(w, D);
     for (long long r0 = 0; r0 < w.R; r0 += kRowChunk) {
       const int rc = (int)((w.R - r0) < kRowChunk ? (w.R - r0) : kRowChunk);
       __syncthreads();
-      build_rows(a, smem, w, r0, rc, kc, false);
+      build_rows_prop(a, smem, w, rc, it, step);
       __syncthreads();
       mom_rows<8>(a, smem, rc, colbase, ns, shift, A1, A2);
     }

@@ -15,8 +15,9 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kRowChunk = 512;    // rows of the row table held in LDS at once
 // rows per row-table pass of the run-form propagation when many distributions
 // are propagated: 256 keeps a workgroup's LDS near 20 KB at 1024-cell rows, so
-// eight workgroups (eight waves per SIMD, the kernel held to 64 VGPRs) fit on
-// a CU; with fewer distributions than resident workgroups, 512 (fewer passes)
+// seven workgroups (seven waves per SIMD, the kernel held to 72 VGPRs without
+// spills) fit on a CU; with fewer distributions than resident workgroups, 512
+// (fewer passes)
 constexpr int kRunRowChunk = 256;
 // rows per row-table pass of the cell-form propagation (8-byte entries, 4 KB;
 // a multiple of the workgroup size, as its row builder steps by whole
