@@ -25,7 +25,7 @@ def build(verbose: bool = False) -> str:
 
 
 def build_sanitized(verbose: bool = False) -> str:
-    """The oracle with its sanitizer driver (san_check.c) as one host
+    """The oracle with its sanitizer harness (san_check.c) as one host
     executable under AddressSanitizer and UndefinedBehaviorSanitizer, every
     report fatal. CPU only; the GPU library is never built this way."""
     cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",

@@ -1,5 +1,5 @@
 /*
- * Sanitizer driver for the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ * Sanitizer harness for the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
  *
  * Built together with vup_oracle.c under AddressSanitizer and
  * UndefinedBehaviorSanitizer (host code only, gcc) by oracle/build.py's
