@@ -667,7 +667,7 @@ def test_workload_generators_shapes():
 
 
 def test_oracle_clean_under_address_and_ub_sanitizers():
-    """The oracle's C code, with a driver calling every exported function on
+    """The oracle's C code, with a harness calling every exported function on
     1- to 4-D grids, mixtures, every density precision, frozen windows and the
     degenerate inputs it defines outputs for, built under AddressSanitizer and
     UndefinedBehaviorSanitizer (host code only): any out-of-bounds access, use
