@@ -52,12 +52,14 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # algorithmic arithmetic per cell-distribution update, from the definitions:
 #   propagation: density (row factor x fastest-axis factor) and its add into
 #   the bin: 2 operations;
-#   exact-f moments: density, f - s, p (f - s), the add into S1 and the
-#   multiply-add into S2 (one operation, as every fused multiply-add here):
-#   5 operations.
-OPS_PER_UPDATE = {"propagate": 2, "moments": 5}
+#   exact-f moments on the matrix cores: per cell and distribution the two
+#   multiply-adds of the bilinear forms sum g (f - a) and sum g (f - a)^2
+#   (4 flops, FP64), the row factors and shifts being per row and per tile.
+OPS_PER_UPDATE = {"propagate": 2}
+MOMENTS_FLOPS_PER_UPDATE = 4
+MFMA_FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 KERNELS = {"propagate": "k_propagate_runs (run form) / k_propagate<FP32> (cell form)",
-           "moments": "k_moments"}
+           "moments": "k_mt_tiles + k_mt_prep + k_mt_main (v_mfma_f64_16x16x4_f64) + k_mt_final"}
 
 
 def traffic_bytes(kernel):
@@ -78,7 +80,7 @@ def traffic_bytes(kernel):
 # sources each measured kernel is built from (its launch and its input layout)
 KERNEL_SOURCES = {
     "propagate": ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"),
-    "moments": ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"),
+    "moments": ("k_mtiles.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp"),
     "ipsa": ("k_fields.hip", "vup_fields.hpp", "vup_device.hpp"),
 }
 
@@ -473,7 +475,7 @@ def ipsa_example_runs(vup, workloads, stream, reps):
                          "propagate_separable_ms": ms_sep}
     return res
 # kernel-name fragments of the sweep kernels in rocprofv3 output
-TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_moments", "ipsa": "k_ipsa<"}
+TRACE_NAMES = {"propagate": "k_propagate_runs", "moments": "k_mt_main", "ipsa": "k_ipsa<"}
 
 
 def _counter_rows(path):
@@ -523,7 +525,7 @@ def summarize_traffic(fetch_csv, write_csv):
 #   LDS conflict = SQ_LDS_BANK_CONFLICT / (256 CUs x cycles)
 #   MFMA busy    = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles)
 N_XCD, N_CU, N_SIMD = 8, 256, 1024
-SWEEP_FRAGMENTS = ("k_propagate", "k_moments", "k_backward")
+SWEEP_FRAGMENTS = ("k_propagate", "k_moments", "k_backward", "k_mt_main")
 
 
 def summarize_pmc(out_path, updates, csv_paths):
@@ -645,8 +647,11 @@ def main():
     # step: resolve it once (one stream sync, outside the timed steps) and set
     # it on each rebuilt matrix without a sync.
     f0 = vup.eval_grid(g, wl.model, wl.theta)
-    form = vup.build_model_matrix(g, f0, vup.uniform_edges(f0, wl.B), want_bin=False).sweep
+    mm0 = vup.build_model_matrix(g, f0, vup.uniform_edges(f0, wl.B), want_bin=False)
+    form = mm0.sweep
     log(f"[bench] FP32 sweep form: {form}")
+    # the tiled moments' workspace (per-pdf records and totals), allocated once
+    mws = vup.moments_workspace(mm0, mu, sigma)
 
     def step(timed=False):
         mark = (lambda i: ev[i].record(stream)) if timed else (lambda i: None)
@@ -660,7 +665,7 @@ def main():
         mark(3)
         P, _ = vup.propagate(mm, mu, sigma, None, "fp32", want_Z=False)
         mark(4)
-        mean, var, _ = vup.moments(mm, mu, sigma)
+        mean, var, _ = vup.moments(mm, mu, sigma, workspace=mws)
         mark(5)
         mh, vh, ent = vup.ipsa(mm, P)
         mark(6)
@@ -689,13 +694,22 @@ def main():
         ", ".join(f"{k} {v:.3f}" for k, v in part_ms.items()))
     # roofline of the longest sweep kernel of the step, and of the other one
     rooflines = {}
-    for k in ("propagate", "moments"):
-        t = part_ms[k] * 1e-3
-        ach = OPS_PER_UPDATE[k] * U / t
-        rooflines[k] = {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                        "unit": "TOP/s", "frac": ach / VALU_PEAK_OPS,
-                        "traffic": traffic_bytes(k), "kernel": KERNELS[k],
-                        "kernel_ms": part_ms[k], "ops_per_update": OPS_PER_UPDATE[k]}
+    t = part_ms["propagate"] * 1e-3
+    ach = OPS_PER_UPDATE["propagate"] * U / t
+    rooflines["propagate"] = {"bound": "alu", "achieved": ach / 1e12,
+                              "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                              "frac": ach / VALU_PEAK_OPS, "traffic": traffic_bytes("propagate"),
+                              "kernel": KERNELS["propagate"], "kernel_ms": part_ms["propagate"],
+                              "ops_per_update": OPS_PER_UPDATE["propagate"]}
+    # moments: the algorithmic FP64 matrix flops over the whole moments call
+    # (its four kernels), against the dense FP64 matrix peak
+    t = part_ms["moments"] * 1e-3
+    ach = MOMENTS_FLOPS_PER_UPDATE * U / t / 1e12
+    rooflines["moments"] = {"bound": "mfma", "achieved": ach, "peak": MFMA_FP64_PEAK_TFLOPS,
+                            "unit": "TFLOP/s", "frac": ach / MFMA_FP64_PEAK_TFLOPS,
+                            "traffic": traffic_bytes("moments"), "kernel": KERNELS["moments"],
+                            "kernel_ms": part_ms["moments"],
+                            "flops_per_update": MOMENTS_FLOPS_PER_UPDATE}
     # the IPSA column statistics stream P once: HBM bound, K*B*4 bytes read
     # plus mean, variance and entropy (3*K*8 bytes) written
     ipsa_bytes = wl.K * wl.B * 4 + 3 * wl.K * 8

@@ -280,10 +280,45 @@ int vup_propagate_separable(const vup_mm* mm, const vup_sepdists* s, void* ws, s
  *   only for delta2 (may be NULL when delta2 is NULL); it must be a model of
  *   the grid's ndim (EINVAL otherwise).
  * Moments are of the f given to vup_bin (its FP32 copy, held in the model
- * matrix). NaN for invalid parameters or all-empty windows.
+ * matrix). NaN for invalid parameters or all-empty windows. The kernel sums
+ * strips of 8 fastest-axis cells (columns 8m .. 8m+7) over the window's rows,
+ * so a non-finite model value gives NaN for every window whose rows hold it
+ * and whose columns meet its strip (vup_moments_tiled: only for windows that
+ * hold it).
  * ------------------------------------------------------------------------ */
 int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, double* mean,
                 double* var, double* delta2, void* stream);
+
+/* --------------------------------------------------------------------------
+ * vup_moments_tiled_workspace_bytes - device workspace of vup_moments_tiled
+ * for K pdfs: 72 + 4 + 16 bytes per pdf and 32 per tile of 64 x 64 cells
+ * (each part rounded up to 256 bytes). 0 when the tiled form does not apply
+ * (see below); then vup_moments_tiled needs no workspace.
+ * ------------------------------------------------------------------------ */
+size_t vup_moments_tiled_workspace_bytes(const vup_mm* mm, const vup_dists* d);
+
+/* --------------------------------------------------------------------------
+ * vup_moments_tiled - the outputs of vup_moments (same arguments, meaning and
+ * NaN rules) by tiles of the model values on the FP32 matrix cores. For a
+ * separable pdf the moment sums over one 64 x 64 tile are bilinear forms in
+ * the tile's model values, sum_ij gx(i) (f_ij - a)^q gy(j), q = 1, 2 (eq. UP
+ * with the Gaussian of eq. gaussh, which factors over the axes): 64 pdfs
+ * whose windows meet a tile share its model values as one matrix operand.
+ * Partial sums are FP32 over a tile (shifted by a per-tile anchor), FP64
+ * across the shift, and the tiles' contributions are added per pdf as 64-bit
+ * fixed-point integers, so results are bit-identical from run to run. The
+ * per-axis factors are exp2(-(c t)^2) in FP32 (v_exp_f32) rather than the
+ * FP64-argument factors of vup_moments: the two agree to a few 1e-7
+ * relative. A window holding a non-finite model value gives NaN (mean and
+ * variance).
+ * Applies to 2-D grids with single-component pdfs (ncomp == 1), at most 256
+ * tiles per axis and K < 2^31; other calls run vup_moments' kernel and
+ * ignore ws.
+ *   ws: dev, 256-byte aligned, ws_bytes >= vup_moments_tiled_workspace_bytes
+ *   (may be NULL when that is 0). EWORKSPACE: workspace too small.
+ * ------------------------------------------------------------------------ */
+int vup_moments_tiled(const vup_mm* mm, const vup_dists* d, const vup_model* model, void* ws,
+                      size_t ws_bytes, double* mean, double* var, double* delta2, void* stream);
 
 /* --------------------------------------------------------------------------
  * vup_ipsa - coarse-grained IPSA quantities per column (Sec. 5.2): with bin

@@ -101,6 +101,10 @@ def _load():
     lib.vup_windows.argtypes = [_P(VupGrid), _P(VupDists), _vp, _vp]
     lib.vup_propagate.argtypes = [_P(VupMM), _P(VupDists), ctypes.c_int32, _vp, _vp, _vp]
     lib.vup_moments.argtypes = [_P(VupMM), _P(VupDists), _P(VupModel), _vp, _vp, _vp, _vp]
+    lib.vup_moments_tiled_workspace_bytes.restype = ctypes.c_size_t
+    lib.vup_moments_tiled_workspace_bytes.argtypes = [_P(VupMM), _P(VupDists)]
+    lib.vup_moments_tiled.argtypes = [_P(VupMM), _P(VupDists), _P(VupModel), _vp, ctypes.c_size_t,
+                                      _vp, _vp, _vp, _vp]
     lib.vup_ipsa.argtypes = [_P(VupMM), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
     lib.vup_ipsa_backward.argtypes = [_P(VupMM), _P(VupDists), _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]
@@ -366,8 +370,14 @@ def propagate_separable(mm: ModelMatrix, mu_x, mu_y, sigma_x, sigma_y, n_sigma: 
 
 
 def moments(mm: ModelMatrix, mu, sigma, weight=None, model: Optional[str] = None,
-            theta: Sequence[float] = (), n_sigma: float = 4.0):
-    """(mean[K], var[K], delta2[K] or None) from the exact model values."""
+            theta: Sequence[float] = (), n_sigma: float = 4.0, tiled: bool = True,
+            workspace: Optional[torch.Tensor] = None):
+    """(mean[K], var[K], delta2[K] or None) from the exact model values.
+
+    ``tiled`` selects vup_moments_tiled (matrix-core tiles; 2-D grids with
+    single-component pdfs, other cases run the per-pdf kernel) over
+    vup_moments. ``workspace`` (uint8, on the device) is used when large
+    enough, else one is allocated."""
     mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
     K = mu.shape[0]
     mean = torch.empty(K, dtype=torch.float64, device=mm.device)
@@ -375,10 +385,34 @@ def moments(mm: ModelMatrix, mu, sigma, weight=None, model: Optional[str] = None
     d2 = torch.empty(K, dtype=torch.float64, device=mm.device) if model else None
     m = make_model(model, theta) if model else None
     d = _dists(mu, sigma, w, n_sigma)
-    _check(_load().vup_moments(ctypes.byref(mm.mm), ctypes.byref(d),
-                               ctypes.byref(m) if m is not None else None, _ptr(mean), _ptr(var),
+    lib = _load()
+    mref = ctypes.byref(m) if m is not None else None
+    if tiled:
+        ws, nb = _moments_ws(mm, d, workspace)
+        _check(lib.vup_moments_tiled(ctypes.byref(mm.mm), ctypes.byref(d), mref,
+                                     _ptr(ws) if ws is not None else None, nb, _ptr(mean),
+                                     _ptr(var), _ptr(d2), _vp(_stream())))
+    else:
+        _check(lib.vup_moments(ctypes.byref(mm.mm), ctypes.byref(d), mref, _ptr(mean), _ptr(var),
                                _ptr(d2), _vp(_stream())))
     return mean, var, d2
+
+
+def moments_workspace(mm: ModelMatrix, mu, sigma, weight=None, n_sigma: float = 4.0):
+    """A device workspace for ``moments(..., tiled=True)`` with these pdfs
+    (None when the tiled form does not apply)."""
+    mu, sigma, w = _norm_params(mu, sigma, weight, mm.device)
+    ws, _ = _moments_ws(mm, _dists(mu, sigma, w, n_sigma), None)
+    return ws
+
+
+def _moments_ws(mm, d, workspace):
+    nb = int(_load().vup_moments_tiled_workspace_bytes(ctypes.byref(mm.mm), ctypes.byref(d)))
+    if nb == 0:
+        return None, 0
+    if workspace is not None and workspace.numel() >= nb and workspace.data_ptr() % 256 == 0:
+        return workspace, workspace.numel()
+    return torch.empty(nb, dtype=torch.uint8, device=mm.device), nb
 
 
 def ipsa(mm: ModelMatrix, P: torch.Tensor):

@@ -15,7 +15,7 @@ INC = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libvup.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["vup_api.cpp", "k_grid.hip", "k_sweep.hip", "k_banded.hip", "k_fields.hip", "k_inverse.hip"]
+SOURCES = ["vup_api.cpp", "k_grid.hip", "k_sweep.hip", "k_mtiles.hip", "k_banded.hip", "k_fields.hip", "k_inverse.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -222,9 +222,11 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
         atomicAdd(&cnt[a.B], 1);
       }
       // anchored FP32 form: columns 8m hold f, the seven after each their
-      // difference from it (taken in FP64, rounded once)
+      // difference from it (taken in FP64, rounded once); after a non-finite
+      // anchor they hold their own values, which the difference would lose
       const int c0 = col & ~7;
-      fv = col == c0 ? (float)y : (float)(y - a.f[row * a.nL + c0]);
+      const double f0 = a.f[row * a.nL + c0];
+      fv = col == c0 ? (float)y : (float)(isfinite(f0) ? y - f0 : y);
     }
     a.binmap[p] = code;
     a.f32[p] = fv;

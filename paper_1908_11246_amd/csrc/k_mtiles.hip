@@ -1,0 +1,499 @@
+// Exact-f moments (eq. UP) of single-component pdfs on 2-D grids by tiles of
+// the model values on the FP32 matrix cores.
+//
+// A separable density is gx(i) gy(j) on cell (i, j), so its moment sums over
+// one 64 x 64 tile T of the grid are bilinear forms in the model values:
+//   S1_T = sum_ij gx(i) (f_ij - a_T) gy(j),
+//   S2_T = sum_ij gx(i) (f_ij - a_T)^2 gy(j),
+// a_T an anchor of the tile (the midpoint of its model values). A workgroup
+// keeps the tile's F' = f - a_T and F'^2 in registers as MFMA A operands and
+// takes the pdfs whose windows meet the tile 64 at a time: their factor
+// tables Gy (64 columns x 64 pdfs) and Gx (64 rows x 64 pdfs) go to LDS,
+// Y = [F'; F'^2] Gy runs on v_mfma_f64_16x16x4_f64, and the row sums
+// sum_i gx(i) Y[i][n] finish S1_T and S2_T. The contraction is FP64 because
+// the variance is a difference: an error e in S2_T or S1_T moves Var Z by
+// about e + 2 (a_T - mean) e_1, and FP32 sums carry errors relative to
+// sum g F'^2 ~ Z (a_T - mean)^2, which exceeds Z Var by a factor of up to
+// (tile range / window spread)^2 (measured: 1e-5 relative variance error with
+// FP32 accumulation on a 64 x 64 grid). With s the pdf's shift (the model
+// value at its window's centre cell), delta = a_T - s and Z_T the tile's
+// factor sum,
+//   sum_T g (f - s)   = S1_T + delta Z_T,
+//   sum_T g (f - s)^2 = S2_T + 2 delta S1_T + delta^2 Z_T     (FP64),
+// and each tile's contribution is added to the pdf's totals as a 64-bit
+// fixed-point integer: a power-of-two scale per pdf from Z and a bound of
+// |f - s| over the tiles its window meets keeps every partial total below
+// 2^60, and integer additions make the result independent of their order.
+//
+// The factors are exp(-t^2/2) = exp2(-(c t)^2), c = sqrt(log2(e)/2), with
+// c t = c (x_lo - mu)/sigma + j c h/sigma for the j-th cell of the window: two
+// FP32 constants per axis and pdf (rounded from FP64 once), one FMA, one
+// multiply and v_exp_f32 per factor, the same instructions wherever a factor
+// is formed, so the normaliser Z (the FP64 sum of the factors) and the tiles
+// use identical values.
+
+#include <math.h>
+
+#include "vup_device.hpp"
+#include "vup_internal.hpp"
+
+namespace vup {
+
+namespace {
+
+typedef double mt_f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 64;               // tile edge in cells
+constexpr int kMTMaxTiles = 256;      // tiles per axis (8-bit tile indices)
+constexpr int kRing = 512;            // candidate ring: < 64 pending + 256 per scan step
+constexpr double kC = 0.8493218002880191;  // sqrt(log2(e) / 2)
+
+struct MTRec {
+  float t0[2];    // c (x_lo - mu) / sigma per axis, x_lo the window's first cell
+  float dt[2];    // c h / sigma per axis
+  int lo[2];      // window (hi < lo: empty)
+  int hi[2];
+  double shift;   // model value at the window's centre cell
+  double Z;       // product of the per-axis factor sums
+  double sc1;     // fixed-point scales of sum g (f - s) and sum g (f - s)^2
+  double sc2;
+  int flags;      // 1 bad parameters, 2 empty window, 4 non-finite f in the window
+  int pad;
+};
+static_assert(sizeof(MTRec) == 72, "record layout");
+
+struct MTTile {
+  double a;       // anchor: midpoint of the tile's finite model values
+  double fmin, fmax;
+  int nonfinite;  // the tile holds a non-finite model value
+  int nfinite;    // finite cells
+};
+static_assert(sizeof(MTTile) == 32, "tile layout");
+
+struct MTArgs {
+  int n0, n1;           // cells along axis 0 (rows) and axis 1 (columns)
+  double lo[2], hi[2];
+  long long rowstride;  // elements per row of the padded FP32 model copy
+  const float* __restrict__ f32;
+  long long K;
+  double ns;
+  const double* __restrict__ mu;
+  const double* __restrict__ sigma;
+  int ntx, nty, parts;
+  MTRec* rec;
+  uint32_t* bbox;       // tile range of each window: tx_lo, tx_hi, ty_lo, ty_hi (8 bits each)
+  unsigned long long* acc;  // [K][2] fixed-point totals
+  MTTile* tiles;
+  double* mean;
+  double* var;
+  double* delta2;
+  vup_model model;
+  int has_model;
+};
+
+// model value of cell (row, col) from the anchored FP32 copy (columns 8m
+// hold f, the seven after each their offset from it, or their own value when
+// the anchor is not finite), in FP64
+__device__ __forceinline__ double mt_f(const MTArgs& a, int row, int col) {
+  const float* p = a.f32 + (long long)row * a.rowstride;
+  const int c0 = col & ~7;
+  const double f0 = (double)p[c0];
+  if (col == c0) return f0;
+  return isfinite(f0) ? f0 + (double)p[col] : (double)p[col];
+}
+
+// Gaussian factor of the j-th cell of a window (see the header comment)
+__device__ __forceinline__ float mt_factor(int j, float t0, float dt) {
+  const float t = __builtin_fmaf((float)j, dt, t0);
+  return __builtin_amdgcn_exp2f(-(t * t));
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// per tile: range and anchor of the model values
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mt_tiles(MTArgs a) {
+  __shared__ double smin[4], smax[4];
+  __shared__ int sbad[4], scnt[4];
+  const int tx = blockIdx.x % a.ntx, ty = blockIdx.x / a.ntx;
+  const int r0 = ty * kMT, c0 = tx * kMT;
+  double mn = INFINITY, mx = -INFINITY;
+  int bad = 0, cnt = 0;
+  for (int e = threadIdx.x; e < kMT * kMT; e += 256) {
+    const int row = r0 + (e >> 6), col = c0 + (e & 63);
+    if (row < a.n0 && col < a.n1) {
+      const double f = mt_f(a, row, col);
+      if (isfinite(f)) {
+        mn = fmin(mn, f);
+        mx = fmax(mx, f);
+        ++cnt;
+      } else {
+        bad = 1;
+      }
+    }
+  }
+  mn = wave_min_f64(mn);
+  mx = wave_max_f64(mx);
+  bad = __any(bad) ? 1 : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smin[w] = mn;
+    smax[w] = mx;
+    sbad[w] = bad;
+    scnt[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    MTTile t;
+    t.fmin = fmin(fmin(smin[0], smin[1]), fmin(smin[2], smin[3]));
+    t.fmax = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+    t.nonfinite = sbad[0] | sbad[1] | sbad[2] | sbad[3];
+    t.nfinite = scnt[0] + scnt[1] + scnt[2] + scnt[3];
+    t.a = t.nfinite ? 0.5 * t.fmin + 0.5 * t.fmax : 0.0;
+    if (!t.nfinite) t.fmin = t.fmax = 0.0;
+    a.tiles[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per pdf (one wave each): window, factor constants, normaliser, shift,
+// fixed-point scales; clears the totals
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
+  const int lane = threadIdx.x & 63;
+  const long long k = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= a.K) return;
+  MTRec r;
+  r.pad = 0;
+  r.shift = r.Z = 0.0;
+  r.sc1 = r.sc2 = 1.0;
+  int lo0, hi0, lo1, hi1;
+  const double mu0 = a.mu[2 * k], mu1 = a.mu[2 * k + 1];
+  const double s0 = a.sigma[2 * k], s1 = a.sigma[2 * k + 1];
+  const bool ok0 = axis_window(a.lo[0], a.hi[0], a.n0, mu0, s0, a.ns, lo0, hi0);
+  const bool ok1 = axis_window(a.lo[1], a.hi[1], a.n1, mu1, s1, a.ns, lo1, hi1);
+  r.flags = (!ok0 || !ok1) ? 1 : ((hi0 < lo0 || hi1 < lo1) ? 2 : 0);
+  r.lo[0] = lo0;
+  r.hi[0] = hi0;
+  r.lo[1] = lo1;
+  r.hi[1] = hi1;
+  r.t0[0] = r.t0[1] = r.dt[0] = r.dt[1] = 0.0f;
+  uint32_t bb = 1u;  // tx_lo = 1 > tx_hi = 0: meets no tile
+  if (r.flags == 0) {
+    const double rs0 = 1.0 / s0, rs1 = 1.0 / s1;
+    const double h0 = (a.hi[0] - a.lo[0]) / a.n0, h1 = (a.hi[1] - a.lo[1]) / a.n1;
+    r.t0[0] = (float)((cell_centre(a.lo[0], a.hi[0], a.n0, lo0) - mu0) * rs0 * kC);
+    r.t0[1] = (float)((cell_centre(a.lo[1], a.hi[1], a.n1, lo1) - mu1) * rs1 * kC);
+    r.dt[0] = (float)(h0 * rs0 * kC);
+    r.dt[1] = (float)(h1 * rs1 * kC);
+    double zx = 0.0, zy = 0.0;
+    for (int j = lane; j <= hi0 - lo0; j += 64) zx += (double)mt_factor(j, r.t0[0], r.dt[0]);
+    for (int j = lane; j <= hi1 - lo1; j += 64) zy += (double)mt_factor(j, r.t0[1], r.dt[1]);
+    r.Z = wave_sum(zx) * wave_sum(zy);
+    double s = mt_f(a, lo0 + (hi0 - lo0 + 1) / 2, lo1 + (hi1 - lo1 + 1) / 2);
+    if (!isfinite(s)) s = 0.0;  // the window holds a non-finite value: NaN result
+    r.shift = s;
+    // bound of |f - s| over the tiles the window meets
+    const int tx0 = lo1 / kMT, tx1 = hi1 / kMT, ty0 = lo0 / kMT, ty1 = hi0 / kMT;
+    const int ntw = tx1 - tx0 + 1, nt = ntw * (ty1 - ty0 + 1);
+    double R = 0.0;
+    for (int t = lane; t < nt; t += 64) {
+      const MTTile T = a.tiles[(long long)(ty0 + t / ntw) * a.ntx + tx0 + t % ntw];
+      if (T.nfinite) R = fmax(R, fmax(T.fmax - s, s - T.fmin));
+    }
+    R = wave_max_f64(R);
+    if (r.Z > 0.0 && R > 0.0 && isfinite(R)) {
+      // Z < 2^(ez+1), R < 2^(er+1): |sum g (f-s)| < 2^(ez+er+2) and
+      // sum g (f-s)^2 < 2^(ez+2er+3); the scales bring both below 2^60
+      const int ez = ilogb(r.Z), er = ilogb(R);
+      r.sc1 = ldexp(1.0, min(60 - (ez + er + 2), 1000));
+      r.sc2 = ldexp(1.0, min(60 - (ez + 2 * er + 3), 1000));
+    }
+    bb = (uint32_t)tx0 | ((uint32_t)tx1 << 8) | ((uint32_t)ty0 << 16) | ((uint32_t)ty1 << 24);
+  }
+  if (lane == 0) {
+    a.rec[k] = r;
+    a.bbox[k] = bb;
+    a.acc[2 * k] = 0ull;
+    a.acc[2 * k + 1] = 0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per (tile, part of the pdf list): the tile's sums of every pdf of the part
+// whose window meets it. The tile's F' = f - a_T (FP64) is staged in LDS
+// once; the workgroup scans the part for pdfs whose windows meet the tile,
+// 256 at a time into a ring, and each wave takes 16 of them at once over all
+// 64 rows: lane (li, lk) forms the column factors of pdf li for columns
+// 4s + lk (s < 16) in registers (the MFMA B operand) and, for the results it
+// holds, the row factors; the sums over rows and columns of the tile stay
+// inside the wave.
+// ---------------------------------------------------------------------------
+constexpr int kFPitch = 66;  // LDS pitch (doubles) of F': 16 lanes of an FP64 read on distinct banks
+
+__global__ __launch_bounds__(256, 4) void k_mt_main(MTArgs a) {
+  __shared__ double Fs[kMT * kFPitch];  // F'[row][col]
+  __shared__ int ring[kRing];
+  __shared__ int wcnt[4];
+  __shared__ unsigned long long nfmask[kMT];
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int part = blockIdx.x % a.parts, tile = blockIdx.x / a.parts;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const int r0 = ty * kMT, c0 = tx * kMT;
+  const MTTile T = a.tiles[tile];
+  const bool tbad = T.nonfinite != 0;  // uniform
+  if (threadIdx.x < kMT) nfmask[threadIdx.x] = 0ull;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kMT * kMT; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    const int row = r0 + i, col = c0 + j;
+    double v = 0.0;
+    if (row < a.n0 && col < a.n1) {
+      const double f = mt_f(a, row, col);
+      if (isfinite(f))
+        v = f - T.a;
+      else
+        atomicOr(&nfmask[i], 1ull << j);
+    }
+    Fs[i * kFPitch + j] = v;
+  }
+  const long long kbeg = a.K * part / a.parts, kend = a.K * (part + 1) / a.parts;
+
+  // 16 pdfs (ring positions pos .. pos + cnt - 1) on this wave
+  auto wave_batch = [&](int pos, int cnt) {
+    const bool valid = li < cnt;
+    long long k = 0;
+    int l0 = 1, h0 = 0, l1 = 1, h1 = 0;
+    float t00 = 0.0f, d0 = 0.0f, t01 = 0.0f, d1 = 0.0f;
+    if (valid) {
+      k = kbeg + ring[(pos + li) & (kRing - 1)];
+      const MTRec& r = a.rec[k];
+      l0 = r.lo[0];
+      h0 = r.hi[0];
+      l1 = r.lo[1];
+      h1 = r.hi[1];
+      t00 = r.t0[0];
+      d0 = r.dt[0];
+      t01 = r.t0[1];
+      d1 = r.dt[1];
+    }
+    // B operands: column factors of pdf li, columns 4s + lk; their sum in
+    // FP64 (exact for these FP32 values: the tile's factor sum enters as
+    // delta^2 Z_T, so an error in it would reach the variance amplified by
+    // (a_T - s)^2 / Var)
+    double gy[16];
+    double zy = 0.0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int col = c0 + 4 * s + lk;
+      float v = 0.0f;
+      if (col >= l1 && col <= h1) v = mt_factor(col - l1, t01, d1);
+      gy[s] = (double)v;
+      zy += gy[s];
+    }
+    double s1 = 0.0, s2 = 0.0, sx = 0.0;
+    const double* fl = Fs + li * kFPitch + lk;
+#pragma unroll 1
+    for (int ib = 0; ib < 4; ++ib) {
+      // Y = [F'; F'^2] Gy for rows 16 ib .. 16 ib + 15
+      mt_f64x4 y1 = {0.0, 0.0, 0.0, 0.0}, y2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const double av = fl[16 * ib * kFPitch + 4 * s];
+        y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, gy[s], y1, 0, 0, 0);
+        y2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, gy[s], y2, 0, 0, 0);
+      }
+      // lane (li, lk) holds rows 16 ib + lk + 4r of pdf li (the FP64 MFMA's
+      // layout: A[i][k], B[k][j] from lane i + 16k, resp. j + 16k; D[q + 4r][j]
+      // in lane j + 16q, slot r); weight by the row factors
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 16 * ib + lk + 4 * r;
+        float gx = 0.0f;
+        if (row >= l0 && row <= h0) gx = mt_factor(row - l0, t00, d0);
+        const double g = (double)gx;
+        s1 = __builtin_fma(g, y1[r], s1);
+        s2 = __builtin_fma(g, y2[r], s2);
+        sx += g;
+      }
+    }
+    // sums over the four lane groups (rows by residue, columns by residue)
+    s1 += __shfl_xor(s1, 16, 64);
+    s2 += __shfl_xor(s2, 16, 64);
+    sx += __shfl_xor(sx, 16, 64);
+    zy += __shfl_xor(zy, 16, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    sx += __shfl_xor(sx, 32, 64);
+    zy += __shfl_xor(zy, 32, 64);
+    if (valid && lk == 0) {
+      const MTRec& r = a.rec[k];
+      const double Zt = sx * zy;
+      const double dl = T.a - r.shift;
+      const double A1 = s1 + dl * Zt;
+      const double A2 = s2 + 2.0 * dl * s1 + dl * dl * Zt;
+      atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * r.sc1));
+      atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * r.sc2));
+      if (tbad) {
+        // does the window's part of the tile hold a non-finite value?
+        const int ra = max(l0, r0) - r0, rb = min(h0, r0 + kMT - 1) - r0;
+        const int ca = max(l1, c0) - c0, cb = min(h1, c0 + kMT - 1) - c0;
+        const unsigned long long cm =
+            (cb - ca == 63) ? ~0ull : (((1ull << (cb - ca + 1)) - 1ull) << ca);
+        unsigned long long hit = 0ull;
+        for (int i = ra; i <= rb; ++i) hit |= nfmask[i] & cm;
+        if (hit) atomicOr(&a.rec[k].flags, 4);
+      }
+    }
+  };
+
+  int head = 0, tail = 0;  // uniform
+  long long k0 = kbeg;
+  for (;;) {
+    // fill the ring up to 256 pending pdfs (or the end of the part)
+    while (tail - head < 256 && k0 < kend) {
+      const long long k = k0 + threadIdx.x;
+      bool hit = false;
+      if (k < kend) {
+        const uint32_t bb = a.bbox[k];
+        hit = tx >= (int)(bb & 255u) && tx <= (int)((bb >> 8) & 255u) &&
+              ty >= (int)((bb >> 16) & 255u) && ty <= (int)(bb >> 24);
+      }
+      const unsigned long long m = __ballot(hit);
+      __syncthreads();  // earlier readers of wcnt are done
+      if (lane == 0) wcnt[w] = __popcll(m);
+      __syncthreads();
+      int off = tail;
+      for (int v = 0; v < w; ++v) off += wcnt[v];
+      if (hit)
+        ring[(off + __popcll(m & ((1ull << lane) - 1ull))) & (kRing - 1)] = (int)(k - kbeg);
+      tail += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      k0 += 256;
+    }
+    const int avail = min(tail - head, 256);
+    if (avail == 0) break;
+    __syncthreads();  // ring entries and the staged tile are visible
+    // wave w: pending pdfs 64w .. 64w + 63, 16 at a time
+    for (int b = 64 * w; b < min(64 * w + 64, avail); b += 16) wave_batch(head + b, min(16, avail - b));
+    head += avail;
+    __syncthreads();  // the ring slots just used may be refilled
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per pdf: moments from the fixed-point totals
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mt_final(MTArgs a) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= a.K) return;
+  const MTRec r = a.rec[k];
+  double E = __builtin_nan(""), V = __builtin_nan("");
+  if (r.flags == 0) {
+    const double A1 = (double)(long long)a.acc[2 * k] / r.sc1;
+    const double A2 = (double)(long long)a.acc[2 * k + 1] / r.sc2;
+    const double s1 = A1 / r.Z, s2 = A2 / r.Z;
+    E = r.shift + s1;
+    // a one-cell window is a point mass: variance 0 exactly
+    V = (r.lo[0] == r.hi[0] && r.lo[1] == r.hi[1]) ? 0.0 : s2 - s1 * s1;
+    if (!(r.Z > 0.0)) E = V = __builtin_nan("");
+  }
+  a.mean[k] = E;
+  a.var[k] = V;
+  if (a.delta2) {
+    double d2 = __builtin_nan("");
+    if ((r.flags & 3) == 0 && a.has_model) {
+      const double x[2] = {a.mu[2 * k], a.mu[2 * k + 1]};
+      const double fm = model_at(a.model.kind, 2, a.model.theta, x);
+      d2 = 0.5 * (V + (E - fm) * (E - fm));
+    }
+    a.delta2[k] = d2;
+  }
+}
+
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct MTLayout {
+  size_t rec, bbox, acc, tiles, bytes;
+};
+
+MTLayout mt_layout(int ntiles, long long K) {
+  MTLayout L;
+  L.rec = 0;
+  L.bbox = L.rec + al256((size_t)K * sizeof(MTRec));
+  L.acc = L.bbox + al256((size_t)K * 4);
+  L.tiles = L.acc + al256((size_t)K * 16);
+  L.bytes = L.tiles + al256((size_t)ntiles * sizeof(MTTile));
+  return L;
+}
+
+}  // namespace
+
+bool moments_tiled_applies(const vup_mm& mm, const vup_dists& d) {
+  if (mm.grid.ndim != 2 || d.ncomp != 1) return false;
+  const long long ntx = (mm.grid.n[1] + kMT - 1) / kMT, nty = (mm.grid.n[0] + kMT - 1) / kMT;
+  return ntx <= kMTMaxTiles && nty <= kMTMaxTiles && d.K < (1ll << 31);
+}
+
+size_t moments_tiled_ws_bytes(const vup_mm& mm, long long K) {
+  const int ntx = (mm.grid.n[1] + kMT - 1) / kMT, nty = (mm.grid.n[0] + kMT - 1) / kMT;
+  return mt_layout(ntx * nty, K).bytes;
+}
+
+hipError_t launch_moments_tiled(const vup_mm& mm, const vup_dists& d, const vup_model* model,
+                                void* ws, double* mean, double* var, double* delta2,
+                                hipStream_t s) {
+  if (d.K == 0) return hipSuccess;
+  MTArgs a{};
+  a.n0 = mm.grid.n[0];
+  a.n1 = mm.grid.n[1];
+  for (int i = 0; i < 2; ++i) {
+    a.lo[i] = mm.grid.lo[i];
+    a.hi[i] = mm.grid.hi[i];
+  }
+  a.rowstride = mm.pitch;
+  a.f32 = reinterpret_cast<const float*>(static_cast<const char*>(mm.ws) + mm.off_f32);
+  a.K = d.K;
+  a.ns = d.n_sigma;
+  a.mu = d.mu;
+  a.sigma = d.sigma;
+  a.ntx = (a.n1 + kMT - 1) / kMT;
+  a.nty = (a.n0 + kMT - 1) / kMT;
+  const int ntiles = a.ntx * a.nty;
+  // parts of the pdf list per tile: about 2048 workgroups, at least 256
+  // pdfs per part
+  long long parts = (2048 + ntiles - 1) / ntiles;
+  parts = parts < d.K / 256 ? parts : d.K / 256;
+  a.parts = (int)(parts < 1 ? 1 : (parts > 64 ? 64 : parts));
+  const MTLayout L = mt_layout(ntiles, d.K);
+  char* base = static_cast<char*>(ws);
+  a.rec = reinterpret_cast<MTRec*>(base + L.rec);
+  a.bbox = reinterpret_cast<uint32_t*>(base + L.bbox);
+  a.acc = reinterpret_cast<unsigned long long*>(base + L.acc);
+  a.tiles = reinterpret_cast<MTTile*>(base + L.tiles);
+  a.mean = mean;
+  a.var = var;
+  a.delta2 = delta2;
+  a.has_model = model != nullptr;
+  if (model) a.model = *model;
+  hipLaunchKernelGGL(k_mt_tiles, dim3(ntiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mt_prep, dim3((unsigned)((d.K + 3) / 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mt_main, dim3((unsigned)(ntiles * a.parts)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mt_final, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vup

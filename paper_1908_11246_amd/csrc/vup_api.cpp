@@ -271,6 +271,36 @@ int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, do
                   "vup_moments");
 }
 
+size_t vup_moments_tiled_workspace_bytes(const vup_mm* mm, const vup_dists* d) {
+  if (check_mm(mm) || check_dists(d, mm->grid.ndim)) return 0;
+  if (!vup::moments_tiled_applies(*mm, *d)) return 0;
+  return vup::moments_tiled_ws_bytes(*mm, d->K);
+}
+
+int vup_moments_tiled(const vup_mm* mm, const vup_dists* d, const vup_model* model, void* ws,
+                      size_t ws_bytes, double* mean, double* var, double* delta2, void* stream) {
+  int r = check_mm(mm);
+  if (r) return r;
+  if ((r = check_dists(d, mm->grid.ndim))) return r;
+  if (!vup::moments_tiled_applies(*mm, *d))
+    return vup_moments(mm, d, model, mean, var, delta2, stream);
+  if (d->K > 0 && (!mean || !var)) return fail(VUP_EINVAL, "mean or var is NULL");
+  if (delta2) {
+    if (!model) return fail(VUP_EINVAL, "delta2 needs the built-in model");
+    if ((r = check_model(model, mm->grid.ndim))) return r;
+  }
+  const size_t need = vup::moments_tiled_ws_bytes(*mm, d->K);
+  if (d->K > 0) {
+    if (!ws) return fail(VUP_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VUP_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < need) return fail(VUP_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  }
+  if ((r = check_device())) return r;
+  return launched(vup::launch_moments_tiled(*mm, *d, delta2 ? model : nullptr, ws, mean, var,
+                                            delta2, (hipStream_t)stream),
+                  "vup_moments_tiled");
+}
+
 int vup_ipsa(const vup_mm* mm, int64_t K, const float* P, double* mean_hist, double* var,
              double* entropy, void* stream) {
   int r = check_mm(mm);

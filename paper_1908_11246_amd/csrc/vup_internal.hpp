@@ -53,6 +53,13 @@ hipError_t launch_propagate(const vup_mm& mm, const vup_dists& d, int prec, floa
                             hipStream_t s);
 hipError_t launch_moments(const vup_mm& mm, const vup_dists& d, const vup_model* model,
                           double* mean, double* var, double* delta2, hipStream_t s);
+// moments by tiles of the model values on the matrix cores (2-D grids,
+// single-component pdfs, at most 256 tiles of 64 cells per axis)
+bool moments_tiled_applies(const vup_mm& mm, const vup_dists& d);
+size_t moments_tiled_ws_bytes(const vup_mm& mm, long long K);
+hipError_t launch_moments_tiled(const vup_mm& mm, const vup_dists& d, const vup_model* model,
+                                void* ws, double* mean, double* var, double* delta2,
+                                hipStream_t s);
 hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            const double* mean_hist, const double* g_var, const double* g_ent,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);

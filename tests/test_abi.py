@@ -164,6 +164,49 @@ def test_dists_validation(lib):
                                  dummy, dummy, None, None) == EINVAL
 
 
+def test_moments_tiled_arguments(lib):
+    """vup_moments_tiled: workspace size (72 + 4 + 16 bytes per pdf and 32 per
+    64 x 64 tile, each part rounded up to 256), workspace checks, and the
+    per-pdf kernel's rules where the tiled form does not apply."""
+    mm = _fake_mm(lib)
+    dummy = ctypes.c_void_p(0x1000)
+
+    def dists(**kw):
+        d = vup.VupDists()
+        d.K, d.ncomp, d.ndim, d.n_sigma = 4, 1, 2, 4.0
+        d.mu, d.sigma, d.weight = 0x1000, 0x2000, None
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+
+    d = dists()
+    ws_bytes = lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm), ctypes.byref(d))
+    assert ws_bytes == 512 + 256 + 256 + 256
+    big = vup.VupDists()
+    big.K, big.ncomp, big.ndim, big.n_sigma, big.mu, big.sigma = 1000, 1, 2, 4.0, 0x1000, 0x2000
+    assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm), ctypes.byref(big)) == (
+        72192 + 4096 + 16128 + 256)
+    ws = ctypes.c_void_p(0x200000)
+
+    def call(dd, ws_, nb, mean=dummy, var=dummy, d2=None, model=None):
+        return lib.vup_moments_tiled(ctypes.byref(mm), ctypes.byref(dd), model, ws_, nb, mean, var,
+                                     d2, None)
+
+    assert call(d, None, ws_bytes) == EWORKSPACE
+    assert call(d, ctypes.c_void_p(0x200010), ws_bytes) == EWORKSPACE
+    assert b"aligned" in lib.vup_last_error()
+    assert call(d, ws, ws_bytes - 1) == EWORKSPACE
+    assert call(d, ws, ws_bytes, mean=None) == EINVAL
+    assert call(d, ws, ws_bytes, d2=dummy) == EINVAL
+    m4 = vup.make_model("ring4")
+    assert call(d, ws, ws_bytes, d2=dummy, model=ctypes.byref(m4)) == EINVAL
+    # mixtures: not tiled (no workspace), vup_moments' rules apply
+    d2c = dists(ncomp=2, weight=0x3000)
+    assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm), ctypes.byref(d2c)) == 0
+    assert call(d2c, None, 0, d2=dummy) == EUNSUPPORTED
+    assert call(dists(K=-1), ws, ws_bytes) == EINVAL
+
+
 def test_grid_too_long_for_lds_is_unsupported(lib):
     # factor tables of every axis live in LDS; four 16384-cell axes do not fit
     mm = _fake_mm(lib, B=16, n=(60000, 30000))

@@ -39,15 +39,15 @@ def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     # counters are summed over the instances of one dispatch
     _counter_csv(fetch, "FETCH_SIZE", [(1, "vup::k_propagate_runs(vup::SweepArgs)", 1000.0),
                                        (1, "vup::k_propagate_runs(vup::SweepArgs)", 1000.0),
-                                       (2, "vup::k_moments(vup::SweepArgs)", 500.0),
+                                       (2, "vup::(anonymous namespace)::k_mt_main(vup::(anonymous namespace)::MTArgs)", 500.0),
                                        (3, "__amd_rocclr_copyBuffer", calib_kib / 2)])
     _counter_csv(write, "WRITE_SIZE", [(1, "vup::k_propagate_runs(vup::SweepArgs)", 300.0),
-                                       (2, "vup::k_moments(vup::SweepArgs)", 7.0),
+                                       (2, "vup::(anonymous namespace)::k_mt_main(vup::(anonymous namespace)::MTArgs)", 7.0),
                                        (3, "__amd_rocclr_copyBuffer", calib_kib)])
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "paper_1908_11246_amd" / "csrc")
-    for name in ("k_sweep.hip", "k_grid.hip", "vup_device.hpp", "vup_internal.hpp",
-                 "k_fields.hip", "vup_fields.hpp"):
+    for name in ("k_sweep.hip", "k_mtiles.hip", "k_grid.hip", "vup_device.hpp",
+                 "vup_internal.hpp", "k_fields.hip", "vup_fields.hpp"):
         (tmp_path / "paper_1908_11246_amd" / "csrc" / name).write_text("// " + name)
     bench.summarize_traffic(str(fetch), str(write))
     rec = json.loads((tmp_path / "profiles" / "traffic_grid1024.json").read_text())
@@ -60,5 +60,7 @@ def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     # a change of a kernel source voids the figures of the kernels built from it
     assert bench.traffic_bytes("propagate") is not None
     (tmp_path / "paper_1908_11246_amd" / "csrc" / "k_sweep.hip").write_text("// changed")
-    assert bench.traffic_bytes("moments") is None
+    assert bench.traffic_bytes("moments") is not None
     assert bench.traffic_bytes("propagate") is None
+    (tmp_path / "paper_1908_11246_amd" / "csrc" / "vup_internal.hpp").write_text("// changed")
+    assert bench.traffic_bytes("moments") is None

@@ -401,6 +401,120 @@ def test_grid48_4d_all_columns(vup, orc, precision):
 
 
 # ---------------------------------------------------------------------------
+# exact-f moments (eq. UP) on 2-D grids: the matrix-core tiles
+# (vup_moments_tiled) and the per-pdf kernel (vup_moments), each against the
+# oracle with the exact-f bars
+# ---------------------------------------------------------------------------
+# name, n, lo, hi, model, theta, K, sigma range, n_sigma: a grid inside one
+# ragged tile, tile edges at 64 and 128 cells with windows of 1 to ~400
+# cells, windows wider than the grid, and the n_sigma = 8 truncation
+TILED_CASES = [
+    ("one_tile", (40, 30), (-3.0, -3.0), (3.0, 3.0), "sincos2", (), 200, (0.01, 2.0), 4.0),
+    ("ragged", (200, 130), (-3.0, -2.0), (3.0, 2.5), "sincos2", (), 300, (0.005, 1.5), 4.0),
+    ("tile_edges", (65, 129), (-2.0, -2.0), (2.0, 2.0), "timing2", (), 300, (0.002, 0.4), 4.0),
+    ("wide", (96, 160), (-1.0, -1.0), (1.0, 1.0), "linear", (0.5, 1.0, -2.0), 150, (0.5, 5.0), 4.0),
+    ("ns8", (128, 192), (-5.0, -1.0), (5.0, 5.0), "ipsa2", (), 200, (0.02, 0.6), 8.0),
+]
+
+
+def _tiled_case(case):
+    name, n, lo, hi, model, theta, K, sr, ns = case
+    wl = workloads.random_workload(name, n, lo, hi, model, 16, K, 1, sr,
+                                   seed=zlib.crc32(name.encode()) % 100000, theta=theta)
+    wl.n_sigma = ns
+    return wl
+
+
+def _moments_vs_oracle(vup, orc, wl, tiled, f=None, label="", nan_expected=None):
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    if f is None:
+        f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta)
+    fin = f[np.isfinite(f)]
+    e = orc.uniform_edges(fin, wl.B)
+    mm = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(e).to(DEV))
+    mg, vg, _ = vup.moments(mm, wl.mu, wl.sigma, wl.weight, n_sigma=wl.n_sigma, tiled=tiled)
+    mo, vo, _ = orc.moments(wl.n, wl.lo, wl.hi, f, wl.mu, wl.sigma, wl.weight, wl.n_sigma)
+    mg, vg = _cpu(mg), _cpu(vg)
+    nan_o = np.isnan(mo) if nan_expected is None else (np.isnan(mo) | nan_expected)
+    assert np.array_equal(np.isnan(mg), nan_o) and np.array_equal(np.isnan(vg), nan_o)
+    ok = ~nan_o
+    _check_moments(mg[ok], vg[ok], mo[ok], vo[ok], fin.max() - fin.min(),
+                   f"exact-f {'tiled' if tiled else 'per-pdf'} {label}")
+    return mm, mg, vg
+
+
+@pytest.mark.parametrize("tiled", [True, False], ids=["tiled", "per_pdf"])
+@pytest.mark.parametrize("case", TILED_CASES, ids=[c[0] for c in TILED_CASES])
+def test_moments_2d_forms(vup, orc, case, tiled):
+    wl = _tiled_case(case)
+    _say(f"[moments {case[0]} {'tiled' if tiled else 'per-pdf'}] n={wl.n} K={wl.K}")
+    _moments_vs_oracle(vup, orc, wl, tiled)
+
+
+def test_moments_tiled_many_parts(vup, orc):
+    """Enough pdfs on a 2 x 2-tile grid that each tile's list is split in
+    parts (part boundaries, partial last batches)."""
+    wl = workloads.random_workload("parts", (128, 100), (-2.0, -2.0), (2.0, 2.0), "sincos2", 16,
+                                   6000, 1, (0.01, 0.6), seed=77)
+    _say(f"[moments parts] n={wl.n} K={wl.K}")
+    _moments_vs_oracle(vup, orc, wl, True)
+
+
+def test_moments_nonfinite_model_values(vup, orc):
+    """NaN model values in a 3 x 3 block (one of them at an anchor column of
+    the FP32 copy, column 64) and one cell: the tiled form gives NaN exactly
+    for the pdfs whose windows hold one (as the oracle's sums do); the per-pdf
+    kernel, which sums 8-column strips, for the windows whose rows hold one
+    and whose 8-aligned column span meets it. The other pdfs are unaffected."""
+    wl = _tiled_case(TILED_CASES[1])
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model, wl.theta).reshape(wl.n)
+    f[100:103, 64:67] = np.nan
+    f[7, 129] = np.nan
+    bad = np.isnan(f)
+    f = f.reshape(-1)
+    win = orc.windows(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, wl.n_sigma)[0][:, 0]
+    strip_nan = np.array([bad[w[0, 0]:w[0, 1] + 1, (w[1, 0] // 8) * 8:(w[1, 1] // 8) * 8 + 8].any()
+                          for w in win])
+    _, mt, _ = _moments_vs_oracle(vup, orc, wl, True, f=f, label="NaN cells")
+    _, mp, _ = _moments_vs_oracle(vup, orc, wl, False, f=f, label="NaN cells",
+                                  nan_expected=strip_nan)
+    _say(f"  NaN: tiled {np.isnan(mt).sum()}, per-pdf {np.isnan(mp).sum()} of {wl.K}")
+    assert 0 < np.isnan(mt).sum() < np.isnan(mp).sum() < wl.K
+
+
+def test_moments_tiled_grid1024_all(vup, orc):
+    """All 65 536 pdfs of grid1024 through both kernels against the oracle;
+    the tiled result is bit-identical over repeated calls (integer
+    accumulation), with a fresh and with a reused workspace."""
+    wl = workloads.grid1024()
+    _say(f"[moments grid1024 both forms] K={wl.K}")
+    mm, m1, v1 = _moments_vs_oracle(vup, orc, wl, True)
+    ws = vup.moments_workspace(mm, wl.mu, wl.sigma)
+    for _ in range(2):
+        m2, v2, _ = vup.moments(mm, wl.mu, wl.sigma, workspace=ws)
+        assert np.array_equal(_cpu(m2), m1) and np.array_equal(_cpu(v2), v1)
+    _, m3, v3 = _moments_vs_oracle(vup, orc, wl, False)
+    _say(f"  tiled vs per-pdf: max |dE| {np.abs(m1 - m3).max():.2e}, "
+         f"max |dVar|/Var {(np.abs(v1 - v3) / v3).max():.2e}")
+
+
+def test_moments_tiled_edge_cases(vup, orc):
+    """The edge-case pdfs of test_edge_cases through vup_moments_tiled: empty
+    and invalid windows NaN, a point mass with variance exactly 0, a window
+    over the whole grid, a clipped corner."""
+    n, lo, hi = (40, 30), (-3.0, -3.0), (3.0, 3.0)
+    h = (6.0 / 40, 6.0 / 30)
+    mu = np.array([[[0.3, -0.2]], [[9.0, 0.0]], [[0.0, 0.0]],
+                   [[lo[0] + 7.5 * h[0], lo[1] + 11.5 * h[1]]], [[0.0, 0.0]], [[-2.99, 2.99]]])
+    sigma = np.array([[[0.4, 0.3]], [[0.2, 0.2]], [[0.0, 0.5]], [[1e-6 * h[0], 1e-6 * h[1]]],
+                      [[1e6, 1e6]], [[0.5, 0.25]]])
+    wl = workloads.Workload("edge", 2, n, lo, hi, "sincos2", (), 12, mu, sigma, None)
+    _, mg, vg = _moments_vs_oracle(vup, orc, wl, True)
+    assert np.isnan(mg[[1, 2]]).all() and np.isnan(vg[[1, 2]]).all()
+    assert vg[3] == 0.0 and np.isfinite(mg[[0, 3, 4, 5]]).all()
+
+
+# ---------------------------------------------------------------------------
 # eq. (IPSAvar): the local expected squared deviation of vup_moments
 # ---------------------------------------------------------------------------
 def _check_delta2(vup, orc, wl):
