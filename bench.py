@@ -54,12 +54,17 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 #   the bin: 2 operations;
 #   exact-f moments on the matrix cores: per cell and distribution the two
 #   multiply-adds of the bilinear forms sum g (f - a) and sum g (f - a)^2
-#   (4 flops, FP64), the row factors and shifts being per row and per tile.
+#   (4 flops at FP64 quality; the kernel forms them exactly from 33-bit and
+#   27-bit fixed-point operands as 2 x 17 int8 digit products), the row
+#   factors and shifts being per row and per tile.
 OPS_PER_UPDATE = {"propagate": 2}
 MOMENTS_FLOPS_PER_UPDATE = 4
+MOMENTS_INT8_MACS_PER_UPDATE = 34
 MFMA_FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+MFMA_INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix peak
 KERNELS = {"propagate": "k_propagate_runs (run form) / k_propagate<FP32> (cell form)",
-           "moments": "k_mt_tiles + k_mt_prep + k_mt_main (v_mfma_f64_16x16x4_f64) + k_mt_final"}
+           "moments": "k_mt_tiles + k_mt_prep + k_mt_main (v_mfma_i32_16x16x64_i8 digit "
+                      "products) + k_mt_final"}
 
 
 def traffic_bytes(kernel):
@@ -701,15 +706,21 @@ def main():
                               "frac": ach / VALU_PEAK_OPS, "traffic": traffic_bytes("propagate"),
                               "kernel": KERNELS["propagate"], "kernel_ms": part_ms["propagate"],
                               "ops_per_update": OPS_PER_UPDATE["propagate"]}
-    # moments: the algorithmic FP64 matrix flops over the whole moments call
-    # (its four kernels), against the dense FP64 matrix peak
+    # moments: the algorithmic flops of the two FP64-quality bilinear forms
+    # over the whole moments call (its four kernels), against the dense FP64
+    # matrix peak; beside it the int8 digit products executed, against the
+    # dense int8 peak
     t = part_ms["moments"] * 1e-3
     ach = MOMENTS_FLOPS_PER_UPDATE * U / t / 1e12
+    ach8 = 2 * MOMENTS_INT8_MACS_PER_UPDATE * U / t / 1e12
     rooflines["moments"] = {"bound": "mfma", "achieved": ach, "peak": MFMA_FP64_PEAK_TFLOPS,
                             "unit": "TFLOP/s", "frac": ach / MFMA_FP64_PEAK_TFLOPS,
                             "traffic": traffic_bytes("moments"), "kernel": KERNELS["moments"],
                             "kernel_ms": part_ms["moments"],
-                            "flops_per_update": MOMENTS_FLOPS_PER_UPDATE}
+                            "flops_per_update": MOMENTS_FLOPS_PER_UPDATE,
+                            "int8_ops": {"achieved": ach8, "peak": MFMA_INT8_PEAK_TOPS,
+                                         "unit": "TOP/s", "frac": ach8 / MFMA_INT8_PEAK_TOPS,
+                                         "macs_per_update": MOMENTS_INT8_MACS_PER_UPDATE}}
     # the IPSA column statistics stream P once: HBM bound, K*B*4 bytes read
     # plus mean, variance and entropy (3*K*8 bytes) written
     ipsa_bytes = wl.K * wl.B * 4 + 3 * wl.K * 8

@@ -299,18 +299,21 @@ size_t vup_moments_tiled_workspace_bytes(const vup_mm* mm, const vup_dists* d);
 
 /* --------------------------------------------------------------------------
  * vup_moments_tiled - the outputs of vup_moments (same arguments, meaning and
- * NaN rules) by tiles of the model values on the FP32 matrix cores. For a
+ * NaN rules) by tiles of the model values on the int8 matrix cores. For a
  * separable pdf the moment sums over one 64 x 64 tile are bilinear forms in
  * the tile's model values, sum_ij gx(i) (f_ij - a)^q gy(j), q = 1, 2 (eq. UP
- * with the Gaussian of eq. gaussh, which factors over the axes): 64 pdfs
+ * with the Gaussian of eq. gaussh, which factors over the axes): 16 pdfs
  * whose windows meet a tile share its model values as one matrix operand.
- * Partial sums are FP32 over a tile (shifted by a per-tile anchor), FP64
- * across the shift, and the tiles' contributions are added per pdf as 64-bit
- * fixed-point integers, so results are bit-identical from run to run. The
- * per-axis factors are exp2(-(c t)^2) in FP32 (v_exp_f32) rather than the
- * FP64-argument factors of vup_moments: the two agree to a few 1e-7
- * relative. A window holding a non-finite model value gives NaN (mean and
- * variance).
+ * The tile's f - a and (f - a)^2 (a: the tile's mid-range value) are 33-bit
+ * fixed-point integers relative to the tile's range, the column factors
+ * 27-bit integers; their products are summed exactly as base-128 digit
+ * products in int32 (v_mfma_i32_16x16x64_i8), combined in FP64 with the row
+ * factors, and the tiles' contributions are added per pdf as 64-bit
+ * fixed-point integers: the sums carry no accumulation error and results are
+ * bit-identical from run to run. The per-axis factors are exp2(-(c t)^2) in
+ * FP32 (v_exp_f32) rather than the FP64-argument factors of vup_moments: the
+ * two agree to a few 1e-7 relative. A window holding a non-finite model value
+ * gives NaN (mean and variance).
  * Applies to 2-D grids with single-component pdfs (ncomp == 1), at most 256
  * tiles per axis and K < 2^31; other calls run vup_moments' kernel and
  * ignore ws.

@@ -1,23 +1,22 @@
 // Exact-f moments (eq. UP) of single-component pdfs on 2-D grids by tiles of
-// the model values on the FP32 matrix cores.
+// the model values on the int8 matrix cores.
 //
 // A separable density is gx(i) gy(j) on cell (i, j), so its moment sums over
 // one 64 x 64 tile T of the grid are bilinear forms in the model values:
 //   S1_T = sum_ij gx(i) (f_ij - a_T) gy(j),
 //   S2_T = sum_ij gx(i) (f_ij - a_T)^2 gy(j),
-// a_T an anchor of the tile (the midpoint of its model values). A workgroup
-// keeps the tile's F' = f - a_T and F'^2 in registers as MFMA A operands and
-// takes the pdfs whose windows meet the tile 64 at a time: their factor
-// tables Gy (64 columns x 64 pdfs) and Gx (64 rows x 64 pdfs) go to LDS,
-// Y = [F'; F'^2] Gy runs on v_mfma_f64_16x16x4_f64, and the row sums
-// sum_i gx(i) Y[i][n] finish S1_T and S2_T. The contraction is FP64 because
-// the variance is a difference: an error e in S2_T or S1_T moves Var Z by
-// about e + 2 (a_T - mean) e_1, and FP32 sums carry errors relative to
-// sum g F'^2 ~ Z (a_T - mean)^2, which exceeds Z Var by a factor of up to
-// (tile range / window spread)^2 (measured: 1e-5 relative variance error with
-// FP32 accumulation on a 64 x 64 grid). With s the pdf's shift (the model
-// value at its window's centre cell), delta = a_T - s and Z_T the tile's
-// factor sum,
+// a_T an anchor of the tile (the midpoint of its model values). The inner
+// sums over j are matrix products of the tile's values with the column
+// factors of the pdfs whose windows meet the tile; they are formed exactly
+// from fixed-point operands (see k_mt_main), so the only errors are those of
+// the operands' quantisation. Exactness matters because the variance is a
+// difference: an error e in S2_T or e_1 in S1_T moves Var Z by about
+// e + 2 (a_T - mean) e_1, and rounded sums (FP32 accumulation) carry errors
+// relative to sum g (f - a_T)^2 ~ Z (a_T - mean)^2, which exceeds Z Var by up
+// to (tile range / window spread)^2: FP32 accumulation measured variance
+// errors of up to 27 times the 1e-5 relative bar on a coarse grid. With s the
+// pdf's shift (the model value at its window's centre cell), delta = a_T - s
+// and Z_T the tile's factor sum,
 //   sum_T g (f - s)   = S1_T + delta Z_T,
 //   sum_T g (f - s)^2 = S2_T + 2 delta S1_T + delta^2 Z_T     (FP64),
 // and each tile's contribution is added to the pdf's totals as a 64-bit
@@ -106,6 +105,12 @@ __device__ __forceinline__ double mt_f(const MTArgs& a, int row, int col) {
 __device__ __forceinline__ float mt_factor(int j, float t0, float dt) {
   const float t = __builtin_fmaf((float)j, dt, t0);
   return __builtin_amdgcn_exp2f(-(t * t));
+}
+
+// column factors as integers of 27 bits, G = rint(g 2^27) (exact in FP32:
+// g <= 1 has 24 significant bits); the normaliser and the tiles use the same
+__device__ __forceinline__ int mt_quant(float g) {
+  return (int)__builtin_rintf(g * 134217728.0f);  // 2^27
 }
 
 __device__ __forceinline__ double wave_max_f64(double v) {
@@ -200,8 +205,8 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
     r.dt[1] = (float)(h1 * rs1 * kC);
     double zx = 0.0, zy = 0.0;
     for (int j = lane; j <= hi0 - lo0; j += 64) zx += (double)mt_factor(j, r.t0[0], r.dt[0]);
-    for (int j = lane; j <= hi1 - lo1; j += 64) zy += (double)mt_factor(j, r.t0[1], r.dt[1]);
-    r.Z = wave_sum(zx) * wave_sum(zy);
+    for (int j = lane; j <= hi1 - lo1; j += 64) zy += (double)mt_quant(mt_factor(j, r.t0[1], r.dt[1]));
+    r.Z = wave_sum(zx) * (wave_sum(zy) * 0x1p-27);
     double s = mt_f(a, lo0 + (hi0 - lo0 + 1) / 2, lo1 + (hi1 - lo1 + 1) / 2);
     if (!isfinite(s)) s = 0.0;  // the window holds a non-finite value: NaN result
     r.shift = s;
@@ -233,45 +238,106 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
 
 // ---------------------------------------------------------------------------
 // per (tile, part of the pdf list): the tile's sums of every pdf of the part
-// whose window meets it. The tile's F' = f - a_T (FP64) is staged in LDS
-// once; the workgroup scans the part for pdfs whose windows meet the tile,
-// 256 at a time into a ring, and each wave takes 16 of them at once over all
-// 64 rows: lane (li, lk) forms the column factors of pdf li for columns
-// 4s + lk (s < 16) in registers (the MFMA B operand) and, for the results it
-// holds, the row factors; the sums over rows and columns of the tile stay
-// inside the wave.
+// whose window meets it, by exact integer products on the int8 matrix cores.
+// The tile's F' = f - a_T and F'^2 are fixed-point integers of 33 bits
+// (scales 2^eF, 2^eS from the tile's range R = max |F'|) written as five
+// balanced base-128 digits in [-64, 63]; the column factors are integers
+// G = rint(g 2^27) written as four 7-bit digits in [0, 127]. A digit pair
+// (a, b) contributes 2^(7(a+b)) sum_j dF_a(j) dG_b(j); v_mfma_i32_16x16x64_i8
+// forms each such sum over the tile's 64 columns exactly (|terms| < 2^13,
+// 64 of them, at most four pairs per weight in one int32 accumulator: below
+// 2^21). The pairs of weight below 2^14 (a + b < 2) are left out: together
+// they are below 2^eF per row sum, under the quantisation of F' itself. The
+// six accumulators per row are combined in FP64 and weighted by the row
+// factors. So the sums are those of the quantised model values (within R
+// 2^-34 of f - a_T), of their squares (within R^2 2^-34) and of the factors
+// (within 2^-28), up to FP64 rounding, with no error from the order or length
+// of the accumulation (an FP32 accumulation would carry errors relative to
+// sum g F'^2, amplified in the variance by (a_T - mean)^2 / Var). F' and F'^2
+// are quantised separately, so sum g F'^2 is not exactly the sum of the
+// quantised F' squared: the difference, about 2 |F'| R 2^-34 per unit weight,
+// is what sets the 33 bits (26 left variance errors of R^2 2^-26 on windows
+// of one or two cells).
+// The tile's digits are staged in LDS once; the workgroup scans the part for
+// pdfs whose windows meet the tile, 256 at a time into a ring, and each wave
+// takes 16 of them at once over all 64 rows: lane (li, g) forms the column
+// factors of pdf li for columns 16g .. 16g + 15 in registers (the B operand)
+// and the row factors of the rows its results belong to; the sums over the
+// tile stay inside the wave.
 // ---------------------------------------------------------------------------
-constexpr int kFPitch = 66;  // LDS pitch (doubles) of F': 16 lanes of an FP64 read on distinct banks
+constexpr int kDPitch = 80;   // LDS bytes per tile row of one digit plane (conflict-free 16-byte reads)
+constexpr int kFBits = 33;    // fixed-point bits of F' and F'^2
+constexpr int kFDig = 5;      // their base-128 digits
+constexpr int kGBits = 27;    // fixed-point bits of the factors
 
-__global__ __launch_bounds__(256, 4) void k_mt_main(MTArgs a) {
-  __shared__ double Fs[kMT * kFPitch];  // F'[row][col]
+typedef int mt_i32x4 __attribute__((ext_vector_type(4)));
+
+// the five balanced base-128 digits of x (|x| <= 2^34), one byte each
+__device__ __forceinline__ unsigned long long digits5(long long x) {
+  unsigned long long out = 0;
+#pragma unroll
+  for (int d = 0; d < kFDig; ++d) {
+    const long long v = ((x + 64) & 127) - 64;
+    x = (x - v) >> 7;
+    out |= (unsigned long long)(v & 255) << (8 * d);
+  }
+  return out;
+}
+
+__global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t Dg[2 * kFDig][kMT * kDPitch];  // digit planes: F', then F'^2
   __shared__ int ring[kRing];
   __shared__ int wcnt[4];
   __shared__ unsigned long long nfmask[kMT];
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
+  const int li = lane & 15, lg = lane >> 4;
   const int part = blockIdx.x % a.parts, tile = blockIdx.x / a.parts;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const int r0 = ty * kMT, c0 = tx * kMT;
   const MTTile T = a.tiles[tile];
   const bool tbad = T.nonfinite != 0;  // uniform
+  // fixed-point scales: |F'| <= R (1 + 2^-30) < 2^(ilogb + 1)
+  const double R = 0.5 * (T.fmax - T.fmin) * (1.0 + 0x1p-30);
+  const int eF = R > 0.0 ? ilogb(R) + 1 - kFBits : 0;
+  const int eS = R > 0.0 ? ilogb(R * R) + 1 - kFBits : 0;
   if (threadIdx.x < kMT) nfmask[threadIdx.x] = 0ull;
   __syncthreads();
-  for (int e = threadIdx.x; e < kMT * kMT; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    const int row = r0 + i, col = c0 + j;
-    double v = 0.0;
-    if (row < a.n0 && col < a.n1) {
-      const double f = mt_f(a, row, col);
-      if (isfinite(f))
-        v = f - T.a;
-      else
-        atomicOr(&nfmask[i], 1ull << j);
+  // stage the digits: thread t writes 4 columns x 4 rows
+  {
+    const int cq = (threadIdx.x & 15) * 4;
+    for (int rr = threadIdx.x >> 4; rr < kMT; rr += 16) {
+      uint32_t pf[kFDig] = {}, ps[kFDig] = {};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = r0 + rr, col = c0 + cq + u;
+        long long fi = 0, si = 0;
+        if (row < a.n0 && col < a.n1) {
+          const double f = mt_f(a, row, col);
+          if (isfinite(f)) {
+            const double v = f - T.a;
+            fi = llrint(ldexp(v, -eF));
+            si = llrint(ldexp(v * v, -eS));
+          } else {
+            atomicOr(&nfmask[rr], 1ull << (cq + u));
+          }
+        }
+        const unsigned long long df = digits5(fi), ds = digits5(si);
+#pragma unroll
+        for (int d = 0; d < kFDig; ++d) {
+          pf[d] |= (uint32_t)((df >> (8 * d)) & 255u) << (8 * u);
+          ps[d] |= (uint32_t)((ds >> (8 * d)) & 255u) << (8 * u);
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < kFDig; ++d) {
+        *reinterpret_cast<uint32_t*>(&Dg[d][rr * kDPitch + cq]) = pf[d];
+        *reinterpret_cast<uint32_t*>(&Dg[kFDig + d][rr * kDPitch + cq]) = ps[d];
+      }
     }
-    Fs[i * kFPitch + j] = v;
   }
   const long long kbeg = a.K * part / a.parts, kend = a.K * (part + 1) / a.parts;
+  const double scF = ldexp(1.0, eF + 14 - kGBits), scS = ldexp(1.0, eS + 14 - kGBits);
 
   // 16 pdfs (ring positions pos .. pos + cnt - 1) on this wave
   auto wave_batch = [&](int pos, int cnt) {
@@ -291,47 +357,76 @@ __global__ __launch_bounds__(256, 4) void k_mt_main(MTArgs a) {
       t01 = r.t0[1];
       d1 = r.dt[1];
     }
-    // B operands: column factors of pdf li, columns 4s + lk; their sum in
-    // FP64 (exact for these FP32 values: the tile's factor sum enters as
-    // delta^2 Z_T, so an error in it would reach the variance amplified by
-    // (a_T - s)^2 / Var)
-    double gy[16];
+    // B operands: digits of the quantised column factors of pdf li, columns
+    // 16 lg + q (q < 16), one plane per digit; their sum (exact in FP64)
+    mt_i32x4 gb[4];
     double zy = 0.0;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int col = c0 + 4 * s + lk;
-      float v = 0.0f;
-      if (col >= l1 && col <= h1) v = mt_factor(col - l1, t01, d1);
-      gy[s] = (double)v;
-      zy += gy[s];
+    for (int qw = 0; qw < 4; ++qw) {
+      uint32_t pk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int col = c0 + 16 * lg + 4 * qw + u;
+        int G = 0;
+        if (col >= l1 && col <= h1) G = mt_quant(mt_factor(col - l1, t01, d1));
+        zy += (double)G;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) pk[d] |= (((uint32_t)G >> (7 * d)) & 127u) << (8 * u);
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) gb[d][qw] = (int)pk[d];
     }
     double s1 = 0.0, s2 = 0.0, sx = 0.0;
-    const double* fl = Fs + li * kFPitch + lk;
 #pragma unroll 1
     for (int ib = 0; ib < 4; ++ib) {
-      // Y = [F'; F'^2] Gy for rows 16 ib .. 16 ib + 15
-      mt_f64x4 y1 = {0.0, 0.0, 0.0, 0.0}, y2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const double av = fl[16 * ib * kFPitch + 4 * s];
-        y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, gy[s], y1, 0, 0, 0);
-        y2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av * av, gy[s], y2, 0, 0, 0);
-      }
-      // lane (li, lk) holds rows 16 ib + lk + 4r of pdf li (the FP64 MFMA's
-      // layout: A[i][k], B[k][j] from lane i + 16k, resp. j + 16k; D[q + 4r][j]
-      // in lane j + 16q, slot r); weight by the row factors
+      const int rowoff = (16 * ib + li) * kDPitch + 16 * lg;
+      // lane (li, lg) holds rows 16 ib + 4 lg + r of pdf li (D[4q + r][j] in
+      // lane j + 16q, slot r)
+      double gr[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 16 * ib + lk + 4 * r;
+        const int row = r0 + 16 * ib + 4 * lg + r;
         float gx = 0.0f;
         if (row >= l0 && row <= h0) gx = mt_factor(row - l0, t00, d0);
-        const double g = (double)gx;
-        s1 = __builtin_fma(g, y1[r], s1);
-        s2 = __builtin_fma(g, y2[r], s2);
-        sx += g;
+        gr[r] = (double)gx;
+        sx += gr[r];
+      }
+#pragma unroll
+      for (int kind = 0; kind < 2; ++kind) {
+        mt_i32x4 fa[kFDig];
+#pragma unroll
+        for (int d = 0; d < kFDig; ++d)
+          fa[d] = *reinterpret_cast<const mt_i32x4*>(&Dg[kind * kFDig + d][rowoff]);
+        // accumulators by weight 2^(7L), L = a + b = 2 .. 7
+        mt_i32x4 y[6];
+#pragma unroll
+        for (int L = 0; L < 6; ++L) y[L] = (mt_i32x4){0, 0, 0, 0};
+#pragma unroll
+        for (int da = 0; da < kFDig; ++da) {
+#pragma unroll
+          for (int db = 0; db < 4; ++db) {
+            if (da + db < 2) continue;
+            y[da + db - 2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[da], gb[db], y[da + db - 2], 0, 0, 0);
+          }
+        }
+        // sum_L 2^(7L) acc_L = 2^14 (acc2 + 2^7 u + 2^21 v + 2^35 acc7) with
+        // u = acc3 + 2^7 acc4, v = acc5 + 2^7 acc6 (below 2^29 in magnitude)
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int u = y[1][r] + y[2][r] * 128, v = y[3][r] + y[4][r] * 128;
+          const double Y = __builtin_fma(
+              (double)y[5][r], 34359738368.0,
+              __builtin_fma((double)v, 2097152.0, __builtin_fma((double)u, 128.0, (double)y[0][r])));
+          s = __builtin_fma(gr[r], Y, s);
+        }
+        if (kind == 0)
+          s1 += s;
+        else
+          s2 += s;
       }
     }
-    // sums over the four lane groups (rows by residue, columns by residue)
+    // sums over the four lane groups (rows by group, columns by group)
     s1 += __shfl_xor(s1, 16, 64);
     s2 += __shfl_xor(s2, 16, 64);
     sx += __shfl_xor(sx, 16, 64);
@@ -340,12 +435,13 @@ __global__ __launch_bounds__(256, 4) void k_mt_main(MTArgs a) {
     s2 += __shfl_xor(s2, 32, 64);
     sx += __shfl_xor(sx, 32, 64);
     zy += __shfl_xor(zy, 32, 64);
-    if (valid && lk == 0) {
+    if (valid && lg == 0) {
       const MTRec& r = a.rec[k];
-      const double Zt = sx * zy;
+      const double S1 = s1 * scF, S2 = s2 * scS;
+      const double Zt = sx * (zy * 0x1p-27);
       const double dl = T.a - r.shift;
-      const double A1 = s1 + dl * Zt;
-      const double A2 = s2 + 2.0 * dl * s1 + dl * dl * Zt;
+      const double A1 = S1 + dl * Zt;
+      const double A2 = S2 + 2.0 * dl * S1 + dl * dl * Zt;
       atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * r.sc1));
       atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * r.sc2));
       if (tbad) {
