@@ -107,10 +107,10 @@ __device__ __forceinline__ float mt_factor(int j, float t0, float dt) {
   return __builtin_amdgcn_exp2f(-(t * t));
 }
 
-// column factors as integers of 27 bits, G = rint(g 2^27) (exact in FP32:
-// g <= 1 has 24 significant bits); the normaliser and the tiles use the same
+// column factors as integers of 30 bits, G = rint(g 2^30) (g <= 1); the
+// normaliser and the tiles use the same
 __device__ __forceinline__ int mt_quant(float g) {
-  return (int)__builtin_rintf(g * 134217728.0f);  // 2^27
+  return (int)__builtin_rintf(g * 1073741824.0f);  // 2^30
 }
 
 __device__ __forceinline__ double wave_max_f64(double v) {
@@ -173,13 +173,24 @@ __global__ __launch_bounds__(256) void k_mt_tiles(MTArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// per pdf (one wave each): window, factor constants, normaliser, shift,
+// per pdf (16 lanes each): window, factor constants, normaliser, shift,
 // fixed-point scales; clears the totals
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+__device__ __forceinline__ double max16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 16));
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
-  const int lane = threadIdx.x & 63;
-  const long long k = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= a.K) return;
+  const int l16 = threadIdx.x & 15;
+  const long long k = (long long)blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (k >= a.K) return;  // the 16 lanes of a pdf leave together
   MTRec r;
   r.pad = 0;
   r.shift = r.Z = 0.0;
@@ -204,9 +215,9 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
     r.dt[0] = (float)(h0 * rs0 * kC);
     r.dt[1] = (float)(h1 * rs1 * kC);
     double zx = 0.0, zy = 0.0;
-    for (int j = lane; j <= hi0 - lo0; j += 64) zx += (double)mt_factor(j, r.t0[0], r.dt[0]);
-    for (int j = lane; j <= hi1 - lo1; j += 64) zy += (double)mt_quant(mt_factor(j, r.t0[1], r.dt[1]));
-    r.Z = wave_sum(zx) * (wave_sum(zy) * 0x1p-27);
+    for (int j = l16; j <= hi0 - lo0; j += 16) zx += (double)mt_factor(j, r.t0[0], r.dt[0]);
+    for (int j = l16; j <= hi1 - lo1; j += 16) zy += (double)mt_quant(mt_factor(j, r.t0[1], r.dt[1]));
+    r.Z = sum16(zx) * (sum16(zy) * 0x1p-30);
     double s = mt_f(a, lo0 + (hi0 - lo0 + 1) / 2, lo1 + (hi1 - lo1 + 1) / 2);
     if (!isfinite(s)) s = 0.0;  // the window holds a non-finite value: NaN result
     r.shift = s;
@@ -214,11 +225,11 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
     const int tx0 = lo1 / kMT, tx1 = hi1 / kMT, ty0 = lo0 / kMT, ty1 = hi0 / kMT;
     const int ntw = tx1 - tx0 + 1, nt = ntw * (ty1 - ty0 + 1);
     double R = 0.0;
-    for (int t = lane; t < nt; t += 64) {
+    for (int t = l16; t < nt; t += 16) {
       const MTTile T = a.tiles[(long long)(ty0 + t / ntw) * a.ntx + tx0 + t % ntw];
       if (T.nfinite) R = fmax(R, fmax(T.fmax - s, s - T.fmin));
     }
-    R = wave_max_f64(R);
+    R = max16(R);
     if (r.Z > 0.0 && R > 0.0 && isfinite(R)) {
       // Z < 2^(ez+1), R < 2^(er+1): |sum g (f-s)| < 2^(ez+er+2) and
       // sum g (f-s)^2 < 2^(ez+2er+3); the scales bring both below 2^60
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
     }
     bb = (uint32_t)tx0 | ((uint32_t)tx1 << 8) | ((uint32_t)ty0 << 16) | ((uint32_t)ty1 << 24);
   }
-  if (lane == 0) {
+  if (l16 == 0) {
     a.rec[k] = r;
     a.bbox[k] = bb;
     a.acc[2 * k] = 0ull;
@@ -239,25 +250,26 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
 // ---------------------------------------------------------------------------
 // per (tile, part of the pdf list): the tile's sums of every pdf of the part
 // whose window meets it, by exact integer products on the int8 matrix cores.
-// The tile's F' = f - a_T and F'^2 are fixed-point integers of 33 bits
-// (scales 2^eF, 2^eS from the tile's range R = max |F'|) written as five
-// balanced base-128 digits in [-64, 63]; the column factors are integers
-// G = rint(g 2^27) written as four 7-bit digits in [0, 127]. A digit pair
-// (a, b) contributes 2^(7(a+b)) sum_j dF_a(j) dG_b(j); v_mfma_i32_16x16x64_i8
-// forms each such sum over the tile's 64 columns exactly (|terms| < 2^13,
-// 64 of them, at most four pairs per weight in one int32 accumulator: below
-// 2^21). The pairs of weight below 2^14 (a + b < 2) are left out: together
-// they are below 2^eF per row sum, under the quantisation of F' itself. The
-// six accumulators per row are combined in FP64 and weighted by the row
-// factors. So the sums are those of the quantised model values (within R
-// 2^-34 of f - a_T), of their squares (within R^2 2^-34) and of the factors
-// (within 2^-28), up to FP64 rounding, with no error from the order or length
-// of the accumulation (an FP32 accumulation would carry errors relative to
-// sum g F'^2, amplified in the variance by (a_T - mean)^2 / Var). F' and F'^2
-// are quantised separately, so sum g F'^2 is not exactly the sum of the
-// quantised F' squared: the difference, about 2 |F'| R 2^-34 per unit weight,
-// is what sets the 33 bits (26 left variance errors of R^2 2^-26 on windows
-// of one or two cells).
+// The tile's F' = f - a_T and F'^2 are fixed-point integers of 30 bits
+// (scales 2^eF, 2^eS from the tile's range R = max |F'|), the column factors
+// integers G = rint(g 2^30); each is written as four balanced base-256
+// digits in [-128, 127] (the bytes of (x + 0x80808080) xor 0x80808080). A
+// digit pair (a, b) contributes 2^(8(a+b)) sum_j dF_a(j) dG_b(j);
+// v_mfma_i32_16x16x64_i8 forms each such sum over the tile's 64 columns
+// exactly (|terms| <= 2^14, 64 of them, at most four pairs per weight in one
+// int32 accumulator: at most 2^22). The pairs of weight below 2^16 (a + b < 2)
+// are left out: together below 2^(eF - 1) per row sum, under the
+// quantisation of F' itself. The five accumulators per row are combined in
+// FP64 and weighted by the row factors. So the sums are those of the
+// quantised model values (within R 2^-31 of f - a_T), of their squares
+// (within R^2 2^-31) and of the factors (within 2^-31), up to FP64 rounding,
+// with no error from the order or length of the accumulation (an FP32
+// accumulation would carry errors relative to sum g F'^2, amplified in the
+// variance by (a_T - mean)^2 / Var). F' and F'^2 are quantised separately,
+// so sum g F'^2 is not exactly the sum of the quantised F' squared: the
+// difference, at most about 2 |F'| R 2^-31 <= R^2 2^-30 per unit weight,
+// sets the 30 bits (26 left variance errors of R^2 2^-26, above the
+// 1e-9 range^2 floor of the parity bar, on windows of one or two cells).
 // The tile's digits are staged in LDS once; the workgroup scans the part for
 // pdfs whose windows meet the tile, 256 at a time into a ring, and each wave
 // takes 16 of them at once over all 64 rows: lane (li, g) forms the column
@@ -266,26 +278,32 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
 // tile stay inside the wave.
 // ---------------------------------------------------------------------------
 constexpr int kDPitch = 80;   // LDS bytes per tile row of one digit plane (conflict-free 16-byte reads)
-constexpr int kFBits = 33;    // fixed-point bits of F' and F'^2
-constexpr int kFDig = 5;      // their base-128 digits
-constexpr int kGBits = 27;    // fixed-point bits of the factors
+constexpr int kFBits = 30;    // fixed-point bits of F', F'^2 and the factors
+constexpr int kDig = 4;       // their base-256 digits
 
 typedef int mt_i32x4 __attribute__((ext_vector_type(4)));
 
-// the five balanced base-128 digits of x (|x| <= 2^34), one byte each
-__device__ __forceinline__ unsigned long long digits5(long long x) {
-  unsigned long long out = 0;
-#pragma unroll
-  for (int d = 0; d < kFDig; ++d) {
-    const long long v = ((x + 64) & 127) - 64;
-    x = (x - v) >> 7;
-    out |= (unsigned long long)(v & 255) << (8 * d);
-  }
-  return out;
+// the four balanced base-256 digits of x (|x| < 0x7F7F7F7F), as the bytes of
+// one word: x + sum 128 256^b has the digits plus 128 as its bytes
+__device__ __forceinline__ uint32_t digits4(int x) {
+  return ((uint32_t)x + 0x80808080u) ^ 0x80808080u;
+}
+
+// byte b of words w0..w3 -> word b (a 4 x 4 byte transpose, v_perm_b32)
+__device__ __forceinline__ void transpose4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                           uint32_t (&o)[4]) {
+  const uint32_t a_lo = __builtin_amdgcn_perm(w1, w0, 0x05010400u);  // w0.0 w1.0 w0.1 w1.1
+  const uint32_t a_hi = __builtin_amdgcn_perm(w1, w0, 0x07030602u);  // w0.2 w1.2 w0.3 w1.3
+  const uint32_t b_lo = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const uint32_t b_hi = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  o[0] = __builtin_amdgcn_perm(b_lo, a_lo, 0x05040100u);
+  o[1] = __builtin_amdgcn_perm(b_lo, a_lo, 0x07060302u);
+  o[2] = __builtin_amdgcn_perm(b_hi, a_hi, 0x05040100u);
+  o[3] = __builtin_amdgcn_perm(b_hi, a_hi, 0x07060302u);
 }
 
 __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t Dg[2 * kFDig][kMT * kDPitch];  // digit planes: F', then F'^2
+  __shared__ __attribute__((aligned(16))) uint8_t Dg[2 * kDig][kMT * kDPitch];  // digit planes: F', then F'^2
   __shared__ int ring[kRing];
   __shared__ int wcnt[4];
   __shared__ unsigned long long nfmask[kMT];
@@ -307,74 +325,90 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
   {
     const int cq = (threadIdx.x & 15) * 4;
     for (int rr = threadIdx.x >> 4; rr < kMT; rr += 16) {
-      uint32_t pf[kFDig] = {}, ps[kFDig] = {};
+      uint32_t hf[4], hs[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int row = r0 + rr, col = c0 + cq + u;
-        long long fi = 0, si = 0;
+        int fi = 0, si = 0;
         if (row < a.n0 && col < a.n1) {
           const double f = mt_f(a, row, col);
           if (isfinite(f)) {
             const double v = f - T.a;
-            fi = llrint(ldexp(v, -eF));
-            si = llrint(ldexp(v * v, -eS));
+            fi = (int)rint(ldexp(v, -eF));
+            si = (int)rint(ldexp(v * v, -eS));
           } else {
             atomicOr(&nfmask[rr], 1ull << (cq + u));
           }
         }
-        const unsigned long long df = digits5(fi), ds = digits5(si);
-#pragma unroll
-        for (int d = 0; d < kFDig; ++d) {
-          pf[d] |= (uint32_t)((df >> (8 * d)) & 255u) << (8 * u);
-          ps[d] |= (uint32_t)((ds >> (8 * d)) & 255u) << (8 * u);
-        }
+        hf[u] = digits4(fi);
+        hs[u] = digits4(si);
       }
+      uint32_t pf[4], ps[4];
+      transpose4(hf[0], hf[1], hf[2], hf[3], pf);
+      transpose4(hs[0], hs[1], hs[2], hs[3], ps);
 #pragma unroll
-      for (int d = 0; d < kFDig; ++d) {
+      for (int d = 0; d < kDig; ++d) {
         *reinterpret_cast<uint32_t*>(&Dg[d][rr * kDPitch + cq]) = pf[d];
-        *reinterpret_cast<uint32_t*>(&Dg[kFDig + d][rr * kDPitch + cq]) = ps[d];
+        *reinterpret_cast<uint32_t*>(&Dg[kDig + d][rr * kDPitch + cq]) = ps[d];
       }
     }
   }
   const long long kbeg = a.K * part / a.parts, kend = a.K * (part + 1) / a.parts;
-  const double scF = ldexp(1.0, eF + 14 - kGBits), scS = ldexp(1.0, eS + 14 - kGBits);
+  const double scF = ldexp(1.0, eF + 16 - kFBits), scS = ldexp(1.0, eS + 16 - kFBits);
 
-  // 16 pdfs (ring positions pos .. pos + cnt - 1) on this wave
-  auto wave_batch = [&](int pos, int cnt) {
-    const bool valid = li < cnt;
-    long long k = 0;
-    int l0 = 1, h0 = 0, l1 = 1, h1 = 0;
-    float t00 = 0.0f, d0 = 0.0f, t01 = 0.0f, d1 = 0.0f;
-    if (valid) {
-      k = kbeg + ring[(pos + li) & (kRing - 1)];
-      const MTRec& r = a.rec[k];
-      l0 = r.lo[0];
-      h0 = r.hi[0];
-      l1 = r.lo[1];
-      h1 = r.hi[1];
-      t00 = r.t0[0];
-      d0 = r.dt[0];
-      t01 = r.t0[1];
-      d1 = r.dt[1];
+  // the record of pdf li of a batch of 16 (ring positions pos .. pos + cnt -
+  // 1); an empty window for li >= cnt
+  struct Params {
+    long long k;
+    int l0, h0, l1, h1;
+    float t00, d0, t01, d1;
+    double sh, c1, c2;
+  };
+  auto load_params = [&](int pos, int cnt) {
+    Params p = {0, 1, 0, 1, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0.0, 0.0};
+    if (li < cnt) {
+      p.k = kbeg + ring[(pos + li) & (kRing - 1)];
+      const MTRec& r = a.rec[p.k];
+      p.l0 = r.lo[0];
+      p.h0 = r.hi[0];
+      p.l1 = r.lo[1];
+      p.h1 = r.hi[1];
+      p.t00 = r.t0[0];
+      p.d0 = r.dt[0];
+      p.t01 = r.t0[1];
+      p.d1 = r.dt[1];
+      p.sh = r.shift;
+      p.c1 = r.sc1;
+      p.c2 = r.sc2;
     }
+    return p;
+  };
+
+  // 16 pdfs on this wave, their records in P
+  auto wave_batch = [&](const Params& P, int cnt) {
+    const bool valid = li < cnt;
+    const long long k = P.k;
+    const int l0 = P.l0, h0 = P.h0, l1 = P.l1, h1 = P.h1;
+    const float t00 = P.t00, d0 = P.d0, t01 = P.t01, d1 = P.d1;
     // B operands: digits of the quantised column factors of pdf li, columns
     // 16 lg + q (q < 16), one plane per digit; their sum (exact in FP64)
-    mt_i32x4 gb[4];
+    mt_i32x4 gb[kDig];
     double zy = 0.0;
 #pragma unroll
     for (int qw = 0; qw < 4; ++qw) {
-      uint32_t pk[4] = {0u, 0u, 0u, 0u};
+      uint32_t h[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int col = c0 + 16 * lg + 4 * qw + u;
         int G = 0;
         if (col >= l1 && col <= h1) G = mt_quant(mt_factor(col - l1, t01, d1));
         zy += (double)G;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) pk[d] |= (((uint32_t)G >> (7 * d)) & 127u) << (8 * u);
+        h[u] = digits4(G);
       }
+      uint32_t pk[4];
+      transpose4(h[0], h[1], h[2], h[3], pk);
 #pragma unroll
-      for (int d = 0; d < 4; ++d) gb[d][qw] = (int)pk[d];
+      for (int d = 0; d < kDig; ++d) gb[d][qw] = (int)pk[d];
     }
     double s1 = 0.0, s2 = 0.0, sx = 0.0;
 #pragma unroll 1
@@ -393,31 +427,30 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       }
 #pragma unroll
       for (int kind = 0; kind < 2; ++kind) {
-        mt_i32x4 fa[kFDig];
+        mt_i32x4 fa[kDig];
 #pragma unroll
-        for (int d = 0; d < kFDig; ++d)
-          fa[d] = *reinterpret_cast<const mt_i32x4*>(&Dg[kind * kFDig + d][rowoff]);
-        // accumulators by weight 2^(7L), L = a + b = 2 .. 7
-        mt_i32x4 y[6];
+        for (int d = 0; d < kDig; ++d)
+          fa[d] = *reinterpret_cast<const mt_i32x4*>(&Dg[kind * kDig + d][rowoff]);
+        // accumulators by weight 2^(8L), L = a + b = 2 .. 6
+        mt_i32x4 y[5];
 #pragma unroll
-        for (int L = 0; L < 6; ++L) y[L] = (mt_i32x4){0, 0, 0, 0};
+        for (int L = 0; L < 5; ++L) y[L] = (mt_i32x4){0, 0, 0, 0};
 #pragma unroll
-        for (int da = 0; da < kFDig; ++da) {
+        for (int da = 0; da < kDig; ++da) {
 #pragma unroll
-          for (int db = 0; db < 4; ++db) {
+          for (int db = 0; db < kDig; ++db) {
             if (da + db < 2) continue;
             y[da + db - 2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[da], gb[db], y[da + db - 2], 0, 0, 0);
           }
         }
-        // sum_L 2^(7L) acc_L = 2^14 (acc2 + 2^7 u + 2^21 v + 2^35 acc7) with
-        // u = acc3 + 2^7 acc4, v = acc5 + 2^7 acc6 (below 2^29 in magnitude)
+        // sum_L 2^(8L) acc_L = 2^16 (acc2 + 2^8 u + 2^24 v) with
+        // u = acc3 + 2^8 acc4, v = acc5 + 2^8 acc6 (below 2^31 in magnitude)
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int u = y[1][r] + y[2][r] * 128, v = y[3][r] + y[4][r] * 128;
-          const double Y = __builtin_fma(
-              (double)y[5][r], 34359738368.0,
-              __builtin_fma((double)v, 2097152.0, __builtin_fma((double)u, 128.0, (double)y[0][r])));
+          const int u = y[1][r] + y[2][r] * 256, v = y[3][r] + y[4][r] * 256;
+          const double Y = __builtin_fma((double)v, 16777216.0,
+                                         __builtin_fma((double)u, 256.0, (double)y[0][r]));
           s = __builtin_fma(gr[r], Y, s);
         }
         if (kind == 0)
@@ -436,14 +469,13 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
     sx += __shfl_xor(sx, 32, 64);
     zy += __shfl_xor(zy, 32, 64);
     if (valid && lg == 0) {
-      const MTRec& r = a.rec[k];
       const double S1 = s1 * scF, S2 = s2 * scS;
-      const double Zt = sx * (zy * 0x1p-27);
-      const double dl = T.a - r.shift;
+      const double Zt = sx * (zy * 0x1p-30);
+      const double dl = T.a - P.sh;
       const double A1 = S1 + dl * Zt;
       const double A2 = S2 + 2.0 * dl * S1 + dl * dl * Zt;
-      atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * r.sc1));
-      atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * r.sc2));
+      atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * P.c1));
+      atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * P.c2));
       if (tbad) {
         // does the window's part of the tile hold a non-finite value?
         const int ra = max(l0, r0) - r0, rb = min(h0, r0 + kMT - 1) - r0;
@@ -459,16 +491,16 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
 
   int head = 0, tail = 0;  // uniform
   long long k0 = kbeg;
+  // tile ranges of the next scan step, loaded one step ahead
+  uint32_t bb_next = (k0 + threadIdx.x < kend) ? a.bbox[k0 + threadIdx.x] : 1u;
   for (;;) {
     // fill the ring up to 256 pending pdfs (or the end of the part)
     while (tail - head < 256 && k0 < kend) {
       const long long k = k0 + threadIdx.x;
-      bool hit = false;
-      if (k < kend) {
-        const uint32_t bb = a.bbox[k];
-        hit = tx >= (int)(bb & 255u) && tx <= (int)((bb >> 8) & 255u) &&
-              ty >= (int)((bb >> 16) & 255u) && ty <= (int)(bb >> 24);
-      }
+      const uint32_t bb = bb_next;
+      bb_next = (k + 256 < kend) ? a.bbox[k + 256] : 1u;
+      const bool hit = k < kend && tx >= (int)(bb & 255u) && tx <= (int)((bb >> 8) & 255u) &&
+                       ty >= (int)((bb >> 16) & 255u) && ty <= (int)(bb >> 24);
       const unsigned long long m = __ballot(hit);
       __syncthreads();  // earlier readers of wcnt are done
       if (lane == 0) wcnt[w] = __popcll(m);
@@ -483,8 +515,18 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
     const int avail = min(tail - head, 256);
     if (avail == 0) break;
     __syncthreads();  // ring entries and the staged tile are visible
-    // wave w: pending pdfs 64w .. 64w + 63, 16 at a time
-    for (int b = 64 * w; b < min(64 * w + 64, avail); b += 16) wave_batch(head + b, min(16, avail - b));
+    // wave w: pending pdfs 64w .. 64w + 63, 16 at a time, the next batch's
+    // records loaded while the current one runs
+    const int bend = min(64 * w + 64, avail);
+    if (64 * w < bend) {
+      Params cur = load_params(head + 64 * w, min(16, avail - 64 * w));
+      for (int b = 64 * w; b < bend; b += 16) {
+        const Params nxt = b + 16 < bend ? load_params(head + b + 16, min(16, avail - b - 16))
+                                         : load_params(0, 0);
+        wave_batch(cur, min(16, avail - b));
+        cur = nxt;
+      }
+    }
     head += avail;
     __syncthreads();  // the ring slots just used may be refilled
   }
@@ -586,7 +628,7 @@ hipError_t launch_moments_tiled(const vup_mm& mm, const vup_dists& d, const vup_
   a.has_model = model != nullptr;
   if (model) a.model = *model;
   hipLaunchKernelGGL(k_mt_tiles, dim3(ntiles), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_mt_prep, dim3((unsigned)((d.K + 3) / 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mt_prep, dim3((unsigned)((d.K + 15) / 16)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_mt_main, dim3((unsigned)(ntiles * a.parts)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_mt_final, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
