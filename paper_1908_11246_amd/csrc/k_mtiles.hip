@@ -315,8 +315,10 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
   const int r0 = ty * kMT, c0 = tx * kMT;
   const MTTile T = a.tiles[tile];
   const bool tbad = T.nonfinite != 0;  // uniform
-  // fixed-point scales: |F'| <= R (1 + 2^-30) < 2^(ilogb + 1)
-  const double R = 0.5 * (T.fmax - T.fmin) * (1.0 + 0x1p-30);
+  // fixed-point scales: rounding is monotonic, so every F' = f - a_T of the
+  // tile (the same FP64 subtraction) is within R = max(fmax - a_T, a_T - fmin)
+  // and F'^2 within R^2, both below 2^(ilogb + 1): |integers| <= 2^30
+  const double R = fmax(T.fmax - T.a, T.a - T.fmin);
   const int eF = R > 0.0 ? ilogb(R) + 1 - kFBits : 0;
   const int eS = R > 0.0 ? ilogb(R * R) + 1 - kFBits : 0;
   if (threadIdx.x < kMT) nfmask[threadIdx.x] = 0ull;
