@@ -562,7 +562,7 @@ def summarize_pmc(out_path, updates, csv_paths):
         if not name.startswith(("vup::", "void vup::")) or c.get("SQ_WAVES", 1.0) < 256:
             continue
         short = name[5:] if name.startswith("void ") else name
-        short = short.split("(")[0]
+        short = short.replace("(anonymous namespace)::", "").split("(")[0]
         cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD or None
         get = c.get
         valu_issue = get("SQ_INSTS_VALU") / (N_CU * cyc) if cyc and "SQ_INSTS_VALU" in c else None
