@@ -291,7 +291,7 @@ int vup_moments(const vup_mm* mm, const vup_dists* d, const vup_model* model, do
 
 /* --------------------------------------------------------------------------
  * vup_moments_tiled_workspace_bytes - device workspace of vup_moments_tiled
- * for K pdfs: 72 + 4 + 16 bytes per pdf and 32 per tile of 64 x 64 cells
+ * for K pdfs: 80 + 8 + 16 bytes per pdf and 32 per tile of 64 x 64 cells
  * (each part rounded up to 256 bytes). 0 when the tiled form does not apply
  * (see below); then vup_moments_tiled needs no workspace.
  * ------------------------------------------------------------------------ */
@@ -314,9 +314,9 @@ size_t vup_moments_tiled_workspace_bytes(const vup_mm* mm, const vup_dists* d);
  * FP32 (v_exp_f32) rather than the FP64-argument factors of vup_moments: the
  * two agree to a few 1e-7 relative. A window holding a non-finite model value
  * gives NaN (mean and variance).
- * Applies to 2-D grids with single-component pdfs (ncomp == 1), at most 256
- * tiles per axis and K < 2^31; other calls run vup_moments' kernel and
- * ignore ws.
+ * Applies to 2-D grids with single-component pdfs (ncomp == 1), at most
+ * 65 535 tiles of 64 cells per axis and 2^20 tiles in all, and K < 2^26;
+ * other calls run vup_moments' kernel and ignore ws.
  *   ws: dev, 256-byte aligned, ws_bytes >= vup_moments_tiled_workspace_bytes
  *   (may be NULL when that is 0). EWORKSPACE: workspace too small.
  * ------------------------------------------------------------------------ */

@@ -27,9 +27,13 @@
 // The factors are exp(-t^2/2) = exp2(-(c t)^2), c = sqrt(log2(e)/2), with
 // c t = c (x_lo - mu)/sigma + j c h/sigma for the j-th cell of the window: two
 // FP32 constants per axis and pdf (rounded from FP64 once), one FMA, one
-// multiply and v_exp_f32 per factor, the same instructions wherever a factor
-// is formed, so the normaliser Z (the FP64 sum of the factors) and the tiles
-// use identical values.
+// multiply-add and v_exp_f32 per factor, the same instructions wherever a
+// factor is formed, so the normaliser Z (the FP64 sum of the factors) and the
+// tiles use identical values. Each axis's factors are divided by that axis's
+// largest one, exp2(-(c t*)^2) at the cell t* nearest the mean (the moments
+// do not change when an axis's factors are scaled alike): the largest factor
+// is 1, so a window far from its mean (a one-cell window of a narrow pdf)
+// neither underflows FP32 nor falls below the factors' fixed-point quantum.
 
 #include <math.h>
 
@@ -43,13 +47,14 @@ namespace {
 typedef double mt_f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMT = 64;               // tile edge in cells
-constexpr int kMTMaxTiles = 256;      // tiles per axis (8-bit tile indices)
-constexpr int kRing = 512;            // candidate ring: < 64 pending + 256 per scan step
+constexpr int kMTMaxTiles = 65535;    // tiles per axis (16-bit tile indices)
+constexpr int kRing = 512;            // candidate ring: < 256 pending + one scan step of 256
 constexpr double kC = 0.8493218002880191;  // sqrt(log2(e) / 2)
 
 struct MTRec {
   float t0[2];    // c (x_lo - mu) / sigma per axis, x_lo the window's first cell
   float dt[2];    // c h / sigma per axis
+  float tm2[2];   // (c t*)^2 per axis, t* the window's cell nearest the mean
   int lo[2];      // window (hi < lo: empty)
   int hi[2];
   double shift;   // model value at the window's centre cell
@@ -59,7 +64,7 @@ struct MTRec {
   int flags;      // 1 bad parameters, 2 empty window, 4 non-finite f in the window
   int pad;
 };
-static_assert(sizeof(MTRec) == 72, "record layout");
+static_assert(sizeof(MTRec) == 80, "record layout");
 
 struct MTTile {
   double a;       // anchor: midpoint of the tile's finite model values
@@ -80,7 +85,7 @@ struct MTArgs {
   const double* __restrict__ sigma;
   int ntx, nty, parts;
   MTRec* rec;
-  uint32_t* bbox;       // tile range of each window: tx_lo, tx_hi, ty_lo, ty_hi (8 bits each)
+  unsigned long long* bbox;  // tile range of each window: tx_lo, tx_hi, ty_lo, ty_hi (16 bits each)
   unsigned long long* acc;  // [K][2] fixed-point totals
   MTTile* tiles;
   double* mean;
@@ -101,10 +106,20 @@ __device__ __forceinline__ double mt_f(const MTArgs& a, int row, int col) {
   return isfinite(f0) ? f0 + (double)p[col] : (double)p[col];
 }
 
-// Gaussian factor of the j-th cell of a window (see the header comment)
-__device__ __forceinline__ float mt_factor(int j, float t0, float dt) {
+// Gaussian factor of the j-th cell of a window, relative to the axis's
+// largest (see the header comment)
+__device__ __forceinline__ float mt_factor(int j, float t0, float dt, float tm2) {
   const float t = __builtin_fmaf((float)j, dt, t0);
-  return __builtin_amdgcn_exp2f(-(t * t));
+  return __builtin_amdgcn_exp2f(-__builtin_fmaf(t, t, -tm2));
+}
+
+// (c t*)^2 for the cell of a window of W cells nearest the mean, with the
+// factor's own rounding of c t
+__device__ __forceinline__ float mt_tmin2(float t0, float dt, int W) {
+  int j = (int)__builtin_rintf(-t0 / dt);
+  j = j < 0 ? 0 : (j > W - 1 ? W - 1 : j);
+  const float t = __builtin_fmaf((float)j, dt, t0);
+  return t * t;
 }
 
 // column factors as integers of 30 bits, G = rint(g 2^30) (g <= 1); the
@@ -205,8 +220,8 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
   r.hi[0] = hi0;
   r.lo[1] = lo1;
   r.hi[1] = hi1;
-  r.t0[0] = r.t0[1] = r.dt[0] = r.dt[1] = 0.0f;
-  uint32_t bb = 1u;  // tx_lo = 1 > tx_hi = 0: meets no tile
+  r.t0[0] = r.t0[1] = r.dt[0] = r.dt[1] = r.tm2[0] = r.tm2[1] = 0.0f;
+  unsigned long long bb = 1ull;  // tx_lo = 1 > tx_hi = 0: meets no tile
   if (r.flags == 0) {
     const double rs0 = 1.0 / s0, rs1 = 1.0 / s1;
     const double h0 = (a.hi[0] - a.lo[0]) / a.n0, h1 = (a.hi[1] - a.lo[1]) / a.n1;
@@ -215,8 +230,12 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
     r.dt[0] = (float)(h0 * rs0 * kC);
     r.dt[1] = (float)(h1 * rs1 * kC);
     double zx = 0.0, zy = 0.0;
-    for (int j = l16; j <= hi0 - lo0; j += 16) zx += (double)mt_factor(j, r.t0[0], r.dt[0]);
-    for (int j = l16; j <= hi1 - lo1; j += 16) zy += (double)mt_quant(mt_factor(j, r.t0[1], r.dt[1]));
+    r.tm2[0] = mt_tmin2(r.t0[0], r.dt[0], hi0 - lo0 + 1);
+    r.tm2[1] = mt_tmin2(r.t0[1], r.dt[1], hi1 - lo1 + 1);
+    for (int j = l16; j <= hi0 - lo0; j += 16)
+      zx += (double)mt_factor(j, r.t0[0], r.dt[0], r.tm2[0]);
+    for (int j = l16; j <= hi1 - lo1; j += 16)
+      zy += (double)mt_quant(mt_factor(j, r.t0[1], r.dt[1], r.tm2[1]));
     r.Z = sum16(zx) * (sum16(zy) * 0x1p-30);
     double s = mt_f(a, lo0 + (hi0 - lo0 + 1) / 2, lo1 + (hi1 - lo1 + 1) / 2);
     if (!isfinite(s)) s = 0.0;  // the window holds a non-finite value: NaN result
@@ -237,7 +256,8 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
       r.sc1 = ldexp(1.0, min(60 - (ez + er + 2), 1000));
       r.sc2 = ldexp(1.0, min(60 - (ez + 2 * er + 3), 1000));
     }
-    bb = (uint32_t)tx0 | ((uint32_t)tx1 << 8) | ((uint32_t)ty0 << 16) | ((uint32_t)ty1 << 24);
+    bb = (unsigned long long)tx0 | ((unsigned long long)tx1 << 16) |
+         ((unsigned long long)ty0 << 32) | ((unsigned long long)ty1 << 48);
   }
   if (l16 == 0) {
     a.rec[k] = r;
@@ -277,7 +297,10 @@ __global__ __launch_bounds__(256) void k_mt_prep(MTArgs a) {
 // and the row factors of the rows its results belong to; the sums over the
 // tile stay inside the wave.
 // ---------------------------------------------------------------------------
-constexpr int kDPitch = 80;   // LDS bytes per tile row of one digit plane (conflict-free 16-byte reads)
+// LDS bytes per tile row of one digit plane; the row's four 16-byte chunks
+// are stored in the order chunk xor (row / 4) mod 4, so that the eight rows
+// one 16-byte read serves at a time fall on distinct banks
+constexpr int kDPitch = 64;
 constexpr int kFBits = 30;    // fixed-point bits of F', F'^2 and the factors
 constexpr int kDig = 4;       // their base-256 digits
 
@@ -302,9 +325,10 @@ __device__ __forceinline__ void transpose4(uint32_t w0, uint32_t w1, uint32_t w2
   o[3] = __builtin_amdgcn_perm(b_hi, a_hi, 0x07060302u);
 }
 
-__global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
+// four workgroups per CU: 128 VGPRs, 34 KB of LDS
+__global__ __launch_bounds__(256, 4) void k_mt_main(MTArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t Dg[2 * kDig][kMT * kDPitch];  // digit planes: F', then F'^2
-  __shared__ int ring[kRing];
+  __shared__ uint16_t ring[kRing];
   __shared__ int wcnt[4];
   __shared__ unsigned long long nfmask[kMT];
 
@@ -350,8 +374,9 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       transpose4(hs[0], hs[1], hs[2], hs[3], ps);
 #pragma unroll
       for (int d = 0; d < kDig; ++d) {
-        *reinterpret_cast<uint32_t*>(&Dg[d][rr * kDPitch + cq]) = pf[d];
-        *reinterpret_cast<uint32_t*>(&Dg[kDig + d][rr * kDPitch + cq]) = ps[d];
+        const int sw = rr * kDPitch + ((((cq >> 4) ^ (rr >> 2)) & 3) << 4) + (cq & 15);
+        *reinterpret_cast<uint32_t*>(&Dg[d][sw]) = pf[d];
+        *reinterpret_cast<uint32_t*>(&Dg[kDig + d][sw]) = ps[d];
       }
     }
   }
@@ -363,11 +388,10 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
   struct Params {
     long long k;
     int l0, h0, l1, h1;
-    float t00, d0, t01, d1;
-    double sh, c1, c2;
+    float t00, d0, t01, d1, m0, m1;
   };
   auto load_params = [&](int pos, int cnt) {
-    Params p = {0, 1, 0, 1, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0, 0.0, 0.0};
+    Params p = {0, 1, 0, 1, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (li < cnt) {
       p.k = kbeg + ring[(pos + li) & (kRing - 1)];
       const MTRec& r = a.rec[p.k];
@@ -379,9 +403,8 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       p.d0 = r.dt[0];
       p.t01 = r.t0[1];
       p.d1 = r.dt[1];
-      p.sh = r.shift;
-      p.c1 = r.sc1;
-      p.c2 = r.sc2;
+      p.m0 = r.tm2[0];
+      p.m1 = r.tm2[1];
     }
     return p;
   };
@@ -403,7 +426,7 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       for (int u = 0; u < 4; ++u) {
         const int col = c0 + 16 * lg + 4 * qw + u;
         int G = 0;
-        if (col >= l1 && col <= h1) G = mt_quant(mt_factor(col - l1, t01, d1));
+        if (col >= l1 && col <= h1) G = mt_quant(mt_factor(col - l1, t01, d1, P.m1));
         zy += (double)G;
         h[u] = digits4(G);
       }
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
     double s1 = 0.0, s2 = 0.0, sx = 0.0;
 #pragma unroll 1
     for (int ib = 0; ib < 4; ++ib) {
-      const int rowoff = (16 * ib + li) * kDPitch + 16 * lg;
+      const int rowoff = (16 * ib + li) * kDPitch + (((lg ^ ((16 * ib + li) >> 2)) & 3) << 4);
       // lane (li, lg) holds rows 16 ib + 4 lg + r of pdf li (D[4q + r][j] in
       // lane j + 16q, slot r)
       double gr[4];
@@ -423,7 +446,7 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + 16 * ib + 4 * lg + r;
         float gx = 0.0f;
-        if (row >= l0 && row <= h0) gx = mt_factor(row - l0, t00, d0);
+        if (row >= l0 && row <= h0) gx = mt_factor(row - l0, t00, d0, P.m0);
         gr[r] = (double)gx;
         sx += gr[r];
       }
@@ -471,13 +494,14 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
     sx += __shfl_xor(sx, 32, 64);
     zy += __shfl_xor(zy, 32, 64);
     if (valid && lg == 0) {
+      const MTRec& r = a.rec[k];
       const double S1 = s1 * scF, S2 = s2 * scS;
       const double Zt = sx * (zy * 0x1p-30);
-      const double dl = T.a - P.sh;
+      const double dl = T.a - r.shift;
       const double A1 = S1 + dl * Zt;
       const double A2 = S2 + 2.0 * dl * S1 + dl * dl * Zt;
-      atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * P.c1));
-      atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * P.c2));
+      atomicAdd(&a.acc[2 * k], (unsigned long long)llrint(A1 * r.sc1));
+      atomicAdd(&a.acc[2 * k + 1], (unsigned long long)llrint(A2 * r.sc2));
       if (tbad) {
         // does the window's part of the tile hold a non-finite value?
         const int ra = max(l0, r0) - r0, rb = min(h0, r0 + kMT - 1) - r0;
@@ -494,15 +518,15 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
   int head = 0, tail = 0;  // uniform
   long long k0 = kbeg;
   // tile ranges of the next scan step, loaded one step ahead
-  uint32_t bb_next = (k0 + threadIdx.x < kend) ? a.bbox[k0 + threadIdx.x] : 1u;
+  unsigned long long bb_next = (k0 + threadIdx.x < kend) ? a.bbox[k0 + threadIdx.x] : 1ull;
   for (;;) {
     // fill the ring up to 256 pending pdfs (or the end of the part)
     while (tail - head < 256 && k0 < kend) {
       const long long k = k0 + threadIdx.x;
-      const uint32_t bb = bb_next;
-      bb_next = (k + 256 < kend) ? a.bbox[k + 256] : 1u;
-      const bool hit = k < kend && tx >= (int)(bb & 255u) && tx <= (int)((bb >> 8) & 255u) &&
-                       ty >= (int)((bb >> 16) & 255u) && ty <= (int)(bb >> 24);
+      const unsigned long long bb = bb_next;
+      bb_next = (k + 256 < kend) ? a.bbox[k + 256] : 1ull;
+      const bool hit = k < kend && tx >= (int)(bb & 0xFFFFu) && tx <= (int)((bb >> 16) & 0xFFFFu) &&
+                       ty >= (int)((bb >> 32) & 0xFFFFu) && ty <= (int)(bb >> 48);
       const unsigned long long m = __ballot(hit);
       __syncthreads();  // earlier readers of wcnt are done
       if (lane == 0) wcnt[w] = __popcll(m);
@@ -510,25 +534,16 @@ __global__ __launch_bounds__(256, 3) void k_mt_main(MTArgs a) {
       int off = tail;
       for (int v = 0; v < w; ++v) off += wcnt[v];
       if (hit)
-        ring[(off + __popcll(m & ((1ull << lane) - 1ull))) & (kRing - 1)] = (int)(k - kbeg);
+        ring[(off + __popcll(m & ((1ull << lane) - 1ull))) & (kRing - 1)] = (uint16_t)(k - kbeg);
       tail += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
       k0 += 256;
     }
     const int avail = min(tail - head, 256);
     if (avail == 0) break;
     __syncthreads();  // ring entries and the staged tile are visible
-    // wave w: pending pdfs 64w .. 64w + 63, 16 at a time, the next batch's
-    // records loaded while the current one runs
+    // wave w: pending pdfs 64w .. 64w + 63, 16 at a time
     const int bend = min(64 * w + 64, avail);
-    if (64 * w < bend) {
-      Params cur = load_params(head + 64 * w, min(16, avail - 64 * w));
-      for (int b = 64 * w; b < bend; b += 16) {
-        const Params nxt = b + 16 < bend ? load_params(head + b + 16, min(16, avail - b - 16))
-                                         : load_params(0, 0);
-        wave_batch(cur, min(16, avail - b));
-        cur = nxt;
-      }
-    }
+    for (int b = 64 * w; b < bend; b += 16) wave_batch(load_params(head + b, min(16, avail - b)), min(16, avail - b));
     head += avail;
     __syncthreads();  // the ring slots just used may be refilled
   }
@@ -574,7 +589,7 @@ MTLayout mt_layout(int ntiles, long long K) {
   MTLayout L;
   L.rec = 0;
   L.bbox = L.rec + al256((size_t)K * sizeof(MTRec));
-  L.acc = L.bbox + al256((size_t)K * 4);
+  L.acc = L.bbox + al256((size_t)K * 8);
   L.tiles = L.acc + al256((size_t)K * 16);
   L.bytes = L.tiles + al256((size_t)ntiles * sizeof(MTTile));
   return L;
@@ -582,15 +597,18 @@ MTLayout mt_layout(int ntiles, long long K) {
 
 }  // namespace
 
+// tile indices are 16 bits, the per-tile table and the workgroup count are
+// kept bounded (at most 2^20 tiles, parts of at most 65 536 pdfs each)
 bool moments_tiled_applies(const vup_mm& mm, const vup_dists& d) {
   if (mm.grid.ndim != 2 || d.ncomp != 1) return false;
   const long long ntx = (mm.grid.n[1] + kMT - 1) / kMT, nty = (mm.grid.n[0] + kMT - 1) / kMT;
-  return ntx <= kMTMaxTiles && nty <= kMTMaxTiles && d.K < (1ll << 31);
+  return ntx <= kMTMaxTiles && nty <= kMTMaxTiles && ntx * nty <= (1ll << 20) &&
+         d.K < (1ll << 26);
 }
 
 size_t moments_tiled_ws_bytes(const vup_mm& mm, long long K) {
-  const int ntx = (mm.grid.n[1] + kMT - 1) / kMT, nty = (mm.grid.n[0] + kMT - 1) / kMT;
-  return mt_layout(ntx * nty, K).bytes;
+  const long long ntx = (mm.grid.n[1] + kMT - 1) / kMT, nty = (mm.grid.n[0] + kMT - 1) / kMT;
+  return mt_layout((int)(ntx * nty), K).bytes;
 }
 
 hipError_t launch_moments_tiled(const vup_mm& mm, const vup_dists& d, const vup_model* model,
@@ -614,14 +632,16 @@ hipError_t launch_moments_tiled(const vup_mm& mm, const vup_dists& d, const vup_
   a.nty = (a.n0 + kMT - 1) / kMT;
   const int ntiles = a.ntx * a.nty;
   // parts of the pdf list per tile: about 2048 workgroups, at least 256
-  // pdfs per part
+  // pdfs per part, at most 65 536 (16-bit ring entries)
   long long parts = (2048 + ntiles - 1) / ntiles;
   parts = parts < d.K / 256 ? parts : d.K / 256;
-  a.parts = (int)(parts < 1 ? 1 : (parts > 64 ? 64 : parts));
+  parts = parts < 1 ? 1 : (parts > 64 ? 64 : parts);
+  const long long need = (d.K + 65535) / 65536;
+  a.parts = (int)(parts > need ? parts : need);
   const MTLayout L = mt_layout(ntiles, d.K);
   char* base = static_cast<char*>(ws);
   a.rec = reinterpret_cast<MTRec*>(base + L.rec);
-  a.bbox = reinterpret_cast<uint32_t*>(base + L.bbox);
+  a.bbox = reinterpret_cast<unsigned long long*>(base + L.bbox);
   a.acc = reinterpret_cast<unsigned long long*>(base + L.acc);
   a.tiles = reinterpret_cast<MTTile*>(base + L.tiles);
   a.mean = mean;

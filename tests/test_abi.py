@@ -165,7 +165,7 @@ def test_dists_validation(lib):
 
 
 def test_moments_tiled_arguments(lib):
-    """vup_moments_tiled: workspace size (72 + 4 + 16 bytes per pdf and 32 per
+    """vup_moments_tiled: workspace size (80 + 8 + 16 bytes per pdf and 32 per
     64 x 64 tile, each part rounded up to 256), workspace checks, and the
     per-pdf kernel's rules where the tiled form does not apply."""
     mm = _fake_mm(lib)
@@ -185,7 +185,7 @@ def test_moments_tiled_arguments(lib):
     big = vup.VupDists()
     big.K, big.ncomp, big.ndim, big.n_sigma, big.mu, big.sigma = 1000, 1, 2, 4.0, 0x1000, 0x2000
     assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm), ctypes.byref(big)) == (
-        72192 + 4096 + 16128 + 256)
+        80128 + 8192 + 16128 + 256)
     ws = ctypes.c_void_p(0x200000)
 
     def call(dd, ws_, nb, mean=dummy, var=dummy, d2=None, model=None):
@@ -200,6 +200,15 @@ def test_moments_tiled_arguments(lib):
     assert call(d, ws, ws_bytes, d2=dummy) == EINVAL
     m4 = vup.make_model("ring4")
     assert call(d, ws, ws_bytes, d2=dummy, model=ctypes.byref(m4)) == EINVAL
+    # tiles per axis up to 65 535, at most 2^20 in all; 3-D grids are not tiled
+    long_mm = _fake_mm(lib, n=(16448, 8))
+    assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(long_mm), ctypes.byref(d)) > 0
+    big_mm = _fake_mm(lib, n=(65600, 1100))
+    assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(big_mm), ctypes.byref(d)) == 0
+    mm3 = _fake_mm(lib)
+    mm3.grid = _grid((8, 8, 8), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    d3 = dists(ndim=3)
+    assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm3), ctypes.byref(d3)) == 0
     # mixtures: not tiled (no workspace), vup_moments' rules apply
     d2c = dists(ncomp=2, weight=0x3000)
     assert lib.vup_moments_tiled_workspace_bytes(ctypes.byref(mm), ctypes.byref(d2c)) == 0

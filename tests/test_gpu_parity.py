@@ -451,6 +451,29 @@ def test_moments_2d_forms(vup, orc, case, tiled):
     _moments_vs_oracle(vup, orc, wl, tiled)
 
 
+def test_moments_tiled_long_grid(vup, orc):
+    """257 tiles along one axis (16-bit tile indices) and windows thousands
+    of cells long against the oracle."""
+    wl = workloads.random_workload("long", (16448, 6), (-4.0, -1.0), (4.0, 1.0), "sincos2", 16,
+                                   200, 1, (0.01, 0.5), seed=5)
+    _say(f"[moments long grid] n={wl.n} K={wl.K}")
+    _moments_vs_oracle(vup, orc, wl, True)
+
+
+def test_moments_tiled_hands_over_to_the_per_pdf_kernel(vup):
+    """Outside the tiled form (a 2-D mixture here) vup_moments_tiled runs the
+    per-pdf kernel of vup_moments: the same bits, and no workspace."""
+    wl = workloads.random_workload("mix", (61, 45), (-3.0, -3.0), (3.0, 3.0), "timing2", 16,
+                                   100, 2, (0.05, 0.8), seed=9)
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    f = vup.eval_grid(g, wl.model)
+    mm = vup.build_model_matrix(g, f, vup.uniform_edges(f, wl.B))
+    assert vup.moments_workspace(mm, wl.mu, wl.sigma, wl.weight) is None
+    m1, v1, _ = vup.moments(mm, wl.mu, wl.sigma, wl.weight, tiled=True)
+    m0, v0, _ = vup.moments(mm, wl.mu, wl.sigma, wl.weight, tiled=False)
+    assert torch.equal(m1, m0) and torch.equal(v1, v0)
+
+
 def test_moments_tiled_many_parts(vup, orc):
     """Enough pdfs on a 2 x 2-tile grid that each tile's list is split in
     parts (part boundaries, partial last batches)."""
