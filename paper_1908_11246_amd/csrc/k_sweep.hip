@@ -1077,33 +1077,32 @@ __device__ __forceinline__ void mom_load(const SweepArgs& a, const float2* rt, c
 }
 
 // One row of a thread's 8-cell strip. The FP32 model copy is anchored: the
-// strip's first cell holds f_0 and the others d_j = f_j - f_0, so with
-// delta = f_0 - shift and gs = the strip's factor sum,
-//   sum_j g_j (f_j - shift)   = sum_{j>0} g_j d_j + delta gs
-//   sum_j g_j (f_j - shift)^2 = sum_{j>0} g_j d_j^2 + 2 delta sum_{j>0} g_j d_j
-//                               + delta^2 gs,
-// three operations per cell instead of four.
+// strip's first cell holds f_0 and the others d_j = f_j - f_0. Each cell's
+// shifted value v_j = f_j - shift = d_j + (f_0 - shift) is formed before it is
+// weighted, so the sums hold only terms of the size of f - shift: expanding
+// (d_j + delta)^2 instead would add terms of the size of d_j and delta that
+// cancel, and lose their FP32 rounding error against the variance whenever the
+// anchor's value lies far from the window's (a strip that meets the window in
+// a few cells of a steep, coarsely sampled axis).
 template <int SW>
-__device__ __forceinline__ void mom_sum(const MomRow<SW>& m, const float* gl, float gs,
-                                        float shift, float& B1, float& B2) {
+__device__ __forceinline__ void mom_sum(const MomRow<SW>& m, const float* gl, float shift,
+                                        float& B1, float& B2) {
   static_assert(SW == 8, "strips of eight cells, one anchor each");
+  const float dl = m.f[0].x - shift;
   float a1 = 0.0f, a2 = 0.0f;
 #pragma unroll
   for (int q = 0; q < SW / 4; ++q) {
     const float fj[4] = {m.f[q].x, m.f[q].y, m.f[q].z, m.f[q].w};
 #pragma unroll
-    for (int e = (q == 0 ? 1 : 0); e < 4; ++e) {
-      const float t = gl[4 * q + e] * fj[e];
+    for (int e = 0; e < 4; ++e) {
+      const float v = (q == 0 && e == 0) ? dl : fj[e] + dl;
+      const float t = gl[4 * q + e] * v;
       a1 += t;
-      a2 = fmaf(t, fj[e], a2);
+      a2 = fmaf(t, v, a2);
     }
   }
-  const float dl = m.f[0].x - shift;
-  const float dg = dl * gs;
-  const float s1 = a1 + dg;
-  const float s2 = fmaf(dl + dl, a1, fmaf(dg, dl, a2));
-  B1 = fmaf(m.go, s1, B1);
-  B2 = fmaf(m.go, s2, B2);
+  B1 = fmaf(m.go, a1, B1);
+  B2 = fmaf(m.go, a2, B2);
 }
 
 template <int SW>
@@ -1121,9 +1120,6 @@ __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, 
     float gl[SW];
 #pragma unroll
     for (int j = 0; j < SW; ++j) gl[j] = tabL[s * SW + j];
-    float gs = 0.0f;
-#pragma unroll
-    for (int j = 0; j < SW; ++j) gs += gl[j];
     const float* fbase = a.f32 + colbase + s * SW;
     int r = ph;
     if (r >= rc) continue;
@@ -1136,11 +1132,11 @@ __device__ __forceinline__ void mom_rows(const SweepArgs& a, const float* smem, 
     for (;;) {
       const int rb = r + P0;
       if (rb < rc) mom_load<SW>(a, rt, fbase, rb, mb);
-      mom_sum<SW>(ma, gl, gs, shift, B1, B2);
+      mom_sum<SW>(ma, gl, shift, B1, B2);
       if (rb >= rc) break;
       r = rb + P0;
       if (r < rc) mom_load<SW>(a, rt, fbase, r, ma);
-      mom_sum<SW>(mb, gl, gs, shift, B1, B2);
+      mom_sum<SW>(mb, gl, shift, B1, B2);
       if (r >= rc) break;
       if (++pairs == 4) {
         A1 += (double)B1;

@@ -451,13 +451,17 @@ def test_moments_2d_forms(vup, orc, case, tiled):
     _moments_vs_oracle(vup, orc, wl, tiled)
 
 
-def test_moments_tiled_long_grid(vup, orc):
-    """257 tiles along one axis (16-bit tile indices) and windows thousands
-    of cells long against the oracle."""
+@pytest.mark.parametrize("tiled", [True, False], ids=["tiled", "per_pdf"])
+def test_moments_long_grid(vup, orc, tiled):
+    """A 16448 x 6 grid against the oracle. Tiled: 257 tiles along one axis
+    (16-bit tile indices) and windows thousands of cells long. Per pdf: the
+    six-cell fastest axis is steep, so a strip's anchor value lies far from
+    those of the few window cells it meets (the case that needs the shifted
+    value formed per cell)."""
     wl = workloads.random_workload("long", (16448, 6), (-4.0, -1.0), (4.0, 1.0), "sincos2", 16,
                                    200, 1, (0.01, 0.5), seed=5)
-    _say(f"[moments long grid] n={wl.n} K={wl.K}")
-    _moments_vs_oracle(vup, orc, wl, True)
+    _say(f"[moments long grid {'tiled' if tiled else 'per-pdf'}] n={wl.n} K={wl.K}")
+    _moments_vs_oracle(vup, orc, wl, tiled)
 
 
 def test_moments_tiled_hands_over_to_the_per_pdf_kernel(vup):
