@@ -201,7 +201,11 @@ int vup_windows(const vup_grid* g, const vup_dists* d, int32_t* win, void* strea
  *   P: dev FP32 [K][B] (row k = output pdf of distribution k; the paper's
  *      N_y x L output matrix stored column-major);
  *   Z: dev FP64 [K][ncomp] or NULL: sum of the (precision-rounded) weights of
- *      each component over its window, including cells with no bin.
+ *      each component over its window, including cells with no bin. An axis
+ *      whose largest weight factor in the window would be below 2^-20 (a pdf
+ *      far narrower than a cell) has its factors scaled by a power of two
+ *      inside the kernels; Z is scaled back exactly, and P does not depend
+ *      on the scale.
  * precision: VUP_FP32 / VUP_BF16 / VUP_BF16X2 / VUP_FP8E4M3. FP32 densities
  * are accumulated per run of equal bin along the fastest axis (prefix sums of
  * the fastest-axis factors) or per cell, as vup_set_sweep_mode selects; the

@@ -8,7 +8,10 @@
 // which is eq. VUP with the input matrix factorised: T is a cheap scatter
 // over one axis, and the contraction over the other axis is a dense banded
 // matrix product that runs on the matrix cores (MFMA, FP32 in and out).
-//   k_axis_factors   A_d, Zd = sum_i A_d[i][m] (FP64), window bounds
+//   k_axis_factors   A_d, Zd = sum_i A_d[i][m] (FP64), window bounds; each
+//                    column scaled by its power of two (axis_scale_exp; the
+//                    scale cancels from P)
+//   k_sep_z          the normalisers Z[k] = Zx Zy with the scales put back
 //   k_axis_prefix    G = prefix sums of A_y along y (FP64)
 //   k_sep_runs_tiled T from the model matrix's runs of equal bin along y:
 //                    one G difference per run, 32-bin LDS tiles, T written
@@ -92,11 +95,13 @@ __global__ __launch_bounds__(256) void k_axis_factors(SepArgs a) {
   const double mu = a.mu[d][m], sg = a.sigma[d][m];
   int jlo, jhi;
   const bool ok = axis_window(a.lo[d], a.hi[d], n, mu, sg, a.ns, jlo, jhi);
+  const int me = (ok && jhi >= jlo) ? axis_scale_exp(a.lo[d], a.hi[d], n, jlo, jhi, mu, 1.0 / sg)
+                                     : 0;
   double zp = 0.0;
   for (int i = threadIdx.x; i < rowsw; i += 256) {
     float v = 0.0f;
     if (ok && i < n && i >= jlo && i <= jhi)
-      v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg);
+      v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg, me);
     if (i < rows) {
       col[(long long)i * ld] = v;
       zp += (double)v;
@@ -554,7 +559,6 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm(SepArgs a) {
             if (b0 + 4 * q4 + q < B) dst[4 * q4 + q] = o[q];
         }
       }
-      if (a.Z && blockIdx.y == 0) a.Z[k] = z;
     }
   }
 }
@@ -750,9 +754,29 @@ __global__ __launch_bounds__(256, 4) void k_sep_gemm_bf16(SepArgs a) {
                                   : (z == 0.0 ? 0.0f : __builtin_nanf(""));
         if (b0 + q < B) dst[q] = o;
       }
-      if (a.Z && blockIdx.y == 0) a.Z[k] = z;
     }
   }
+}
+
+// Z[k] for k = mx M_y + my: the product of the two axes' factor sums, times
+// 2^-(m_x + m_y) to undo the columns' scaling (k_axis_factors), so that Z is
+// the mass of the truncated densities themselves
+__global__ __launch_bounds__(256) void k_sep_z(SepArgs a) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long K = (long long)a.M[0] * a.M[1];
+  if (k >= K) return;
+  const int m[2] = {(int)(k / a.M[1]), (int)(k % a.M[1])};
+  double z = 1.0;
+  int ms = 0;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    z *= a.Zd[d][m[d]];
+    const int jlo = a.win[d][2 * m[d]], jhi = a.win[d][2 * m[d] + 1];
+    if (jhi >= jlo)
+      ms += axis_scale_exp(a.lo[d], a.hi[d], a.n[d], jlo, jhi, a.mu[d][m[d]],
+                           1.0 / a.sigma[d][m[d]]);
+  }
+  a.Z[k] = ldexp(z, -ms);
 }
 
 // per-distribution parameters of a family propagated by the general sweep:
@@ -854,6 +878,12 @@ hipError_t launch_separable(const vup_mm& mm, int Mx, int My, const double* mu_x
   hipLaunchKernelGGL(k_axis_factors, dim3(Mmax, 2), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (Z) {
+    const long long K = (long long)Mx * My;
+    hipLaunchKernelGGL(k_sep_z, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (a.n[1] <= 65534) {
     // run records hold 16-bit columns: T from the runs and the y prefix sums
     hipLaunchKernelGGL(k_axis_prefix, dim3(My), dim3(256), 0, s, a);

@@ -4,9 +4,9 @@
 // i.e. the posterior over input cells given that the output fell in bin b,
 // relative to the forward propagation that produced P (and its per-component
 // normalisation Z). p_k is the same truncated, normalised Gaussian mixture the
-// propagation sums: FP32 per-axis factors (gauss_factor_r) and their product;
-// the mixture weight, 1/Z_{k,c} and 1/P_b are combined in FP64 per bin and
-// applied in FP32.
+// propagation sums: FP32 per-axis factors (gauss_factor_r, each axis scaled by
+// its power of two 2^m) and their product; the mixture weight, 2^-sum m,
+// 1/Z_{k,c} and 1/P_b are combined in FP64 per bin and applied in FP32.
 //   k_posterior       workgroups over grid rows: per-bin factors
 //                     pi_c / (Z_c P_b), the fastest-axis factors and the
 //                     row's factor product staged, one multiply-add per cell
@@ -59,7 +59,8 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
   extern __shared__ float sfb[];  // [C][B], then (when it fits) the fastest-axis factors [C][n_L]
   __shared__ int swin[VUP_MAX_COMP][VUP_MAX_DIM][2];
   __shared__ double smu[VUP_MAX_COMP][VUP_MAX_DIM], srs[VUP_MAX_COMP][VUP_MAX_DIM];
-  __shared__ double sfac[VUP_MAX_COMP];  // pi_c / Z_{k,c}
+  __shared__ int sm[VUP_MAX_COMP][VUP_MAX_DIM];  // the factors' scale exponents
+  __shared__ double sfac[VUP_MAX_COMP];            // pi_c 2^-sum_d m_d / Z_{k,c}
   __shared__ int sbad;
   const int t = blockIdx.y;
   const long long k = a.sel[t];
@@ -77,13 +78,21 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
     swin[c][d][1] = hi;
     smu[c][d] = mu;
     srs[c][d] = 1.0 / sg;
+    sm[c][d] = (ok && hi >= lo) ? axis_scale_exp(a.lo[d], a.hi[d], a.n[d], lo, hi, mu, 1.0 / sg)
+                                : 0;
     if (!ok) atomicOr(&sbad, 1);
-    if (d == 0) {
-      const double z = a.Z[k * C + c];
-      const double w = C > 1 ? a.weight[k * C + c] : 1.0;
-      sfac[c] = w / z;
-      if (!isfinite(z)) atomicOr(&sbad, 1);
-    }
+  }
+  __syncthreads();
+  if (threadIdx.x < C && kok) {
+    // the scaled factors' product is 2^(sum_d m_d) times the density, as in
+    // the propagation that reported Z
+    const int c = threadIdx.x;
+    int ms = 0;
+    for (int d = 0; d < D; ++d) ms += sm[c][d];
+    const double z = a.Z[k * C + c];
+    const double w = C > 1 ? a.weight[k * C + c] : 1.0;
+    sfac[c] = ldexp(w / z, -ms);
+    if (!isfinite(z)) atomicOr(&sbad, 1);
   }
   __syncthreads();
   if (kok) {
@@ -104,7 +113,7 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
       const int wlo = swin[c][D - 1][0], whi = swin[c][D - 1][1];
       for (int col = wlo + (int)threadIdx.x; col <= whi; col += blockDim.x)
         gtab[c * nL + col] = gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
-                                            smu[c][D - 1], srs[c][D - 1]);
+                                            smu[c][D - 1], srs[c][D - 1], sm[c][D - 1]);
     }
   }
   __syncthreads();
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
         for (int d = 0; d + 1 < D; ++d) {
           in = in && j[d] >= swin[c][d][0] && j[d] <= swin[c][d][1];
           if (in) f *= gauss_factor_r(cell_centre(a.lo[d], a.hi[d], a.n[d], j[d]), smu[c][d],
-                                      srs[c][d]);
+                                      srs[c][d], sm[c][d]);
         }
         if (in && swin[c][D - 1][1] >= swin[c][D - 1][0]) {
           ri.rf[c] = f;
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
         if (c < C && col >= ri.clo[c] && col <= ri.chi[c]) {
           const float g = a.gtab ? gtab[c * nL + col]
                                  : gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
-                                                  smu[c][D - 1], srs[c][D - 1]);
+                                                  smu[c][D - 1], srs[c][D - 1], sm[c][D - 1]);
           v = fmaf(ri.rf[c] * g, sfb[c * B + b], v);
         }
       }

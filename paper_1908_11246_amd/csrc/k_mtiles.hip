@@ -44,8 +44,6 @@ namespace vup {
 
 namespace {
 
-typedef double mt_f64x4 __attribute__((ext_vector_type(4)));
-
 constexpr int kMT = 64;               // tile edge in cells
 constexpr int kMTMaxTiles = 65535;    // tiles per axis (16-bit tile indices)
 constexpr int kRing = 512;            // candidate ring: < 256 pending + one scan step of 256

@@ -77,34 +77,44 @@ __device__ __forceinline__ T pick4(const T (&v)[4], int i) {
 struct Win {
   int lo[4];
   int W[4];
+  const int* m;  // LDS: the factors' scale exponents per axis (axis_scale_exp)
+  bool scaled;   // some m is not 0
   long long R;  // rows
   bool bad;
   bool empty;
 };
 
 // Window of component kc. Lanes 0..3 of wave 0 compute one axis each (FP64,
-// the exact formula of axis_window) into LDS (`wsh`, 12 ints); every thread
-// then reads the result. Contains two workgroup barriers.
+// the exact formula of axis_window, and the axis's scale exponent) into LDS
+// (`wsh`, 16 ints); every thread then reads the result. Contains two
+// workgroup barriers.
 __device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* wsh) {
   const int D = a.g.ndim;
   __syncthreads();  // earlier readers of wsh are done
   if (threadIdx.x < 4) {
     const int d = threadIdx.x;
-    int jlo = 0, jhi = 0, flags = 0;
+    int jlo = 0, jhi = 0, flags = 0, m = 0;
     if (d < D) {
-      const bool ok = axis_window(a.g.lo[d], a.g.hi[d], a.g.n[d], a.d.mu[kc * D + d],
-                                  a.d.sigma[kc * D + d], a.d.ns, jlo, jhi);
+      const double mu = a.d.mu[kc * D + d], sg = a.d.sigma[kc * D + d];
+      const bool ok = axis_window(a.g.lo[d], a.g.hi[d], a.g.n[d], mu, sg, a.d.ns, jlo, jhi);
       flags = (ok ? 0 : 1) | (jhi < jlo ? 2 : 0);
+      // a window of several cells holds only cells within n_sigma sigma of the
+      // mean, so m = 0 there unless n_sigma reaches about 5.27 (axis_scale_exp)
+      if (ok && jhi >= jlo && (jhi == jlo || a.d.ns >= 5.25))
+        m = axis_scale_exp(a.g.lo[d], a.g.hi[d], a.g.n[d], jlo, jhi, mu, 1.0 / sg);
     }
     wsh[d] = jlo;
     wsh[4 + d] = jhi - jlo + 1;
     wsh[8 + d] = flags;
+    wsh[12 + d] = m;
   }
   __syncthreads();
   // the values are uniform: keep them in scalar registers
   Win w;
   w.R = 1;
   const int flags = __builtin_amdgcn_readfirstlane(wsh[8] | wsh[9] | wsh[10] | wsh[11]);
+  w.m = wsh + 12;
+  w.scaled = __builtin_amdgcn_readfirstlane(wsh[12] | wsh[13] | wsh[14] | wsh[15]) != 0;
   w.bad = (flags & 1) != 0;
   w.empty = (flags & 2) != 0;
 #pragma unroll
@@ -114,6 +124,12 @@ __device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* w
     if (d + 1 < D) w.R *= (w.W[d] > 0 ? w.W[d] : 0);
   }
   return w;
+}
+
+// scale exponent of axis d (0 unless the window has a scaled axis: one LDS
+// read, uniform, in that rare case only)
+__device__ __forceinline__ int win_m(const Win& w, int d) {
+  return w.scaled ? __builtin_amdgcn_readfirstlane(w.m[d]) : 0;
 }
 
 // fastest-axis window bounds (avoids dynamic indexing of the Win arrays)
@@ -166,10 +182,13 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
     if (d + 1 < D) {
       float* tab = smem + a.L.tab_off[d];
       const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-      for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
-        const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
-        tab[i] = gauss_factor_r(x, mu, rsig);
-      }
+      const int m = win_m(w, d);
+      with_scale(m, [&](auto S) {
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
+          const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
+          tab[i] = gauss_factor_r<S.value>(x, mu, rsig, m);
+        }
+      });
     }
   }
   const int L = D - 1;
@@ -177,15 +196,18 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
   last_axis(w, D, loL, WL);
   float* tab = smem + pick4(a.L.tab_off, L);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
-  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
-    const int j = colbase + jj;
-    float v = 0.0f;
-    if (j >= loL && j < loL + WL) {
-      const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j);
-      v = gauss_factor_r(x, mu, rsig);
+  const int m = win_m(w, L);
+  with_scale(m, [&](auto S) {
+    for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+      const int j = colbase + jj;
+      float v = 0.0f;
+      if (j >= loL && j < loL + WL) {
+        const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j);
+        v = gauss_factor_r<S.value>(x, mu, rsig, m);
+      }
+      tab[jj] = v;
     }
-    tab[jj] = v;
-  }
+  });
 }
 
 // Row table for rows [r0, r0 + rc): row factor (product of the slower axes'
@@ -345,9 +367,13 @@ __device__ __forceinline__ double exp_nonpos(double a) {
   return ldexp(p, (int)n);
 }
 
-__device__ __forceinline__ float gauss_factor_exact(double x, double mu, double rsig) {
+// scaled by 2^m as gauss_factor_r (axis_scale_exp keeps the argument <= 0)
+template <bool S>
+__device__ __forceinline__ float gauss_factor_exact(double x, double mu, double rsig, int m) {
   const double t = (x - mu) * rsig;
-  return (float)exp_nonpos(-0.5 * (t * t));
+  double arg = -0.5 * (t * t);
+  if constexpr (S) arg += (double)m * 0.6931471805599453;
+  return (float)exp_nonpos(arg);
 }
 
 __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* smem, const Win& w,
@@ -358,9 +384,12 @@ __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* sm
     if (d + 1 < D) {
       float* tab = smem + a.L.tab_off[d];
       const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-      for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-        tab[i] = gauss_factor_exact(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
-                                    rsig);
+      const int m = win_m(w, d);
+      with_scale(m, [&](auto S) {
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+          tab[i] = gauss_factor_exact<S.value>(
+              cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
+      });
     }
   }
   const int L = D - 1;
@@ -368,20 +397,34 @@ __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* sm
   last_axis(w, D, loL, WL);
   float* tab = smem + pick4(a.L.tab_off, L);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
-  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
-    const int j = colbase + jj;
-    float v = 0.0f;
-    if (j >= loL && j < loL + WL)
-      v = gauss_factor_exact(cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j),
-                             mu, rsig);
-    tab[jj] = v;
-  }
+  const int m = win_m(w, L);
+  with_scale(m, [&](auto S) {
+    for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+      const int j = colbase + jj;
+      float v = 0.0f;
+      if (j >= loL && j < loL + WL)
+        v = gauss_factor_exact<S.value>(
+            cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j), mu, rsig, m);
+      tab[jj] = v;
+    }
+  });
+}
+
+// sum over the axes of component kc of their scale exponents m
+// (axis_scale_exp): the factor tables' products, and the masses summed from
+// them, are 2^sum times the densities'
+__device__ __forceinline__ int win_scale_exp(const SweepArgs& a, const Win& w) {
+  if (!w.scaled) return 0;
+  int s = 0;
+  for (int d = 0; d < a.g.ndim; ++d) s += w.m[d];
+  return s;
 }
 
 // per-copy scales of the cell form, shared by all threads (LDS)
 struct PropScales {
   double scale[16];    // fixed-point units per unit of density, per copy
   double unscale[16];  // 1 / scale (0 for a copy without cells)
+  int mexp;            // win_scale_exp of the component
   float scalef[16];    // scale rounded to FP32
 };
 constexpr int kPropScalesFloats = (int)(sizeof(PropScales) / sizeof(float));
@@ -397,8 +440,9 @@ constexpr int kPropScaleScratch = 16 + 16 + 256 + 16;  // doubles: A, G, partial
 // sum of axis x's factors at i_x = e (mod nc). FP64, in a fixed order. The
 // row table's LDS serves as scratch (it is rebuilt after this).
 template <int PREC>
-__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w, int ns,
-                                            int sw, int cols, PropScales* ps) {
+__device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, const Win& w,
+                                            long long kc, int ns, int sw, int cols,
+                                            PropScales* ps) {
   static_assert(kThreads == 256, "256 partial sums");
   const int D = a.g.ndim;
   const int nc = a.L.cpw;
@@ -476,6 +520,7 @@ __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, con
     ps->unscale[t] = sc > 0.0 ? 1.0 / sc : 0.0;
     ps->scalef[t] = (float)sc;
   }
+  if (t == 0) ps->mexp = win_scale_exp(a, w);
   __syncthreads();
 }
 
@@ -648,10 +693,11 @@ __device__ __forceinline__ void prop_rows(const SweepArgs& a, float* smem, int r
 
 // Unscale the interleaved histogram copies of component kc (bin b, copy c at
 // word b nc + c), normalise by the sum over all slots (cells without a bin
-// included) and add the weighted column into Pk.
+// included) and add the weighted column into Pk. The reported normaliser is
+// the mass of the densities: the tables' mass times 2^-*mexp.
 __device__ __forceinline__ void finish_cells(const SweepArgs& a, const uint32_t* hist, int nc,
                                              const double* unscale, double* red, long long kc,
-                                             float* Pk, bool written) {
+                                             const int* mexp, float* Pk, bool written) {
   const int B = a.B;
   auto slot = [&](int b) {
     double v = 0.0;
@@ -673,7 +719,7 @@ __device__ __forceinline__ void finish_cells(const SweepArgs& a, const uint32_t*
     const double v0 = b0 <= B ? slot(b0) : 0.0;
     const double v1 = b1 <= B ? slot(b1) : 0.0;
     const double Zc = block_sum(v0 + v1, red);
-    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+    if (a.Z && threadIdx.x == 0) a.Z[kc] = ldexp(Zc, -*mexp);
     const double f = wk / Zc;
     if (b0 < B) Pk[b0] = (float)((written ? (double)Pk[b0] : 0.0) + v0 * f);
     if (b1 < B) Pk[b1] = (float)((written ? (double)Pk[b1] : 0.0) + v1 * f);
@@ -682,7 +728,7 @@ __device__ __forceinline__ void finish_cells(const SweepArgs& a, const uint32_t*
   double zpart = 0.0;
   for (int b = threadIdx.x; b <= B; b += kThreads) zpart += slot(b);
   const double Zc = block_sum(zpart, red);
-  if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+  if (a.Z && threadIdx.x == 0) a.Z[kc] = ldexp(Zc, -*mexp);
   const double f = wk / Zc;
   for (int b = threadIdx.x; b < B; b += kThreads) {
     const double prev = written ? (double)Pk[b] : 0.0;
@@ -696,7 +742,8 @@ __device__ __forceinline__ void finish_cells(const SweepArgs& a, const uint32_t*
 // stride.
 __device__ __forceinline__ void finish_component(const SweepArgs& a, const uint32_t* hist, int ncls,
                                                  int cpc, const double* unscale, double* red,
-                                                 long long kc, float* Pk, bool written) {
+                                                 long long kc, const int* mexp, float* Pk,
+                                                 bool written) {
   const int B = a.B;
   const int stride = a.L.hist_stride;
   auto slot = [&](int b) {
@@ -715,7 +762,7 @@ __device__ __forceinline__ void finish_component(const SweepArgs& a, const uint3
     const double v0 = b0 <= B ? slot(b0) : 0.0;
     const double v1 = b1 <= B ? slot(b1) : 0.0;
     const double Zc = block_sum(v0 + v1, red);
-    if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+    if (a.Z && threadIdx.x == 0) a.Z[kc] = ldexp(Zc, -*mexp);
     const double f = wk / Zc;
     if (b0 < B) Pk[b0] = (float)((written ? (double)Pk[b0] : 0.0) + v0 * f);
     if (b1 < B) Pk[b1] = (float)((written ? (double)Pk[b1] : 0.0) + v1 * f);
@@ -724,7 +771,7 @@ __device__ __forceinline__ void finish_component(const SweepArgs& a, const uint3
   double zpart = 0.0;
   for (int b = threadIdx.x; b <= B; b += kThreads) zpart += slot(b);
   const double Zc = block_sum(zpart, red);
-  if (a.Z && threadIdx.x == 0) a.Z[kc] = Zc;
+  if (a.Z && threadIdx.x == 0) a.Z[kc] = ldexp(Zc, -*mexp);
   const double f = wk / Zc;
   for (int b = threadIdx.x; b < B; b += kThreads) {
     const double prev = written ? (double)Pk[b] : 0.0;
@@ -785,7 +832,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_propagate(SweepArgs a) {
         h4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
-    prop_scales<PREC>(a, smem, w, ns, sw, ns < kThreads ? ns : kThreads, ps);
+    prop_scales<PREC>(a, smem, w, kc, ns, sw, ns < kThreads ? ns : kThreads, ps);
     const int rr = a.L.rrows;
     RowIt it;
     rowit_init(it, threadIdx.x, w, D);
@@ -802,7 +849,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_propagate(SweepArgs a) {
       }
     }
     __syncthreads();
-    finish_cells(a, hist, nc, ps->unscale, red, kc, Pk, written);
+    finish_cells(a, hist, nc, ps->unscale, red, kc, &ps->mexp, Pk, written);
     written = true;
   }
   finish_column(a, Pk, anybad, written);
@@ -834,6 +881,7 @@ struct RunRow {
 struct RunScales {
   double srow[3];
   double unscale[3];
+  int mexp;  // win_scale_exp of the component
 };
 
 constexpr int kRunGroup = 16;  // lanes per row: one DPP row
@@ -846,7 +894,7 @@ constexpr int kBwdRowChunk = 256;
 // for every column c = 0 .. n (0 up to loL, the window total from hiL + 1 on).
 // Thread t sums a contiguous slice of the window; slice totals are scanned.
 __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* smem, long long kc,
-                                                  int loL, int WL, double* red) {
+                                                  int loL, int WL, int m, double* red) {
   const int D = a.g.ndim;
   const int L = D - 1;
   const int nL = pick4(a.g.n, L);
@@ -857,12 +905,14 @@ __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* sme
   const int j1 = min(j0 + per, WL);
   double* Gw = G + loL;  // Gw[j + 1] = sum over window columns loL .. loL + j
   double sum = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), nL, loL + j);
-    const double g = (double)gauss_factor_r(x, mu, rsig);
-    Gw[j + 1] = g;
-    sum += g;
-  }
+  with_scale(m, [&](auto S) {
+    for (int j = j0; j < j1; ++j) {
+      const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), nL, loL + j);
+      const double g = (double)gauss_factor_r<S.value>(x, mu, rsig, m);
+      Gw[j + 1] = g;
+      sum += g;
+    }
+  });
   // inclusive scan of the slice sums within the wave, then across waves
   const int lane = threadIdx.x & 63;
   const double incl = wave_scan(sum);
@@ -1022,13 +1072,16 @@ __global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
       if (d + 1 < D) {
         float* tab = smem + a.L.tab_off[d];
         const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
-                                  rsig);
+        const int m = win_m(w, d);
+        with_scale(m, [&](auto S) {
+          for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+            tab[i] = gauss_factor_r<S.value>(
+                cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
+        });
       }
     }
     for (int i = threadIdx.x; i < 3 * a.L.hist_stride; i += kThreads) smem[a.L.hist_off + i] = 0.0f;
-    build_prefix_runs(a, smem, kc, loL, WL, red);
+    build_prefix_runs(a, smem, kc, loL, WL, win_m(w, D - 1), red);
     const double Zrows = row_mass(a, smem, w, red);
     if (threadIdx.x == 0) {
       const double colmass = reinterpret_cast<const double*>(smem + a.L.g_off)[loL + WL];
@@ -1040,6 +1093,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
         ps->srow[r] = K / (prec_qfac<VUP_FP32>() * rowbound[r] * colmass);
         ps->unscale[r] = 1.0 / ps->srow[r];
       }
+      ps->mexp = win_scale_exp(a, w);
     }
     for (long long r0 = 0; r0 < w.R; r0 += RR) {
       const int rc = (int)((w.R - r0) < RR ? (w.R - r0) : RR);
@@ -1049,7 +1103,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
       prop_runs(a, smem, rc);
     }
     __syncthreads();
-    finish_component(a, hist, 3, 1, ps->unscale, red, kc, Pk, written);
+    finish_component(a, hist, 3, 1, ps->unscale, red, kc, &ps->mexp, Pk, written);
     written = true;
   }
   finish_column(a, Pk, anybad, written);
@@ -1517,7 +1571,8 @@ __device__ __forceinline__ f32x4v lds_load_f4(uint32_t byte_addr) {
 // G3[c] = (G0, G1, G2, -) for c = 0 .. n (sums over the window columns below
 // c); the FP64 window totals go to tot[0..2].
 __device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem, long long kc,
-                                                 int loL, int WL, double* red, double* tot) {
+                                                 int loL, int WL, int m, double* red,
+                                                 double* tot) {
   const int D = a.g.ndim;
   const int L = D - 1;
   const int nL = pick4(a.g.n, L);
@@ -1528,15 +1583,17 @@ __device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem
   const int j0 = min((int)threadIdx.x * per, WL);
   const int j1 = min(j0 + per, WL);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
-    const float gf = gauss_factor_r(cell_centre(lo, hi, nL, loL + j), mu, rsig);
-    const double g = (double)gf;
-    s0 += g;
-    s1 += g * t;
-    s2 += g * t * t;
-    G3[loL + j + 1].w = gf;  // the factor, until the sums overwrite the entry
-  }
+  with_scale(m, [&](auto S) {
+    for (int j = j0; j < j1; ++j) {
+      const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
+      const float gf = gauss_factor_r<S.value>(cell_centre(lo, hi, nL, loL + j), mu, rsig, m);
+      const double g = (double)gf;
+      s0 += g;
+      s1 += g * t;
+      s2 += g * t * t;
+      G3[loL + j + 1].w = gf;  // the factor, until the sums overwrite the entry
+    }
+  });
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double i0 = wave_scan(s0), i1 = wave_scan(s1), i2 = wave_scan(s2);
   if (lane == 63) {
@@ -1730,12 +1787,15 @@ __global__ __launch_bounds__(kThreads, NO <= 1 ? 5 : 1) void k_backward_runs(Swe
       if (d + 1 < D) {
         float* tab = smem + a.L.tab_off[d];
         const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
-                                  rsig);
+        const int m = win_m(w, d);
+        with_scale(m, [&](auto S) {
+          for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+            tab[i] = gauss_factor_r<S.value>(
+                cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
+        });
       }
     }
-    build_prefix_bwd(a, smem, kc, loL, WL, red, tot);
+    build_prefix_bwd(a, smem, kc, loL, WL, win_m(w, D - 1), red, tot);
     BwdAcc<NO> acc;
     acc.a0 = acc.l1 = acc.l2 = 0.0;
 #pragma unroll

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/vup.h"
 
 namespace vup {
@@ -104,13 +106,47 @@ __device__ __forceinline__ double cell_centre(double lo, double hi, int n, int j
   return lo + (j + 0.5) * ((hi - lo) / n);
 }
 
-// per-axis Gaussian factor exp(-t^2/2), t = (x_j - mu)/sigma, rounded to
-// FP32. The argument is formed in FP64 and split into an FP32 head and tail,
+// The per-axis Gaussian factors exp(-t^2/2), t = (x_j - mu)/sigma, of a pdf
+// much narrower than a cell would fall below FP32's range: its window is the
+// one cell holding the mean, whose centre can lie up to half a cell, i.e. many
+// sigma, away. Such an axis's factors are scaled by 2^m, m = floor(t*^2/2
+// log2 e) with t* the t of the window's cell nearest the mean, so its largest
+// factor lies in (1/2, 1]; the scale cancels from every normalised result, and
+// the reported normalisers are scaled back exactly (ldexp). Only axes whose
+// largest factor would be below 2^-kScaleMinExp (t* above about 5.3) are
+// scaled, m = 0 otherwise: every pdf the grid resolves (sigma above a tenth of
+// a cell) keeps its unscaled factors and its densities' roundings (BF16 and
+// E4M3 included), while the products over four axes of unscaled factors stay
+// above 2^-80, where the fixed-point scales (2^32 over the mass) fit FP32. m
+// is capped at kMaxScaleExp, beyond which the density is below FP64's range.
+constexpr int kScaleMinExp = 20;
+constexpr int kMaxScaleExp = 1100;
+
+// m for window cells jlo .. jhi of n over [lo, hi], t formed as the factors
+// form it
+__device__ __forceinline__ int axis_scale_exp(double lo, double hi, int n, int jlo, int jhi,
+                                              double mu, double rsig) {
+  const double h = (hi - lo) / n;
+  double c = floor((mu - lo) / h);
+  c = c >= (double)jlo ? c : (double)jlo;  // (a NaN goes to jlo)
+  c = c <= (double)jhi ? c : (double)jhi;
+  const double t = (cell_centre(lo, hi, n, (int)c) - mu) * rsig;
+  const double e = floor(0.5 * (t * t) * 1.4426950408889634);  // t*^2 / 2 / ln 2
+  if (!(e >= (double)kScaleMinExp)) return 0;
+  return e < (double)kMaxScaleExp ? (int)e : kMaxScaleExp;  // (t = inf: the cap)
+}
+
+// per-axis Gaussian factor 2^m exp(-t^2/2), t = (x_j - mu)/sigma, rounded to
+// FP32 (S: the scaled form; the loops that fill factor tables run the
+// unscaled one, S = false, whenever m = 0, so the common case costs nothing).
+// The argument is formed in FP64 and split into an FP32 head and tail,
 // exp(a) = exp(a_hi) (1 + a_lo), which keeps the result within about one FP32
 // ulp without the register cost of an FP64 exponential.
-__device__ __forceinline__ float gauss_factor(double x, double mu, double sigma) {
+template <bool S = true>
+__device__ __forceinline__ float gauss_factor(double x, double mu, double sigma, int m) {
   const double t = (x - mu) / sigma;
-  const double arg = -0.5 * (t * t);
+  double arg = -0.5 * (t * t);
+  if constexpr (S) arg += (double)m * 0.6931471805599453;
   const float hi = (float)arg;
   const float lo = (float)(arg - (double)hi);
   return expf(hi) * (1.0f + lo);
@@ -118,12 +154,25 @@ __device__ __forceinline__ float gauss_factor(double x, double mu, double sigma)
 
 // the same with t = (x - mu) * rsig, rsig = 1/sigma computed once per axis
 // (t then differs from the quotient by at most an FP64 ulp or so)
-__device__ __forceinline__ float gauss_factor_r(double x, double mu, double rsig) {
+template <bool S = true>
+__device__ __forceinline__ float gauss_factor_r(double x, double mu, double rsig, int m) {
   const double t = (x - mu) * rsig;
-  const double arg = -0.5 * (t * t);
+  double arg = -0.5 * (t * t);
+  if constexpr (S) arg += (double)m * 0.6931471805599453;
   const float hi = (float)arg;
   const float lo = (float)(arg - (double)hi);
   return expf(hi) * (1.0f + lo);
+}
+
+// run body(std::false_type) when m = 0 (the factors unscaled: the code of a
+// pdf the grid resolves), else body(std::true_type); m is uniform, so this is
+// one scalar branch around two versions of a table-filling loop
+template <typename F>
+__device__ __forceinline__ void with_scale(int m, F&& body) {
+  if (m == 0)
+    body(std::false_type{});
+  else
+    body(std::true_type{});
 }
 
 // ---------------------------------------------------------------------------

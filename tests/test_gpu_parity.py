@@ -542,6 +542,76 @@ def test_moments_tiled_edge_cases(vup, orc):
 
 
 # ---------------------------------------------------------------------------
+# pdfs far narrower than a cell (truncation windows of one cell whose centre
+# lies 14 to 36 sigma from the mean): each such axis's factor is below FP32's
+# range, so the kernels scale every axis's factors to a largest of 1 and put
+# the scale back into the reported normalisers in FP64
+# ---------------------------------------------------------------------------
+NARROW_2D = ("narrow2", (40, 30), (-3.0, -3.0), (3.0, 3.0), "sincos2", 24, 90, 301,
+             [(0,), (1,), (0, 1)])
+NARROW_3D = ("narrow3", (19, 23, 17), (-2.0, -1.0, 0.0), (2.0, 1.5, 2.0), "damped3", 29, 60, 302,
+             [(2,), (0,), (0, 2), (0, 1, 2)])
+
+
+def _narrow(case):
+    name, n, lo, hi, model, B, K, seed, sets = case
+    return workloads.narrow_workload(name, n, lo, hi, model, B, K, seed, sets)
+
+
+@pytest.mark.parametrize("case", [NARROW_2D, NARROW_3D], ids=["2d", "3d"])
+def test_narrow_pdfs_propagate(vup, orc, case):
+    """Both sweep forms against the oracle: P within the FP32 bar, Z (the mass
+    of the truncated densities, down to 1e-266 here) within rtol 2e-6."""
+    wl = _narrow(case)
+    _say(f"[narrow pdfs propagate] {wl.name} n={wl.n} K={wl.K}")
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    e = orc.uniform_edges(f, wl.B)
+    Po, Zo = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(f, e), wl.B, wl.mu, wl.sigma)
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    mm = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(e).to(DEV))
+    for mode in ("cells", "runs"):
+        mm.set_sweep_mode(mode)
+        P, Z = vup.propagate(mm, wl.mu, wl.sigma)
+        _check_P(_cpu(P), Po, 2e-5, f"{wl.name} {mode} form")
+        zg = _cpu(Z)[:, 0]
+        _say(f"  Z: max rel err {np.max(np.abs(zg - Zo[:, 0]) / Zo[:, 0]):.2e}, "
+             f"min Z {Zo[:, 0].min():.1e}")
+        assert np.allclose(zg, Zo[:, 0], rtol=2e-6, atol=0)
+    mm.set_sweep_mode("auto")
+
+
+@pytest.mark.parametrize("case", [NARROW_2D, NARROW_3D], ids=["2d", "3d"])
+def test_narrow_pdfs_moments(vup, orc, case):
+    """Exact-f moments of the narrow pdfs against the oracle: the per-pdf
+    kernel (2-D and 3-D) and the tiled form (2-D)."""
+    wl = _narrow(case)
+    _say(f"[narrow pdfs moments] {wl.name} n={wl.n} K={wl.K}")
+    forms = (True, False) if wl.ndim == 2 else (False,)
+    for tiled in forms:
+        _moments_vs_oracle(vup, orc, wl, tiled, label="narrow pdfs")
+
+
+def test_narrow_family_banded(vup, orc):
+    """The banded form with locations whose x deviation is far below a cell:
+    P and Z against the oracle (the columns of A_x are scaled to a largest
+    factor of 1; k_sep_z puts the scale back into Z)."""
+    n, lo, hi = (48, 40), (-3.0, -3.0), (3.0, 3.0)
+    hx = 6.0 / 48
+    centres = workloads.subgrid_midpoints(-3.0, 3.0, 48)
+    rng = np.random.Generator(np.random.PCG64(303))
+    idx = rng.choice(np.arange(2, 46), size=16, replace=False)
+    u = rng.uniform(0.1, 0.45, 16) * np.where(rng.uniform(size=16) < 0.5, -1.0, 1.0)
+    mux = centres[idx] + u * hx
+    sgx = np.abs(u) * hx / rng.uniform(14.0, 36.0, 16)  # the cell centre 14 .. 36 sigma away
+    muy = workloads.subgrid_midpoints(-2.5, 2.5, 16)
+    sgy = np.full(16, 0.3)
+    Pg, Zg, Po, Zo, mm, mu, sg = _sep_case(vup, orc, n, lo, hi, "sincos2", 32, mux, muy, sgx, sgy,
+                                           "narrow x deviations")
+    _check_P(Pg, Po, 2e-5, "P separable (narrow) vs oracle")
+    assert np.allclose(Zg, Zo, rtol=2e-6, atol=0)
+
+
+# ---------------------------------------------------------------------------
 # eq. (IPSAvar): the local expected squared deviation of vup_moments
 # ---------------------------------------------------------------------------
 def _check_delta2(vup, orc, wl):

@@ -110,6 +110,15 @@ def test_posterior_3d_and_mixtures(vup, orc):
     _run(vup, orc, wl4, [3, 11, 19], "4-D mixtures")
 
 
+def test_posterior_narrow_pdfs(vup, orc):
+    """Pdfs far narrower than a cell along some axes (their factors below
+    FP32's range): the posterior scales each axis's factors to a largest of
+    1 and divides by the normaliser scaled alike."""
+    wl = workloads.narrow_workload("inv_narrow", (19, 23, 17), (-2.0, -1.0, 0.0), (2.0, 1.5, 2.0),
+                                   "damped3", 29, 24, 304, [(2,), (0, 2), (0, 1, 2)])
+    _run(vup, orc, wl, [0, 1, 2, 5, 13], "3-D narrow pdfs")
+
+
 def test_posterior_edge_cases(vup, orc):
     n, lo, hi = (30, 26), (-3.0, -3.0), (3.0, 3.0)
     mu = np.array([[[0.3, -0.2]], [[9.0, 0.0]], [[0.0, 0.0]], [[2.9, 2.9]]])

@@ -180,6 +180,41 @@ def random_workload(name: str, n, lo, hi, model: str, B: int, K: int, C: int,
                     None if weight is None else np.ascontiguousarray(weight))
 
 
+def narrow_workload(name: str, n, lo, hi, model: str, B: int, K: int, seed: int,
+                    narrow_sets) -> Workload:
+    """Pdfs far narrower than a cell along some axes. Distribution k is narrow
+    along the axes of ``narrow_sets[k % len(narrow_sets)]``: there sigma is
+    1/200 to 1/80 of a cell and the mean sits 0.1 to 0.45 cells from the
+    centre of a cell, so its truncation window is the one cell holding the
+    mean, whose centre is t* = 14 .. tmax sigma away (tmax 36, 25, 20 for one,
+    two, three narrow axes: each such factor, e^(-t*^2/2), lies below FP32's
+    range and the product of all of them inside FP64's). The other axes take
+    sigma ~ U[0.05, 0.5] and a mean at least 0.5 inside the domain."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = len(n)
+    h = [(hi[i] - lo[i]) / n[i] for i in range(d)]
+    mu = np.empty((K, 1, d))
+    sigma = np.empty((K, 1, d))
+    for k in range(K):
+        narrow = narrow_sets[k % len(narrow_sets)]
+        tmax = {1: 36.0, 2: 25.0}.get(len(narrow), 20.0)
+        for ax in range(d):
+            if ax in narrow:
+                while True:
+                    c = int(rng.integers(1, n[ax] - 1))
+                    u = rng.uniform(0.1, 0.45) * (1.0 if rng.uniform() < 0.5 else -1.0)
+                    v = rng.uniform(1.0 / 200.0, 1.0 / 80.0)
+                    if 14.0 <= abs(u) / v <= tmax:
+                        break
+                mu[k, 0, ax] = lo[ax] + (c + 0.5 + u) * h[ax]
+                sigma[k, 0, ax] = v * h[ax]
+            else:
+                mu[k, 0, ax] = rng.uniform(lo[ax] + 0.5, hi[ax] - 0.5)
+                sigma[k, 0, ax] = rng.uniform(0.05, 0.5)
+    return Workload(name, d, tuple(int(x) for x in n), tuple(float(x) for x in lo),
+                    tuple(float(x) for x in hi), model, (), B, mu, sigma, None)
+
+
 IPSA_EXAMPLE_SIGMAS = (0.05, 0.25, 0.5, 1.0, 3.0)
 
 
