@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_axis_factors(SepArgs a) {
   for (int i = threadIdx.x; i < rowsw; i += 256) {
     float v = 0.0f;
     if (ok && i < n && i >= jlo && i <= jhi)
-      v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg, me);
+      v = gauss_factor(cell_centre(a.lo[d], a.hi[d], n, i), mu, sg, scale_log(me));
     if (i < rows) {
       col[(long long)i * ld] = v;
       zp += (double)v;

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
       const int wlo = swin[c][D - 1][0], whi = swin[c][D - 1][1];
       for (int col = wlo + (int)threadIdx.x; col <= whi; col += blockDim.x)
         gtab[c * nL + col] = gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
-                                            smu[c][D - 1], srs[c][D - 1], sm[c][D - 1]);
+                                            smu[c][D - 1], srs[c][D - 1],
+                                            scale_log(sm[c][D - 1]));
     }
   }
   __syncthreads();
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
         for (int d = 0; d + 1 < D; ++d) {
           in = in && j[d] >= swin[c][d][0] && j[d] <= swin[c][d][1];
           if (in) f *= gauss_factor_r(cell_centre(a.lo[d], a.hi[d], a.n[d], j[d]), smu[c][d],
-                                      srs[c][d], sm[c][d]);
+                                      srs[c][d], scale_log(sm[c][d]));
         }
         if (in && swin[c][D - 1][1] >= swin[c][D - 1][0]) {
           ri.rf[c] = f;
@@ -168,7 +169,8 @@ __global__ __launch_bounds__(256) void k_posterior(PostArgs a) {
         if (c < C && col >= ri.clo[c] && col <= ri.chi[c]) {
           const float g = a.gtab ? gtab[c * nL + col]
                                  : gauss_factor_r(cell_centre(a.lo[D - 1], a.hi[D - 1], nL, col),
-                                                  smu[c][D - 1], srs[c][D - 1], sm[c][D - 1]);
+                                                  smu[c][D - 1], srs[c][D - 1],
+                                                  scale_log(sm[c][D - 1]));
           v = fmaf(ri.rf[c] * g, sfb[c * B + b], v);
         }
       }

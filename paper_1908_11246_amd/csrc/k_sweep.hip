@@ -77,8 +77,6 @@ __device__ __forceinline__ T pick4(const T (&v)[4], int i) {
 struct Win {
   int lo[4];
   int W[4];
-  const int* m;  // LDS: the factors' scale exponents per axis (axis_scale_exp)
-  bool scaled;   // some m is not 0
   long long R;  // rows
   bool bad;
   bool empty;
@@ -113,8 +111,6 @@ __device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* w
   Win w;
   w.R = 1;
   const int flags = __builtin_amdgcn_readfirstlane(wsh[8] | wsh[9] | wsh[10] | wsh[11]);
-  w.m = wsh + 12;
-  w.scaled = __builtin_amdgcn_readfirstlane(wsh[12] | wsh[13] | wsh[14] | wsh[15]) != 0;
   w.bad = (flags & 1) != 0;
   w.empty = (flags & 2) != 0;
 #pragma unroll
@@ -126,10 +122,11 @@ __device__ __forceinline__ Win make_win(const SweepArgs& a, long long kc, int* w
   return w;
 }
 
-// scale exponent of axis d (0 unless the window has a scaled axis: one LDS
-// read, uniform, in that rare case only)
-__device__ __forceinline__ int win_m(const Win& w, int d) {
-  return w.scaled ? __builtin_amdgcn_readfirstlane(w.m[d]) : 0;
+// scale exponent of axis d of the current window (make_win leaves it in LDS
+// after the window ints; one uniform LDS read where a table needs it)
+__device__ __forceinline__ int win_m(const SweepArgs& a, const float* smem, int d) {
+  return __builtin_amdgcn_readfirstlane(
+      reinterpret_cast<const int*>(smem + a.L.red_off + 80)[12 + d]);
 }
 
 // fastest-axis window bounds (avoids dynamic indexing of the Win arrays)
@@ -182,13 +179,11 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
     if (d + 1 < D) {
       float* tab = smem + a.L.tab_off[d];
       const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-      const int m = win_m(w, d);
-      with_scale(m, [&](auto S) {
-        for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
-          const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
-          tab[i] = gauss_factor_r<S.value>(x, mu, rsig, m);
-        }
-      });
+      const double off = scale_log(win_m(a, smem, d));
+      for (int i = threadIdx.x; i < w.W[d]; i += kThreads) {
+        const double x = cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i);
+        tab[i] = gauss_factor_r(x, mu, rsig, off);
+      }
     }
   }
   const int L = D - 1;
@@ -196,18 +191,16 @@ __device__ __forceinline__ void build_tables(const SweepArgs& a, float* smem, co
   last_axis(w, D, loL, WL);
   float* tab = smem + pick4(a.L.tab_off, L);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
-  const int m = win_m(w, L);
-  with_scale(m, [&](auto S) {
-    for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
-      const int j = colbase + jj;
-      float v = 0.0f;
-      if (j >= loL && j < loL + WL) {
-        const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j);
-        v = gauss_factor_r<S.value>(x, mu, rsig, m);
-      }
-      tab[jj] = v;
+  const double off = scale_log(win_m(a, smem, L));
+  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+    const int j = colbase + jj;
+    float v = 0.0f;
+    if (j >= loL && j < loL + WL) {
+      const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j);
+      v = gauss_factor_r(x, mu, rsig, off);
     }
-  });
+    tab[jj] = v;
+  }
 }
 
 // Row table for rows [r0, r0 + rc): row factor (product of the slower axes'
@@ -367,13 +360,12 @@ __device__ __forceinline__ double exp_nonpos(double a) {
   return ldexp(p, (int)n);
 }
 
-// scaled by 2^m as gauss_factor_r (axis_scale_exp keeps the argument <= 0)
-template <bool S>
-__device__ __forceinline__ float gauss_factor_exact(double x, double mu, double rsig, int m) {
+// scaled by 2^m as gauss_factor_r, off = scale_log(m) (axis_scale_exp keeps
+// the argument <= 0)
+__device__ __forceinline__ float gauss_factor_exact(double x, double mu, double rsig,
+                                                    double off) {
   const double t = (x - mu) * rsig;
-  double arg = -0.5 * (t * t);
-  if constexpr (S) arg += (double)m * 0.6931471805599453;
-  return (float)exp_nonpos(arg);
+  return (float)exp_nonpos(fma(-0.5, t * t, off));
 }
 
 __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* smem, const Win& w,
@@ -384,12 +376,10 @@ __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* sm
     if (d + 1 < D) {
       float* tab = smem + a.L.tab_off[d];
       const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-      const int m = win_m(w, d);
-      with_scale(m, [&](auto S) {
-        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-          tab[i] = gauss_factor_exact<S.value>(
-              cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
-      });
+      const double off = scale_log(win_m(a, smem, d));
+      for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+        tab[i] = gauss_factor_exact(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                    rsig, off);
     }
   }
   const int L = D - 1;
@@ -397,26 +387,23 @@ __device__ __forceinline__ void build_tables_exact(const SweepArgs& a, float* sm
   last_axis(w, D, loL, WL);
   float* tab = smem + pick4(a.L.tab_off, L);
   const double mu = a.d.mu[kc * D + L], rsig = 1.0 / a.d.sigma[kc * D + L];
-  const int m = win_m(w, L);
-  with_scale(m, [&](auto S) {
-    for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
-      const int j = colbase + jj;
-      float v = 0.0f;
-      if (j >= loL && j < loL + WL)
-        v = gauss_factor_exact<S.value>(
-            cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j), mu, rsig, m);
-      tab[jj] = v;
-    }
-  });
+  const double off = scale_log(win_m(a, smem, L));
+  for (int jj = threadIdx.x; jj < ns * sw; jj += kThreads) {
+    const int j = colbase + jj;
+    float v = 0.0f;
+    if (j >= loL && j < loL + WL)
+      v = gauss_factor_exact(cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), pick4(a.g.n, L), j),
+                             mu, rsig, off);
+    tab[jj] = v;
+  }
 }
 
 // sum over the axes of component kc of their scale exponents m
 // (axis_scale_exp): the factor tables' products, and the masses summed from
 // them, are 2^sum times the densities'
-__device__ __forceinline__ int win_scale_exp(const SweepArgs& a, const Win& w) {
-  if (!w.scaled) return 0;
+__device__ __forceinline__ int win_scale_exp(const SweepArgs& a, const float* smem) {
   int s = 0;
-  for (int d = 0; d < a.g.ndim; ++d) s += w.m[d];
+  for (int d = 0; d < a.g.ndim; ++d) s += win_m(a, smem, d);
   return s;
 }
 
@@ -520,7 +507,7 @@ __device__ __forceinline__ void prop_scales(const SweepArgs& a, float* smem, con
     ps->unscale[t] = sc > 0.0 ? 1.0 / sc : 0.0;
     ps->scalef[t] = (float)sc;
   }
-  if (t == 0) ps->mexp = win_scale_exp(a, w);
+  if (t == 0) ps->mexp = win_scale_exp(a, smem);
   __syncthreads();
 }
 
@@ -894,7 +881,7 @@ constexpr int kBwdRowChunk = 256;
 // for every column c = 0 .. n (0 up to loL, the window total from hiL + 1 on).
 // Thread t sums a contiguous slice of the window; slice totals are scanned.
 __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* smem, long long kc,
-                                                  int loL, int WL, int m, double* red) {
+                                                  int loL, int WL, double off, double* red) {
   const int D = a.g.ndim;
   const int L = D - 1;
   const int nL = pick4(a.g.n, L);
@@ -905,14 +892,12 @@ __device__ __forceinline__ void build_prefix_runs(const SweepArgs& a, float* sme
   const int j1 = min(j0 + per, WL);
   double* Gw = G + loL;  // Gw[j + 1] = sum over window columns loL .. loL + j
   double sum = 0.0;
-  with_scale(m, [&](auto S) {
-    for (int j = j0; j < j1; ++j) {
-      const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), nL, loL + j);
-      const double g = (double)gauss_factor_r<S.value>(x, mu, rsig, m);
-      Gw[j + 1] = g;
-      sum += g;
-    }
-  });
+  for (int j = j0; j < j1; ++j) {
+    const double x = cell_centre(pick4(a.g.lo, L), pick4(a.g.hi, L), nL, loL + j);
+    const double g = (double)gauss_factor_r(x, mu, rsig, off);
+    Gw[j + 1] = g;
+    sum += g;
+  }
   // inclusive scan of the slice sums within the wave, then across waves
   const int lane = threadIdx.x & 63;
   const double incl = wave_scan(sum);
@@ -1072,16 +1057,14 @@ __global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
       if (d + 1 < D) {
         float* tab = smem + a.L.tab_off[d];
         const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-        const int m = win_m(w, d);
-        with_scale(m, [&](auto S) {
-          for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-            tab[i] = gauss_factor_r<S.value>(
-                cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
-        });
+        const double off = scale_log(win_m(a, smem, d));
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                  rsig, off);
       }
     }
     for (int i = threadIdx.x; i < 3 * a.L.hist_stride; i += kThreads) smem[a.L.hist_off + i] = 0.0f;
-    build_prefix_runs(a, smem, kc, loL, WL, win_m(w, D - 1), red);
+    build_prefix_runs(a, smem, kc, loL, WL, scale_log(win_m(a, smem, D - 1)), red);
     const double Zrows = row_mass(a, smem, w, red);
     if (threadIdx.x == 0) {
       const double colmass = reinterpret_cast<const double*>(smem + a.L.g_off)[loL + WL];
@@ -1093,7 +1076,7 @@ __global__ __launch_bounds__(kThreads, 7) void k_propagate_runs(SweepArgs a) {
         ps->srow[r] = K / (prec_qfac<VUP_FP32>() * rowbound[r] * colmass);
         ps->unscale[r] = 1.0 / ps->srow[r];
       }
-      ps->mexp = win_scale_exp(a, w);
+      ps->mexp = win_scale_exp(a, smem);
     }
     for (long long r0 = 0; r0 < w.R; r0 += RR) {
       const int rc = (int)((w.R - r0) < RR ? (w.R - r0) : RR);
@@ -1571,7 +1554,7 @@ __device__ __forceinline__ f32x4v lds_load_f4(uint32_t byte_addr) {
 // G3[c] = (G0, G1, G2, -) for c = 0 .. n (sums over the window columns below
 // c); the FP64 window totals go to tot[0..2].
 __device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem, long long kc,
-                                                 int loL, int WL, int m, double* red,
+                                                 int loL, int WL, double off, double* red,
                                                  double* tot) {
   const int D = a.g.ndim;
   const int L = D - 1;
@@ -1583,17 +1566,15 @@ __device__ __forceinline__ void build_prefix_bwd(const SweepArgs& a, float* smem
   const int j0 = min((int)threadIdx.x * per, WL);
   const int j1 = min(j0 + per, WL);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  with_scale(m, [&](auto S) {
-    for (int j = j0; j < j1; ++j) {
-      const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
-      const float gf = gauss_factor_r<S.value>(cell_centre(lo, hi, nL, loL + j), mu, rsig, m);
-      const double g = (double)gf;
-      s0 += g;
-      s1 += g * t;
-      s2 += g * t * t;
-      G3[loL + j + 1].w = gf;  // the factor, until the sums overwrite the entry
-    }
-  });
+  for (int j = j0; j < j1; ++j) {
+    const double t = (cell_centre(lo, hi, nL, loL + j) - mu) * rsig;
+    const float gf = gauss_factor_r(cell_centre(lo, hi, nL, loL + j), mu, rsig, off);
+    const double g = (double)gf;
+    s0 += g;
+    s1 += g * t;
+    s2 += g * t * t;
+    G3[loL + j + 1].w = gf;  // the factor, until the sums overwrite the entry
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double i0 = wave_scan(s0), i1 = wave_scan(s1), i2 = wave_scan(s2);
   if (lane == 63) {
@@ -1787,15 +1768,13 @@ __global__ __launch_bounds__(kThreads, NO <= 1 ? 5 : 1) void k_backward_runs(Swe
       if (d + 1 < D) {
         float* tab = smem + a.L.tab_off[d];
         const double mu = a.d.mu[kc * D + d], rsig = 1.0 / a.d.sigma[kc * D + d];
-        const int m = win_m(w, d);
-        with_scale(m, [&](auto S) {
-          for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
-            tab[i] = gauss_factor_r<S.value>(
-                cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu, rsig, m);
-        });
+        const double off = scale_log(win_m(a, smem, d));
+        for (int i = threadIdx.x; i < w.W[d]; i += kThreads)
+          tab[i] = gauss_factor_r(cell_centre(a.g.lo[d], a.g.hi[d], a.g.n[d], w.lo[d] + i), mu,
+                                  rsig, off);
       }
     }
-    build_prefix_bwd(a, smem, kc, loL, WL, win_m(w, D - 1), red, tot);
+    build_prefix_bwd(a, smem, kc, loL, WL, scale_log(win_m(a, smem, D - 1)), red, tot);
     BwdAcc<NO> acc;
     acc.a0 = acc.l1 = acc.l2 = 0.0;
 #pragma unroll

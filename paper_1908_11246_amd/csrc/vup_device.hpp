@@ -6,8 +6,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "../../include/vup.h"
 
 namespace vup {
@@ -123,9 +121,10 @@ constexpr int kScaleMinExp = 20;
 constexpr int kMaxScaleExp = 1100;
 
 // m for window cells jlo .. jhi of n over [lo, hi], t formed as the factors
-// form it
-__device__ __forceinline__ int axis_scale_exp(double lo, double hi, int n, int jlo, int jhi,
-                                              double mu, double rsig) {
+// form it. Out of line: it runs for few windows, and inlined its FP64 code
+// raised the scalar-register pressure of the sweep kernels' set-up
+__device__ __noinline__ int axis_scale_exp(double lo, double hi, int n, int jlo, int jhi,
+                                           double mu, double rsig) {
   const double h = (hi - lo) / n;
   double c = floor((mu - lo) / h);
   c = c >= (double)jlo ? c : (double)jlo;  // (a NaN goes to jlo)
@@ -136,17 +135,18 @@ __device__ __forceinline__ int axis_scale_exp(double lo, double hi, int n, int j
   return e < (double)kMaxScaleExp ? (int)e : kMaxScaleExp;  // (t = inf: the cap)
 }
 
+// the natural log of an axis's scale 2^m, added to the factors' arguments
+__device__ __forceinline__ double scale_log(int m) { return (double)m * 0.6931471805599453; }
+
 // per-axis Gaussian factor 2^m exp(-t^2/2), t = (x_j - mu)/sigma, rounded to
-// FP32 (S: the scaled form; the loops that fill factor tables run the
-// unscaled one, S = false, whenever m = 0, so the common case costs nothing).
-// The argument is formed in FP64 and split into an FP32 head and tail,
+// FP32, with off = scale_log(m). The argument fma(-1/2, t^2, off) costs the
+// one FP64 operation that -t^2/2 alone does, and equals it for off = 0 (halving
+// is exact). It is formed in FP64 and split into an FP32 head and tail,
 // exp(a) = exp(a_hi) (1 + a_lo), which keeps the result within about one FP32
 // ulp without the register cost of an FP64 exponential.
-template <bool S = true>
-__device__ __forceinline__ float gauss_factor(double x, double mu, double sigma, int m) {
+__device__ __forceinline__ float gauss_factor(double x, double mu, double sigma, double off) {
   const double t = (x - mu) / sigma;
-  double arg = -0.5 * (t * t);
-  if constexpr (S) arg += (double)m * 0.6931471805599453;
+  const double arg = fma(-0.5, t * t, off);
   const float hi = (float)arg;
   const float lo = (float)(arg - (double)hi);
   return expf(hi) * (1.0f + lo);
@@ -154,25 +154,12 @@ __device__ __forceinline__ float gauss_factor(double x, double mu, double sigma,
 
 // the same with t = (x - mu) * rsig, rsig = 1/sigma computed once per axis
 // (t then differs from the quotient by at most an FP64 ulp or so)
-template <bool S = true>
-__device__ __forceinline__ float gauss_factor_r(double x, double mu, double rsig, int m) {
+__device__ __forceinline__ float gauss_factor_r(double x, double mu, double rsig, double off) {
   const double t = (x - mu) * rsig;
-  double arg = -0.5 * (t * t);
-  if constexpr (S) arg += (double)m * 0.6931471805599453;
+  const double arg = fma(-0.5, t * t, off);
   const float hi = (float)arg;
   const float lo = (float)(arg - (double)hi);
   return expf(hi) * (1.0f + lo);
-}
-
-// run body(std::false_type) when m = 0 (the factors unscaled: the code of a
-// pdf the grid resolves), else body(std::true_type); m is uniform, so this is
-// one scalar branch around two versions of a table-filling loop
-template <typename F>
-__device__ __forceinline__ void with_scale(int m, F&& body) {
-  if (m == 0)
-    body(std::false_type{});
-  else
-    body(std::true_type{});
 }
 
 // ---------------------------------------------------------------------------
