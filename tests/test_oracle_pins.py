@@ -680,3 +680,29 @@ def test_oracle_clean_under_address_and_ub_sanitizers():
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0 and "san_check ok" in r.stdout, r.stderr[-4000:]
 
+
+
+def test_narrow_workload_recipe(orc):
+    """The narrow-pdf inputs are what their tests assume: a one-cell window
+    along every narrow axis, its centre 14 .. t_max sigma from the mean (the
+    factor below FP32's range), and an oracle normaliser inside FP64's."""
+    import workloads
+    sets = [(0,), (1,), (0, 1)]
+    wl = workloads.narrow_workload("narrow2", (40, 30), (-3.0, -3.0), (3.0, 3.0), "sincos2", 24,
+                                   90, 301, sets)
+    win = orc.windows(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, 4.0)[0][:, 0]
+    h = [(wl.hi[d] - wl.lo[d]) / wl.n[d] for d in range(2)]
+    for k in range(wl.K):
+        narrow = sets[k % len(sets)]
+        tmax = 36.0 if len(narrow) == 1 else 25.0
+        for d in narrow:
+            assert win[k, d, 0] == win[k, d, 1]
+            c = wl.lo[d] + (win[k, d, 0] + 0.5) * h[d]
+            t = abs(c - wl.mu[k, 0, d]) / wl.sigma[k, 0, d]
+            assert 14.0 - 1e-9 <= t <= tmax + 1e-9
+            assert np.exp(-0.5 * t * t) < np.finfo(np.float32).tiny
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    P, Z = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(f, orc.uniform_edges(f, wl.B)), wl.B,
+                         wl.mu, wl.sigma)
+    assert (Z > 0).all() and np.isfinite(P).all()
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-12)
