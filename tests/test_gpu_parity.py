@@ -591,6 +591,42 @@ def test_narrow_pdfs_moments(vup, orc, case):
         _moments_vs_oracle(vup, orc, wl, tiled, label="narrow pdfs")
 
 
+def test_scaled_multicell_windows(vup, orc):
+    """n_sigma = 8 with means 5.5 to 7.5 sigma outside the grid along x: the
+    windows hold several cells along x, all 5.5 to 8 sigma from the mean, so
+    that axis is scaled (largest factor below 2^-20) while its factors still
+    differ from cell to cell. P (both forms), Z and the moments (per pdf and
+    tiled) against the oracle."""
+    n, lo, hi = (40, 30), (-3.0, -3.0), (3.0, 3.0)
+    K = 48
+    rng = np.random.Generator(np.random.PCG64(305))
+    mu = np.empty((K, 1, 2))
+    sg = np.empty((K, 1, 2))
+    sg[:, 0, 0] = rng.uniform(0.1, 0.3, K)
+    side = np.where(np.arange(K) % 2 == 0, -1.0, 1.0)
+    mu[:, 0, 0] = np.where(side < 0, lo[0], hi[0]) + side * rng.uniform(5.5, 7.5, K) * sg[:, 0, 0]
+    mu[:, 0, 1] = rng.uniform(-2.5, 2.5, K)
+    sg[:, 0, 1] = rng.uniform(0.05, 0.5, K)
+    wl = workloads.Workload("scaled8", 2, n, lo, hi, "sincos2", (), 24, mu, sg, None)
+    wl.n_sigma = 8.0
+    _say(f"[scaled multi-cell windows] n={n} K={K} n_sigma=8")
+    f = orc.eval_grid(wl.n, wl.lo, wl.hi, wl.model)
+    e = orc.uniform_edges(f, wl.B)
+    win = orc.windows(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, 8.0)[0][:, 0]
+    assert ((win[:, 0, 1] - win[:, 0, 0]) >= 1).sum() >= K // 2  # several cells along x
+    Po, Zo = orc.propagate(wl.n, wl.lo, wl.hi, orc.bins(f, e), wl.B, wl.mu, wl.sigma, None, 8.0)
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    mm = vup.build_model_matrix(g, torch.from_numpy(f).to(DEV), torch.from_numpy(e).to(DEV))
+    for mode in ("cells", "runs"):
+        mm.set_sweep_mode(mode)
+        P, Z = vup.propagate(mm, wl.mu, wl.sigma, None, "fp32", 8.0)
+        _check_P(_cpu(P), Po, 2e-5, f"scaled8 {mode} form")
+        assert np.allclose(_cpu(Z)[:, 0], Zo[:, 0], rtol=2e-6, atol=0)
+    mm.set_sweep_mode("auto")
+    for tiled in (True, False):
+        _moments_vs_oracle(vup, orc, wl, tiled, label="n_sigma 8, scaled x")
+
+
 def test_narrow_family_banded(vup, orc):
     """The banded form with locations whose x deviation is far below a cell:
     P and Z against the oracle (the columns of A_x are scaled to a largest
