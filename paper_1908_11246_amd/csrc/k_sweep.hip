@@ -1405,11 +1405,16 @@ __device__ __forceinline__ double build_vtable(const SweepArgs& a, float* vt, lo
 // Gradients of component kc from the normalised sweep sums: A0 = E[v],
 // l1, l2 = E[v t], E[v t^2] along the fastest axis, t1[d], t2[d] the same for
 // the slower axes, m1[d], m2[d] = E[t], E[t^2] per axis (covariances, since
-// the weight table is centred), scaled by the mixture weight pc.
-__device__ __forceinline__ void write_grads(const SweepArgs& a, long long kc, double pc,
-                                            double A0, double l1, double l2, const double* t1,
-                                            const double* t2, const double* m1,
-                                            const double* m2, double vref) {
+// the weight table is centred), scaled by the mixture weight pc. An axis
+// whose window is one cell has a constant t, so its covariances, and the
+// derivatives, are exactly 0 (the component's output does not depend on its
+// mean or deviation along that axis within the window): written as 0 rather
+// than as the rounding residue of two equal sums times t / sigma, which for a
+// pdf much narrower than a cell is large.
+__device__ __forceinline__ void write_grads(const SweepArgs& a, const Win& w, long long kc,
+                                            double pc, double A0, double l1, double l2,
+                                            const double* t1, const double* t2,
+                                            const double* m1, const double* m2, double vref) {
   if (threadIdx.x != 0) return;
   const int D = a.g.ndim;
   const int L = D - 1;
@@ -1419,8 +1424,9 @@ __device__ __forceinline__ void write_grads(const SweepArgs& a, long long kc, do
       const double sg = a.d.sigma[kc * D + d];
       const double s1 = (d == L) ? l1 : t1[d < 3 ? d : 0];
       const double s2 = (d == L) ? l2 : t2[d < 3 ? d : 0];
-      a.g_mu[kc * D + d] = pc * (s1 - m1[d] * A0) / sg;
-      a.g_sigma[kc * D + d] = pc * (s2 - m2[d] * A0) / sg;
+      const bool one = w.W[d] == 1;
+      a.g_mu[kc * D + d] = one ? 0.0 : pc * (s1 - m1[d] * A0) / sg;
+      a.g_sigma[kc * D + d] = one ? 0.0 : pc * (s2 - m2[d] * A0) / sg;
     }
   }
   if (a.g_weight) a.g_weight[kc] = A0 + vref;
@@ -1522,7 +1528,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(SweepArgs a) {
     t2[3] = 0.0;
     const double l1 = block_sum(acc.l1, red) / Z;
     const double l2 = block_sum(acc.l2, red) / Z;
-    write_grads(a, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
+    write_grads(a, w, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
   }
 }
 
@@ -1823,7 +1829,7 @@ __global__ __launch_bounds__(kThreads, NO <= 1 ? 5 : 1) void k_backward_runs(Swe
     t2[3] = 0.0;
     const double l1 = block_sum(acc.l1, red) / Z;
     const double l2 = block_sum(acc.l2, red) / Z;
-    write_grads(a, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
+    write_grads(a, w, kc, pc, A0, l1, l2, t1, t2, m1, m2, vref);
   }
 }
 

@@ -591,6 +591,22 @@ def test_narrow_pdfs_moments(vup, orc, case):
         _moments_vs_oracle(vup, orc, wl, tiled, label="narrow pdfs")
 
 
+@pytest.mark.parametrize("form", ["cells", "runs"])
+@pytest.mark.parametrize("case", [NARROW_2D, NARROW_3D], ids=["2d", "3d"])
+def test_narrow_pdfs_backward(vup, orc, case, form):
+    """The adjoint on pdfs far narrower than a cell against the oracle's FP64
+    analytic gradient: along a one-cell axis the derivatives are exactly 0
+    (the output does not depend on that axis's mean or deviation within the
+    window), the other axes' as for any pdf."""
+    wl = _narrow(case)
+    _say(f"[narrow pdfs backward {form}] {wl.name} n={wl.n} K={wl.K}")
+    gm, gs, _ = _grad_case(vup, orc, wl, np.arange(wl.K), 45, form=form)
+    win = orc.windows(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, wl.n_sigma)[0][:, 0]
+    one = (win[:, :, 1] == win[:, :, 0])
+    assert one.any() and np.all(_cpu(gm)[:, 0, :][one] == 0.0)
+    assert np.all(_cpu(gs)[:, 0, :][one] == 0.0)
+
+
 def test_scaled_multicell_windows(vup, orc):
     """n_sigma = 8 with means 5.5 to 7.5 sigma outside the grid along x: the
     windows hold several cells along x, all 5.5 to 8 sigma from the mean, so
