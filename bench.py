@@ -151,6 +151,28 @@ PRECISIONS = {"grid1024": ("fp32", "bf16", "bf16x2", "fp8e4m3"),
 
 CALIB_BYTES = 256 << 20
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+# LDS rates of the run loop's operations, per CU and clock, at the vendor
+# clock: integer atomic adds to random addresses (measured on this part with a
+# microbenchmark: 6.4 lanes per clock per CU) and the LDS bandwidth (128 bytes
+# per clock per CU)
+LDS_ATOMIC_PEAK = 6.4 * 256 * 2.4e9
+LDS_BYTES_PEAK = 128 * 256 * 2.4e9
+
+
+def runs_in_windows(runidx, rows, pitch, win):
+    """Runs of equal bin that the 2-D windows hold, summed over the windows:
+    per window row r, runidx[r][hi] - runidx[r][lo] + 1 (runidx: each cell's
+    run within its row, [rows][pitch]; win: [K][2][2] inclusive bounds, empty
+    windows (hi < lo) count 0), by prefix sums over the rows."""
+    ri = (np.asarray(runidx).astype(np.int64) & 0xFFFF).reshape(rows, pitch)
+    pre = np.zeros((rows + 1, pitch), dtype=np.int64)
+    np.cumsum(ri, axis=0, out=pre[1:])
+    r0, r1 = win[:, 0, 0].astype(np.int64), win[:, 0, 1].astype(np.int64)
+    c0, c1 = win[:, 1, 0].astype(np.int64), win[:, 1, 1].astype(np.int64)
+    ok = (r1 >= r0) & (c1 >= c0)
+    r0, r1, c0, c1 = (np.where(ok, v, 0) for v in (r0, r1, c0, c1))
+    cnt = (pre[r1 + 1, c1] - pre[r0, c1]) - (pre[r1 + 1, c0] - pre[r0, c0]) + (r1 - r0 + 1)
+    return int(np.where(ok, cnt, 0).sum())
 
 
 def _time_on(stream, fn, reps, batch=1):
@@ -706,6 +728,22 @@ def main():
                               "frac": ach / VALU_PEAK_OPS, "traffic": traffic_bytes("propagate"),
                               "kernel": KERNELS["propagate"], "kernel_ms": part_ms["propagate"],
                               "ops_per_update": OPS_PER_UPDATE["propagate"]}
+    if form == "runs" and len(wl.n) == 2:
+        # the run loop's own bound: per run of equal bin inside a window one
+        # random LDS atomic and two 8-byte prefix-sum reads
+        win = vup.windows(g, mu, sigma)[:, 0].cpu().numpy()
+        R = runs_in_windows(mm0.runidx.cpu().numpy(), int(mm0.mm.rows), int(mm0.mm.pitch), win)
+        rooflines["propagate"]["lds"] = {
+            "runs_per_launch": R,
+            "atomics_per_s": R / t, "atomic_peak_per_s": LDS_ATOMIC_PEAK,
+            "atomic_frac": R / t / LDS_ATOMIC_PEAK,
+            "read_bytes_per_s": 16 * R / t, "read_peak_bytes_per_s": LDS_BYTES_PEAK,
+            "read_frac": 16 * R / t / LDS_BYTES_PEAK,
+            "peaks": "random-address ds_add_u32 rate measured on this part (6.4 lanes/clk/CU) "
+                     "and LDS bandwidth (128 B/clk/CU), at 2.4 GHz"}
+        log(f"[bench] run loop: {R:.3e} runs, LDS atomics "
+            f"{rooflines['propagate']['lds']['atomic_frac']:.2f} and prefix-sum reads "
+            f"{rooflines['propagate']['lds']['read_frac']:.2f} of their peaks")
     # moments: the algorithmic flops of the two FP64-quality bilinear forms
     # over the whole moments call (its four kernels), against the dense FP64
     # matrix peak; beside it the int8 digit products executed, against the

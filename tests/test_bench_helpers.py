@@ -64,3 +64,29 @@ def test_traffic_summary_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     assert bench.traffic_bytes("propagate") is None
     (tmp_path / "paper_1908_11246_amd" / "csrc" / "vup_internal.hpp").write_text("// changed")
     assert bench.traffic_bytes("moments") is None
+
+
+def test_runs_in_windows_counts_bin_changes():
+    """The run count behind the bench's LDS rates: per window row, one run plus
+    one per change of bin inside the window, summed over rows and windows
+    (brute force from the bins), with empty windows counting 0."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    rows, n, pitch = 37, 53, 56
+    bins = np.cumsum(rng.integers(0, 2, size=(rows, n)), axis=1) // 2  # runs of 1-4 cells
+    runidx = np.zeros((rows, pitch), dtype=np.int16)
+    runidx[:, :n] = np.concatenate([np.zeros((rows, 1), np.int64),
+                                    np.cumsum(bins[:, 1:] != bins[:, :-1], axis=1)], axis=1)
+    win = np.zeros((40, 2, 2), dtype=np.int32)
+    for k in range(40):
+        r = np.sort(rng.integers(0, rows, 2))
+        c = np.sort(rng.integers(0, n, 2))
+        win[k] = [r, c]
+    win[3] = [[5, 4], [0, 10]]  # empty
+    brute = 0
+    for k in range(40):
+        (r0, r1), (c0, c1) = win[k]
+        for r in range(r0, r1 + 1):
+            if c1 >= c0:
+                brute += 1 + int((bins[r, c0 + 1:c1 + 1] != bins[r, c0:c1]).sum())
+    assert bench.runs_in_windows(runidx.reshape(-1), rows, pitch, win) == brute
