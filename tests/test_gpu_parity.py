@@ -591,6 +591,23 @@ def test_narrow_pdfs_moments(vup, orc, case):
         _moments_vs_oracle(vup, orc, wl, tiled, label="narrow pdfs")
 
 
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("case", [NARROW_2D, NARROW_3D], ids=["2d", "3d"])
+def test_narrow_pdfs_reduced_precision(vup, orc, case, precision):
+    """BF16 and split BF16 round each density. The narrow axes' factors are
+    scaled by powers of two, which BF16 rounding (FP32's exponent range, 8
+    significant bits) does not see, so P matches the same-precision oracle's
+    roundings of the unscaled densities within the usual bar."""
+    wl = _narrow(case)
+    _say(f"[narrow pdfs {precision}] {wl.name} n={wl.n} K={wl.K}")
+    o = orc.run_workload(wl, precision=precision, with_moments=False)
+    gp = _gpu_pipeline(vup, wl, precision, moments=False)
+    P64, _ = orc.propagate(wl.n, wl.lo, wl.hi, o["bin"], wl.B, wl.mu, wl.sigma, wl.weight)
+    F = orc.rounding_l1_bound(wl.n, wl.lo, wl.hi, wl.mu, wl.sigma, wl.weight, wl.n_sigma,
+                              precision, EPS_DENSITY)
+    _check_reduced(_cpu(gp["P"]), o["P"], P64, F, f"P {precision} narrow")
+
+
 @pytest.mark.parametrize("form", ["cells", "runs"])
 @pytest.mark.parametrize("case", [NARROW_2D, NARROW_3D], ids=["2d", "3d"])
 def test_narrow_pdfs_backward(vup, orc, case, form):
