@@ -464,7 +464,9 @@ int vup_marginalize_noalloc(int64_t K, int32_t n, const float* A, const double* 
  * after the model matrix it returns the input pdf (the footnote's identity:
  * sum_b post[i] P[k][b] [bin(i) = b] = p_k(x_i)), and over the cells of one
  * bin it sums to 1. p_k is the truncated, normalised mixture the propagation
- * uses (FP32 per-axis factors, normalised by Z in FP64).
+ * uses (FP32 per-axis factors, normalised by Z in FP64; the factors of an axis
+ * of a pdf far narrower than a cell are scaled by the same power of two as in
+ * vup_propagate, and the scale is divided out of Z exactly).
  * Optional per-bin posterior means E[x_d | y in b, k] = sum over the bin's
  * cells of post x_d (FP64, summed in the compressed-by-bin order).
  *   d: the distributions given to vup_propagate; sel: dev int64 [n_sel]
