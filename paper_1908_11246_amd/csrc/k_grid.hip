@@ -643,6 +643,18 @@ __global__ void k_set_mode(unsigned long long* counters, int mode) {
   if (threadIdx.x == 0) counters[kCntMode] = (unsigned long long)mode;
 }
 
+// zero the model matrix's counters (8 words) with a kernel rather than a
+// memset, so that a caller may capture vup_bin in a graph
+__global__ void k_clear_counters(unsigned long long* counters) {
+  if (threadIdx.x < 8) counters[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_clear_counters(void* counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, s,
+                     static_cast<unsigned long long*>(counters));
+  return hipGetLastError();
+}
+
 hipError_t launch_set_mode(const vup_mm& mm, int mode, hipStream_t s) {
   unsigned long long* c =
       reinterpret_cast<unsigned long long*>(static_cast<char*>(mm.ws) + mm.off_counters);

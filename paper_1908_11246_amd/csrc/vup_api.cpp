@@ -186,7 +186,7 @@ int vup_bin(const vup_grid* g, const double* f, const double* edges, int32_t B, 
   mm.reserved = 0;
   mm.magic = vup::kMagic;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemsetAsync(static_cast<char*>(ws) + L.off_counters, 0, 64, s);
+  hipError_t e = vup::launch_clear_counters(static_cast<char*>(ws) + L.off_counters, s);
   if (e != hipSuccess) return launched(e, "vup_bin (clear counters)");
   e = vup::launch_bin(mm, f, edges, bin, s);
   if (e != hipSuccess) return launched(e, "vup_bin");

@@ -65,6 +65,8 @@ hipError_t launch_backward(const vup_mm& mm, const vup_dists& d, const float* P,
                            double* g_mu, double* g_sigma, double* g_weight, hipStream_t s);
 
 hipError_t launch_set_mode(const vup_mm& mm, int mode, hipStream_t s);
+// zero the 64 bytes of counters at `counters` (device, 8-byte aligned)
+hipError_t launch_clear_counters(void* counters, hipStream_t s);
 // the run form of the FP32 propagation applies to this model matrix
 bool runs_allowed(const vup_mm& mm);
 size_t sep_workspace_bytes(const vup_grid& g, int B, int Mx, int My);
