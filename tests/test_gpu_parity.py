@@ -1110,3 +1110,53 @@ def test_model_copy_is_anchored(vup):
         c0 = c - c % 8
         want[:, c] = fh[:, c] if c == c0 else (fh[:, c] - fh[:, c0])
     assert np.array_equal(f32, want)
+
+
+def test_step_graph_capture(vup):
+    """The whole step (model evaluation, edges, model matrix with its sweep
+    form set explicitly, propagation, tiled moments, IPSA statistics) captured
+    in one HIP graph: nothing in these calls synchronises or records a memset,
+    and every replay, with eager steps and synchronisations between replays
+    and the outputs cleared before each, reproduces the eager results bit for
+    bit (all accumulation is in integers)."""
+    wl = workloads.grid64()
+    g = vup.make_grid(wl.n, wl.lo, wl.hi)
+    mu = torch.from_numpy(wl.mu).to(DEV)
+    sg = torch.from_numpy(wl.sigma).to(DEV)
+    f0 = vup.eval_grid(g, wl.model)
+    mm0 = vup.build_model_matrix(g, f0, vup.uniform_edges(f0, wl.B), want_bin=False)
+    form = mm0.sweep
+    ws = vup.moments_workspace(mm0, mu, sg)
+    assert ws is not None
+
+    def step():
+        f = vup.eval_grid(g, wl.model)
+        e = vup.uniform_edges(f, wl.B)
+        mm = vup.build_model_matrix(g, f, e, want_bin=False, resolve_sweep=False)
+        mm.set_sweep_mode(form)
+        P, _ = vup.propagate(mm, mu, sg, None, "fp32", want_Z=False)
+        mean, var, _ = vup.moments(mm, mu, sg, workspace=ws)
+        mh, vh, ent = vup.ipsa(mm, P)
+        return P, mean, var, mh, vh, ent
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for i in range(3):
+        eager = step()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(eager, ref))
+        for t in outs:
+            t.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        _say(f"  replay {i}: " + ", ".join(str(torch.equal(a, b)) for a, b in zip(outs, ref)))
+        assert all(torch.equal(a, b) for a, b in zip(outs, ref)), i
